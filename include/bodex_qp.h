@@ -1,0 +1,192 @@
+/*
+ * bodex_qp.h -- C ABI of the MI355X (gfx950) batched contact-force QP library.
+ *
+ * The library solves, for every grasp g and every desired wrench direction
+ * t_j of that grasp, the lower-level QP of BODex (arXiv 2412.16490,
+ * Sec. IV-A, Eq. 7-9):
+ *
+ *     Q_j = min_f || G f - beta t_j ||^2 + eps ||f||^2
+ *           s.t.  f_i inside the 8-facet pyramid that linearises the friction
+ *                 cone of Eq. 1 (Sec. IV-A, last paragraph), 0 <= f_i1 <= fmax,
+ *                 and sum_i f_i1 >= gamma (Eq. 9),
+ *
+ * where G = [G_1 .. G_m] is the grasp matrix of Eq. 2 built from contact
+ * points p_i and inward normals n_i (Sec. III), with the torque rows scaled by
+ * torque_scale.  It returns the optimal forces, Q_j, the grasp energy
+ * E_g = sum_j Q_j (Eq. 3 restricted to the QP terms), and the gradient of a
+ * weighted sum of E_g and Q_j with respect to p_i and n_i (Sec. IV-A: Q_j is
+ * differentiable because G_i is).
+ *
+ * Method: ADMM in the ReLU-QP style (Sec. IV-B) -- one Cholesky-factorised
+ * KKT matrix per grasp shared by all of its wrenches, an affine step plus a
+ * clamp per iteration, periodic residual checks with per-grasp step-size
+ * adaptation -- followed by an FP64 polish that re-solves the reduced KKT
+ * system on the identified active set and corrects that set with dual
+ * active-set steps, keeping the polished point only when its KKT conditions
+ * hold.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Return value: 0 on success or a negative BODEX_E* code.  No C++ exception
+ *    crosses this boundary.  bodex_qp_last_error() gives a message.
+ *  * Device arrays are caller-owned, contiguous, 4-byte aligned, on the
+ *    handle's device.  Host arrays (marked HOST) are read during the call only.
+ *  * Work is enqueued on the handle's HIP stream; calls return once enqueued.
+ *    Outputs are valid after the stream (or an event recorded on it) is
+ *    synchronised.  Host arrays may be reused as soon as the call returns.
+ *  * A handle is not thread-safe; use one handle per stream.  Handles are
+ *    independent of each other.
+ *  * Per-QP numerical trouble never fails a call: it is reported in status[].
+ */
+#ifndef BODEX_QP_H
+#define BODEX_QP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BODEX_MAX_CONTACTS 8  /* m_max upper limit                       */
+#define BODEX_MAX_WRENCHES 64 /* s_max upper limit (wrenches per grasp)   */
+
+/* Error codes. */
+#define BODEX_OK 0
+#define BODEX_EINVAL -1     /* invalid argument (bad size, null pointer, ...) */
+#define BODEX_EHIP -2       /* HIP runtime error; see bodex_qp_last_error     */
+#define BODEX_EBUDGET -3    /* request exceeds the handle's device budget     */
+#define BODEX_EINFEAS -4    /* gamma > m * fmax for some grasp: infeasible    */
+#define BODEX_EUNSUP -5     /* unsupported size (s > s_max, m > m_max)        */
+#define BODEX_ENODEV -6     /* no usable GPU device                           */
+
+/* Per-QP status bits (status[w]). */
+#define BODEX_ST_CONVERGED 0x01  /* final relative KKT residual <= tol_rel     */
+#define BODEX_ST_MAX_ITER 0x02   /* ADMM stopped at max_iters above tol_rel   */
+#define BODEX_ST_NONFINITE 0x04  /* non-finite input or iterate (QP isolated) */
+#define BODEX_ST_FP64_CHOL 0x08  /* the grasp's KKT factor needed FP64        */
+#define BODEX_ST_POLISH_REJ 0x10 /* polish ran but its point failed KKT       */
+#define BODEX_ST_POLISHED 0x20   /* returned point is the accepted polish     */
+
+/* Flags (bodex_qp_params.flags). */
+#define BODEX_F_WARM_START 0x01   /* start ADMM from the state passed in       */
+#define BODEX_F_POLISH 0x02       /* run the FP64 polish after ADMM            */
+#define BODEX_F_ADAPTIVE_RHO 0x04 /* per-grasp rho adaptation                  */
+#define BODEX_F_BATCHED 0x08      /* persistent cost-sorted launch (uneven m,s)*/
+#define BODEX_F_GRAPH 0x10        /* capture launches in a hipGraph and replay */
+                                  /* it while the batch shape is unchanged     */
+
+typedef struct {
+    int m_max;            /* contacts per grasp, 1..8 (array padding)        */
+    int s_max;            /* wrenches per grasp, 1..64                        */
+    float force_max;      /* fmax, upper bound of f_i1 (Eq. 1: 1.0)           */
+    float gamma;          /* lower bound of sum_i f_i1 (Eq. 9); 0 = unused    */
+    float beta;           /* desired-wrench magnitude (Eq. 7)                 */
+    float eps_reg;        /* regulariser eps on ||f||^2                       */
+    float torque_scale;   /* kappa: torque rows of G are kappa * (p x c)      */
+    float tol_rel;        /* stop when relative KKT residual <= tol_rel       */
+    int max_iters;        /* ADMM iteration cap                               */
+    float rho0;           /* initial ADMM step size                           */
+    float alpha;          /* over-relaxation, in (0, 2)                       */
+    int check_every;      /* residual check / rho update period (iterations)  */
+    float rho_min;        /* clamp of the adapted rho                         */
+    float rho_max;
+    float rho_hysteresis; /* refactor only when rho changes by this factor    */
+    float fp64_cond;      /* factor K in FP64 when cond estimate exceeds this */
+    int polish_steps;     /* cap on active-set corrections in the polish      */
+    int iters_per_chunk;  /* batched form: iterations between queue checks    */
+    unsigned flags;       /* BODEX_F_*                                        */
+} bodex_qp_params;
+
+/* One batch of grasps (CSR over wrenches). */
+typedef struct {
+    int n_grasps;              /* G >= 0                                      */
+    int n_qps;                 /* W = wrench_offset[G]                        */
+    const int *contact_count;  /* HOST [G], 1 <= m_g <= m_max                 */
+    const int *wrench_offset;  /* HOST [G+1], nondecreasing, s_g <= s_max     */
+    const float *points;       /* device [G][m_max][3]  p_i (object frame)    */
+    const float *normals;      /* device [G][m_max][3]  n_i (normalised inside)*/
+    const float *mu;           /* device [G][m_max]     friction, > 0         */
+    const float *wrench_dir;   /* device [W][6]         t_j (beta applied)    */
+} bodex_batch;
+
+/* ADMM state, structure-of-arrays so that consecutive QPs are consecutive in
+ * memory.  Rows of z, y per contact i: 8 pyramid facets (9i .. 9i+7), then
+ * the normal bound (9i+8); row 9*m_max is the gamma row.  Unused rows of
+ * grasps with fewer contacts hold zeros. */
+typedef struct {
+    float *x;   /* device [3 m_max][W]      forces in (normal, d, e) order    */
+    float *z;   /* device [9 m_max + 1][W]                                    */
+    float *y;   /* device [9 m_max + 1][W]  dual variables                    */
+    float *rho; /* device [G]               per-grasp ADMM step size          */
+} bodex_state;
+
+typedef struct {
+    float *forces;          /* device [W][3 m_max]  optimal f (zero padded)   */
+    float *qp_obj;          /* device [W]   Q_j = ||G f - beta t||^2+eps||f||^2 */
+    float *energy;          /* device [G]   E_g = sum_j Q_j                   */
+    float *kkt_rel;         /* device [W]   relative KKT residual of state    */
+    int *iters;             /* device [W]   ADMM iterations used              */
+    unsigned char *status;  /* device [W]   BODEX_ST_* bits                   */
+    bodex_state state;      /* optional in/out state; all-NULL pointers make  */
+                            /* the library use its own workspace              */
+} bodex_result;
+
+typedef struct bodex_qp bodex_qp_t;
+
+/* Fill *p with the defaults: m_max 5, s_max 32, fmax 1, gamma 0, beta 1,
+ * eps 1e-6, torque_scale 20, tol 1e-5, 500 iterations, rho0 0.1, alpha 1.6,
+ * check every 10, rho in [1e-4, 1e4], hysteresis 5, fp64_cond 1e4, 64 polish
+ * steps, 20 iterations per chunk, flags POLISH | ADAPTIVE_RHO. */
+void bodex_qp_default_params(bodex_qp_params *p);
+
+/* Create a handle on `device` that enqueues on `hip_stream` (a hipStream_t;
+ * NULL = the default stream).  hbm_budget_bytes caps the library-owned
+ * workspace (0 = 4 GiB).  Errors: EINVAL (bad params), ENODEV, EHIP. */
+int bodex_qp_create(const bodex_qp_params *p, int device, void *hip_stream,
+                    size_t hbm_budget_bytes, bodex_qp_t **out);
+
+/* Change the stream used by later calls (same device). */
+int bodex_qp_set_stream(bodex_qp_t *h, void *hip_stream);
+
+/* Forward solve of every QP in the batch.  With BODEX_F_WARM_START the ADMM
+ * starts from out->state (which must then be non-NULL and hold a previous
+ * state, e.g. from an earlier call on the same grasps); otherwise from zero.
+ * Errors: EINVAL (null pointers, bad sizes, mu <= 0 is reported per QP as
+ * non-finite), EUNSUP, EINFEAS, EBUDGET (workspace above budget), EHIP. */
+int bodex_qp_solve(bodex_qp_t *h, const bodex_batch *in, bodex_result *out);
+
+/* Gradient of L = sum_g dL_dE[g] E_g + sum_w dL_dQ[w] Q_w with respect to
+ * points and normals (Danskin's theorem: the feasible set does not depend on
+ * p or n, so dQ/dG = 2 (G f* - beta t) f*^T, chained through Eq. 2 and the
+ * tangent-basis construction).  f* is recomputed from `st` (the state a
+ * solve wrote for the same batch); ADMM iterates are never stored.
+ * dL_dE [G] and dL_dQ [W] are device arrays, either may be NULL.
+ * Outputs dL_dpoints, dL_dnormals: device [G][m_max][3]; overwritten, or
+ * added to when `accumulate` is non-zero.  The normal gradient has no radial
+ * component (normals are normalised inside).  Errors: EINVAL, EHIP. */
+int bodex_qp_backward(bodex_qp_t *h, const bodex_batch *in,
+                      const bodex_state *st, const float *dL_dE,
+                      const float *dL_dQ, float *dL_dpoints,
+                      float *dL_dnormals, int accumulate);
+
+/* Free library-owned memory and graphs.  Never frees caller arrays. */
+int bodex_qp_destroy(bodex_qp_t *h);
+
+/* Message of the last error on this handle (or of the last failed create when
+ * h is NULL).  Valid until the next call on the handle. */
+const char *bodex_qp_last_error(const bodex_qp_t *h);
+
+/* Device bytes of a caller-held state for a batch (x, z, y, rho). */
+size_t bodex_qp_state_bytes(int n_grasps, int n_qps, int m_max);
+
+/* Statistics of the last solve (host copies, filled after the stream is
+ * synchronised by this call): number of graph replays, refactorisations,
+ * launches.  Any pointer may be NULL.  Synchronises the handle's stream. */
+int bodex_qp_last_stats(bodex_qp_t *h, int *launches, int *graph_replays,
+                        int *tiles);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BODEX_QP_H */

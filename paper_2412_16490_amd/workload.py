@@ -1,0 +1,197 @@
+"""Seeded synthetic contact configurations shaped like the paper's workloads.
+
+This module only draws inputs; it holds none of the QP's arithmetic, so both the
+GPU library's tests and the CPU oracle can be fed from it.
+
+Shapes follow the paper's setting: 4-fingertip (Allegro/Leap) and 5-fingertip
+(Shadow) hands (Sec. V-A, V-C), objects rescaled to 0.06-0.12 m (Sec. V-A) and
+unit desired-wrench directions t_j (Sec. IV-A, Eq. 7).  The object meshes are
+stood in by spheres and axis-aligned ellipsoids centred at the origin, the
+object's centre of gravity (Sec. III).
+
+Array layout (all float32, C-contiguous, padded to ``m_max`` contacts):
+  points  [G, m_max, 3]   contact positions p_i (object frame, metres)
+  normals [G, m_max, 3]   inward surface normals n_i (unit)
+  mu      [G, m_max]      friction coefficients
+  wrench  [W, 6]          desired wrench directions t_j (unit in R^6)
+  counts  [G]   int32     contacts per grasp m_g
+  woff    [G+1] int32     CSR offsets of each grasp's wrenches (W = woff[G])
+Padding entries (contacts beyond m_g) hold p = 0, n = (0, 0, 1), mu = 0.5.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+#: Torque scale 1/L with L = 0.05 m (the scale the desired torques are quoted in).
+TORQUE_SCALE = 20.0
+
+
+@dataclasses.dataclass
+class Batch:
+    points: np.ndarray
+    normals: np.ndarray
+    mu: np.ndarray
+    wrench: np.ndarray
+    counts: np.ndarray
+    woff: np.ndarray
+    name: str = ""
+
+    @property
+    def n_grasps(self) -> int:
+        return int(self.counts.shape[0])
+
+    @property
+    def m_max(self) -> int:
+        return int(self.points.shape[1])
+
+    @property
+    def n_qps(self) -> int:
+        return int(self.woff[-1])
+
+    def subset(self, grasps) -> "Batch":
+        """A new batch holding the listed grasps (in that order)."""
+        grasps = np.asarray(grasps, dtype=np.int64)
+        s = self.woff[1:] - self.woff[:-1]
+        ws = [np.arange(self.woff[g], self.woff[g + 1]) for g in grasps]
+        widx = np.concatenate(ws) if ws else np.zeros(0, dtype=np.int64)
+        woff = np.zeros(len(grasps) + 1, dtype=np.int32)
+        woff[1:] = np.cumsum(s[grasps])
+        return Batch(self.points[grasps].copy(), self.normals[grasps].copy(),
+                     self.mu[grasps].copy(), self.wrench[widx].copy(),
+                     self.counts[grasps].copy(), woff, self.name + "[subset]")
+
+
+def unit_sphere(rng: np.random.Generator, shape) -> np.ndarray:
+    """Uniform directions on S^2 (normalised Gaussians)."""
+    v = rng.standard_normal(tuple(shape) + (3,))
+    return v / np.linalg.norm(v, axis=-1, keepdims=True)
+
+
+def wrench_dirs(rng: np.random.Generator, w: int) -> np.ndarray:
+    """Uniform unit desired-wrench directions on S^5."""
+    v = rng.standard_normal((w, 6))
+    return (v / np.linalg.norm(v, axis=-1, keepdims=True)).astype(np.float32)
+
+
+def sphere_contacts(rng, n_grasps, m, radius=0.05):
+    u = unit_sphere(rng, (n_grasps, m))
+    return (radius * u).astype(np.float32), (-u).astype(np.float32)
+
+
+def ellipsoid_contacts(rng, n_grasps, m, lo=0.02, hi=0.08):
+    """Points uniform-in-direction on axis-aligned ellipsoids with semi-axes
+    ~ U[lo, hi]; inward normals are the negated normalised gradient of
+    x^2/a^2 + y^2/b^2 + z^2/c^2."""
+    axes = rng.uniform(lo, hi, size=(n_grasps, 1, 3))
+    u = unit_sphere(rng, (n_grasps, m))
+    p = axes * u
+    g = p / axes ** 2
+    n = -g / np.linalg.norm(g, axis=-1, keepdims=True)
+    return p.astype(np.float32), n.astype(np.float32)
+
+
+def _pack(points_list, normals_list, mu_list, counts, s_list, wrench, m_max, name):
+    G = len(counts)
+    P = np.zeros((G, m_max, 3), np.float32)
+    N = np.zeros((G, m_max, 3), np.float32)
+    N[..., 2] = 1.0
+    MU = np.full((G, m_max), 0.5, np.float32)
+    for g in range(G):
+        m = counts[g]
+        P[g, :m] = points_list[g]
+        N[g, :m] = normals_list[g]
+        MU[g, :m] = mu_list[g]
+    woff = np.zeros(G + 1, np.int32)
+    woff[1:] = np.cumsum(np.asarray(s_list, np.int64))
+    return Batch(P, N, MU, wrench, np.asarray(counts, np.int32), woff, name)
+
+
+def uniform_batch(seed, n_grasps, m, s, geometry="ellipsoid", mu=None,
+                  mu_range=(0.3, 0.8), name=""):
+    """Every grasp has m contacts and s wrenches."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if geometry == "sphere":
+        p, n = sphere_contacts(rng, n_grasps, m)
+    else:
+        p, n = ellipsoid_contacts(rng, n_grasps, m)
+    if mu is None:
+        mug = rng.uniform(mu_range[0], mu_range[1], size=(n_grasps, 1))
+        muv = np.repeat(mug, m, axis=1).astype(np.float32)
+    else:
+        muv = np.full((n_grasps, m), mu, np.float32)
+    t = wrench_dirs(rng, n_grasps * s)
+    woff = (np.arange(n_grasps + 1, dtype=np.int64) * s).astype(np.int32)
+    return Batch(np.ascontiguousarray(p), np.ascontiguousarray(n),
+                 np.ascontiguousarray(muv), t,
+                 np.full(n_grasps, m, np.int32), woff, name)
+
+
+def mixed_batch(seed, n_grasps, m_choices=(4, 5), s_range=(6, 32),
+                mu_range=(0.3, 0.8), name=""):
+    """Equal split over m_choices (shuffled); s uniform integer in s_range
+    (inclusive) per grasp; ellipsoid geometry; mu per grasp."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k = len(m_choices)
+    counts = np.repeat(np.asarray(m_choices), -(-n_grasps // k))[:n_grasps]
+    rng.shuffle(counts)
+    m_max = int(max(m_choices))
+    p, n = ellipsoid_contacts(rng, n_grasps, m_max)
+    mug = rng.uniform(mu_range[0], mu_range[1], size=(n_grasps, 1))
+    s = rng.integers(s_range[0], s_range[1] + 1, size=n_grasps)
+    t = wrench_dirs(rng, int(s.sum()))
+    pl = [p[g, :counts[g]] for g in range(n_grasps)]
+    nl = [n[g, :counts[g]] for g in range(n_grasps)]
+    ml = [np.repeat(mug[g], counts[g]) for g in range(n_grasps)]
+    return _pack(pl, nl, ml, counts, s, t, m_max, name)
+
+
+# The five benchmark configurations.  ``scale`` shrinks the grasp count for
+# quick parity runs while keeping every per-grasp distribution unchanged.
+CONFIG_SEEDS = (16490, 16491, 16492, 16493, 16494)
+
+
+def config(idx: int, n_grasps: int | None = None) -> Batch:
+    if idx == 0:
+        return uniform_batch(CONFIG_SEEDS[0], n_grasps or 64, 4, 6,
+                             geometry="sphere", mu=0.5, name="sphere-m4-s6")
+    if idx in (1, 2):
+        return uniform_batch(CONFIG_SEEDS[idx], n_grasps or 8192, 5, 16,
+                             geometry="ellipsoid", name="ellipsoid-m5-s16")
+    if idx == 3:
+        return mixed_batch(CONFIG_SEEDS[3], n_grasps or 50000,
+                           name="ellipsoid-m45-s6to32")
+    raise ValueError("config %d is not a single batch" % idx)
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float      # seconds from stream start
+    batch: Batch
+    steps: int          # upper-level steps to run
+    walk: np.ndarray    # [steps, G, m_max, 3] perturbations of the points
+
+
+def request_stream(seed=CONFIG_SEEDS[4], rate=200.0, duration=60.0,
+                   size_range=(16, 4096), steps=50, sigma=1e-3,
+                   max_requests=None):
+    """Poisson arrivals; each request is a mixed batch of log-uniform size,
+    with a random walk on its contact points (normals fixed) per step."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    rid = 0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > duration or (max_requests is not None and rid >= max_requests):
+            return
+        size = int(np.exp(rng.uniform(np.log(size_range[0]), np.log(size_range[1]))))
+        sub_seed = int(rng.integers(0, 2 ** 62))
+        b = mixed_batch(sub_seed, size, name="req%d" % rid)
+        walk_rng = np.random.Generator(np.random.PCG64(sub_seed ^ 0x5DEECE66D))
+        walk = (sigma * walk_rng.standard_normal((steps,) + b.points.shape)).astype(np.float32)
+        for g in range(b.n_grasps):
+            walk[:, g, b.counts[g]:] = 0.0
+        yield Request(rid, t, b, steps, walk)
+        rid += 1
