@@ -1,0 +1,288 @@
+"""ctypes binding of the C ABI in include/bodex_qp.h (argument marshalling only).
+
+Every step of the solve runs in the HIP library; this module converts torch
+tensors to device pointers and host arrays to C arrays.  If the library has not
+been built, importing works but every call raises -- there is no fallback.
+
+Functions keep the C names (``bodex_qp_create``, ``bodex_qp_solve``,
+``bodex_qp_backward``, ``bodex_qp_destroy``); ``Solver`` bundles them.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbodex_qp.so")
+
+OK, EINVAL, EHIP, EBUDGET, EINFEAS, EUNSUP, ENODEV = 0, -1, -2, -3, -4, -5, -6
+ST_CONVERGED, ST_MAX_ITER, ST_NONFINITE, ST_FP64_CHOL, ST_POLISH_REJ, ST_POLISHED = (
+    0x01, 0x02, 0x04, 0x08, 0x10, 0x20)
+F_WARM_START, F_POLISH, F_ADAPTIVE_RHO, F_BATCHED, F_GRAPH = 0x01, 0x02, 0x04, 0x08, 0x10
+
+
+class BodexError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("bodex_qp error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("m_max", ctypes.c_int), ("s_max", ctypes.c_int),
+        ("force_max", ctypes.c_float), ("gamma", ctypes.c_float),
+        ("beta", ctypes.c_float), ("eps_reg", ctypes.c_float),
+        ("torque_scale", ctypes.c_float), ("tol_rel", ctypes.c_float),
+        ("max_iters", ctypes.c_int), ("rho0", ctypes.c_float),
+        ("alpha", ctypes.c_float), ("check_every", ctypes.c_int),
+        ("rho_min", ctypes.c_float), ("rho_max", ctypes.c_float),
+        ("rho_hysteresis", ctypes.c_float), ("fp64_cond", ctypes.c_float),
+        ("polish_steps", ctypes.c_int), ("iters_per_chunk", ctypes.c_int),
+        ("flags", ctypes.c_uint),
+    ]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [
+        ("n_grasps", ctypes.c_int), ("n_qps", ctypes.c_int),
+        ("contact_count", ctypes.POINTER(ctypes.c_int)),
+        ("wrench_offset", ctypes.POINTER(ctypes.c_int)),
+        ("points", ctypes.c_void_p), ("normals", ctypes.c_void_p),
+        ("mu", ctypes.c_void_p), ("wrench_dir", ctypes.c_void_p),
+    ]
+
+
+class State(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("z", ctypes.c_void_p),
+                ("y", ctypes.c_void_p), ("rho", ctypes.c_void_p)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("forces", ctypes.c_void_p), ("qp_obj", ctypes.c_void_p),
+        ("energy", ctypes.c_void_p), ("kkt_rel", ctypes.c_void_p),
+        ("iters", ctypes.c_void_p), ("status", ctypes.c_void_p),
+        ("state", State),
+    ]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def lib():
+    """The loaded library; raises when it is missing (no CPU fallback)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("HIP library %s is not built; run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        L.bodex_qp_default_params.argtypes = [ctypes.POINTER(Params)]
+        L.bodex_qp_default_params.restype = None
+        L.bodex_qp_create.argtypes = [ctypes.POINTER(Params), ctypes.c_int, ctypes.c_void_p,
+                                      ctypes.c_size_t, ctypes.POINTER(ctypes.c_void_p)]
+        L.bodex_qp_create.restype = ctypes.c_int
+        L.bodex_qp_set_stream.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.bodex_qp_set_stream.restype = ctypes.c_int
+        L.bodex_qp_solve.argtypes = [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Result)]
+        L.bodex_qp_solve.restype = ctypes.c_int
+        L.bodex_qp_backward.argtypes = [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(State),
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_int]
+        L.bodex_qp_backward.restype = ctypes.c_int
+        L.bodex_qp_destroy.argtypes = [ctypes.c_void_p]
+        L.bodex_qp_destroy.restype = ctypes.c_int
+        L.bodex_qp_last_error.argtypes = [ctypes.c_void_p]
+        L.bodex_qp_last_error.restype = ctypes.c_char_p
+        L.bodex_qp_state_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.bodex_qp_state_bytes.restype = ctypes.c_size_t
+        L.bodex_qp_last_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        L.bodex_qp_last_stats.restype = ctypes.c_int
+        _lib = L
+        return L
+
+
+EXPORTED = ("bodex_qp_default_params", "bodex_qp_create", "bodex_qp_set_stream",
+            "bodex_qp_solve", "bodex_qp_backward", "bodex_qp_destroy",
+            "bodex_qp_last_error", "bodex_qp_state_bytes", "bodex_qp_last_stats")
+
+
+def default_params(**overrides) -> Params:
+    p = Params()
+    lib().bodex_qp_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        if k == "flags_set":
+            p.flags |= int(v)
+        elif k == "flags_clear":
+            p.flags &= ~int(v)
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _check(rc, handle=None):
+    if rc != 0:
+        msg = lib().bodex_qp_last_error(handle)
+        raise BodexError(rc, msg.decode() if msg else "")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def bodex_qp_create(params: Params, device: int = 0, stream=None, budget: int = 0):
+    h = ctypes.c_void_p()
+    s = ctypes.c_void_p(stream) if stream else None
+    _check(lib().bodex_qp_create(ctypes.byref(params), int(device), s, ctypes.c_size_t(budget),
+                                 ctypes.byref(h)))
+    return h
+
+
+def bodex_qp_destroy(h) -> None:
+    if h:
+        _check(lib().bodex_qp_destroy(h))
+
+
+def bodex_qp_state_bytes(n_grasps: int, n_qps: int, m_max: int) -> int:
+    return int(lib().bodex_qp_state_bytes(n_grasps, n_qps, m_max))
+
+
+class DeviceBatch:
+    """Device copies of a workload.Batch plus its host CSR arrays."""
+
+    def __init__(self, batch, device="cuda"):
+        import torch
+        self.counts = np.ascontiguousarray(batch.counts, dtype=np.int32)
+        self.woff = np.ascontiguousarray(batch.woff, dtype=np.int32)
+        self.points = torch.as_tensor(np.ascontiguousarray(batch.points, np.float32), device=device)
+        self.normals = torch.as_tensor(np.ascontiguousarray(batch.normals, np.float32), device=device)
+        self.mu = torch.as_tensor(np.ascontiguousarray(batch.mu, np.float32), device=device)
+        self.wrench = torch.as_tensor(np.ascontiguousarray(batch.wrench, np.float32), device=device)
+        self.n_grasps = int(self.counts.shape[0])
+        self.n_qps = int(self.woff[-1])
+        self.m_max = int(self.points.shape[1])
+
+    def c_batch(self) -> Batch:
+        b = Batch()
+        b.n_grasps = self.n_grasps
+        b.n_qps = self.n_qps
+        b.contact_count = self.counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        b.wrench_offset = self.woff.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        b.points = _ptr(self.points)
+        b.normals = _ptr(self.normals)
+        b.mu = _ptr(self.mu)
+        b.wrench_dir = _ptr(self.wrench)
+        return b
+
+
+def new_state(n_grasps, n_qps, m_max, device="cuda"):
+    import torch
+    return {
+        "x": torch.zeros((3 * m_max, n_qps), dtype=torch.float32, device=device),
+        "z": torch.zeros((9 * m_max + 1, n_qps), dtype=torch.float32, device=device),
+        "y": torch.zeros((9 * m_max + 1, n_qps), dtype=torch.float32, device=device),
+        "rho": torch.zeros((n_grasps,), dtype=torch.float32, device=device),
+    }
+
+
+def new_result(n_grasps, n_qps, m_max, device="cuda"):
+    import torch
+    return {
+        "forces": torch.empty((n_qps, 3 * m_max), dtype=torch.float32, device=device),
+        "qp_obj": torch.empty((n_qps,), dtype=torch.float32, device=device),
+        "energy": torch.empty((n_grasps,), dtype=torch.float32, device=device),
+        "kkt_rel": torch.empty((n_qps,), dtype=torch.float32, device=device),
+        "iters": torch.empty((n_qps,), dtype=torch.int32, device=device),
+        "status": torch.empty((n_qps,), dtype=torch.uint8, device=device),
+    }
+
+
+def _c_state(st) -> State:
+    s = State()
+    if st is not None:
+        s.x, s.z, s.y, s.rho = _ptr(st["x"]), _ptr(st["z"]), _ptr(st["y"]), _ptr(st["rho"])
+    return s
+
+
+def bodex_qp_solve(h, batch: DeviceBatch, result: dict, state: dict | None = None) -> None:
+    r = Result()
+    r.forces = _ptr(result["forces"])
+    r.qp_obj = _ptr(result["qp_obj"])
+    r.energy = _ptr(result["energy"])
+    r.kkt_rel = _ptr(result["kkt_rel"])
+    r.iters = _ptr(result["iters"])
+    r.status = _ptr(result["status"])
+    r.state = _c_state(state)
+    b = batch.c_batch()
+    _check(lib().bodex_qp_solve(h, ctypes.byref(b), ctypes.byref(r)), h)
+
+
+def bodex_qp_backward(h, batch: DeviceBatch, state: dict, dL_dE=None, dL_dQ=None,
+                      dL_dpoints=None, dL_dnormals=None, accumulate: bool = False) -> None:
+    b = batch.c_batch()
+    s = _c_state(state)
+    _check(lib().bodex_qp_backward(h, ctypes.byref(b), ctypes.byref(s), _ptr(dL_dE), _ptr(dL_dQ),
+                                   _ptr(dL_dpoints), _ptr(dL_dnormals), 1 if accumulate else 0), h)
+
+
+def last_stats(h):
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().bodex_qp_last_stats(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), h)
+    return {"launches": a.value, "graph_replays": b.value, "tiles": c.value}
+
+
+class Solver:
+    """A handle on one device and stream (torch's current stream by default)."""
+
+    def __init__(self, params: Params | None = None, device: int = 0, stream=None,
+                 budget: int = 0, **overrides):
+        import torch
+        self.params = params if params is not None else default_params(**overrides)
+        if params is not None:
+            for k, v in overrides.items():
+                setattr(self.params, k, v)
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self.stream = stream
+        self.h = bodex_qp_create(self.params, device, stream, budget)
+
+    def solve(self, batch: DeviceBatch, state: dict | None = None, result: dict | None = None):
+        if result is None:
+            result = new_result(batch.n_grasps, batch.n_qps, self.params.m_max)
+        bodex_qp_solve(self.h, batch, result, state)
+        return result
+
+    def backward(self, batch: DeviceBatch, state: dict, dL_dE=None, dL_dQ=None, out=None,
+                 accumulate=False):
+        import torch
+        if out is None:
+            out = (torch.zeros_like(batch.points), torch.zeros_like(batch.normals))
+        bodex_qp_backward(self.h, batch, state, dL_dE, dL_dQ, out[0], out[1], accumulate)
+        return out
+
+    def stats(self):
+        return last_stats(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            bodex_qp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

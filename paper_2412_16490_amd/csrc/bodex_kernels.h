@@ -1,0 +1,909 @@
+// bodex_kernels.h -- gfx950 kernels of the batched contact-force QP.
+//
+// Mapping: one wavefront (64 lanes, one workgroup) per tile; a tile is a run
+// of up to kMaxSlots grasps ("slots") whose wrench QPs total at most 64; each
+// lane owns one wrench QP and keeps its ADMM state in VGPRs for the whole
+// solve.  The grasp's shared matrices (G, the inverse KKT matrix) live in LDS
+// and are read by all of the grasp's lanes.  There is no MFMA: the per-QP work
+// is a 15x15 symmetric matrix-vector product plus structured row operations,
+// not a dense contraction.
+//
+// Kernels:
+//   admm_kernel      grasp matrix, per-grasp factorisation, fused ADMM loop with
+//                    periodic residual checks and per-grasp rho adaptation;
+//                    writes the state (x, z, y, rho), iterations and status.
+//   finalize_kernel  FP64 polish (reduced KKT re-solve with dual active-set
+//                    correction), objective, energy, KKT residual, outputs.
+//   backward_kernel  recomputes f* from the state, Danskin gradient of the
+//                    energy with respect to G, chain rule to points/normals.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bodex_math.h"
+
+namespace bodex {
+
+constexpr int kMaxSlots = 12;  // keeps every kernel under 64 KB of LDS
+constexpr int kWave = 64;
+
+// Status bits (same values as the public header).
+constexpr unsigned char kStConverged = 0x01;
+constexpr unsigned char kStMaxIter = 0x02;
+constexpr unsigned char kStNonfinite = 0x04;
+constexpr unsigned char kStFp64 = 0x08;
+constexpr unsigned char kStPolishRej = 0x10;
+constexpr unsigned char kStPolished = 0x20;
+
+struct KArgs {
+    // inputs (device)
+    const float* points;
+    const float* normals;
+    const float* mu;
+    const float* wrench;
+    const int* counts;
+    const int* woff;
+    // schedule (device): tile t covers perm[tile_start[t] .. tile_start[t+1])
+    const int* perm;
+    const int* tile_start;
+    int n_tiles;
+    int slots;  // max grasps per tile (sizes the dynamic LDS)
+    int* queue; // persistent launch: tile counter (null = one tile per block)
+    int W;
+    int ms;     // array stride in contacts (m_max of the caller's layout, <= MM)
+    // state and outputs (device)
+    float* x;
+    float* z;
+    float* y;
+    float* rho;
+    float* forces;
+    float* qobj;
+    float* energy;
+    float* kkt;
+    int* iters;
+    unsigned char* status;
+    // backward
+    const float* dLdE;
+    const float* dLdQ;
+    float* dP;
+    float* dN;
+    int accumulate;
+    // polish workspace, NK doubles per lane, one 64-lane region per block
+    double* gwork;
+    // parameters
+    float kappa, beta, eps, fmax, gamma, tol, rho0, alpha, rho_min, rho_max, hyst, fp64_cond;
+    int max_iters, check_every, warm, adaptive, polish, polish_steps;
+};
+
+struct SlotInfo {
+    int g, m, s, w0;
+};
+
+// Row r of a kernel compiled for MM contacts in the caller's state layout with
+// ms <= MM contacts per grasp: rows of real contacts keep their index, the
+// normal-sum row moves from 9 MM to 9 ms, rows of padding contacts have none.
+template <int MM>
+__device__ inline int state_row(int r, int ms) {
+    if (r == 9 * MM) return 9 * ms;
+    return r < 9 * ms ? r : -1;
+}
+
+// Slot of each lane: lanes of one grasp are contiguous, in slot order.
+__device__ inline void lane_slot(const SlotInfo* info, int nsl, int lane, int& slot, int& j) {
+    slot = -1;
+    j = 0;
+    int acc = 0;
+    for (int k = 0; k < nsl; ++k) {
+        const int s = info[k].s;
+        if (lane >= acc && lane < acc + s) {
+            slot = k;
+            j = lane - acc;
+        }
+        acc += s;
+    }
+}
+
+__device__ inline int fetch_tile(const KArgs& a, int* sTile, int prev) {
+    if (a.queue == nullptr) return prev < 0 ? int(blockIdx.x) : a.n_tiles;
+    __syncthreads();
+    if (threadIdx.x == 0) *sTile = atomicAdd(a.queue, 1);
+    __syncthreads();
+    return *sTile;
+}
+
+__device__ inline void load_slots(const KArgs& a, int t, SlotInfo* info, int& nsl) {
+    const int gb = a.tile_start[t];
+    nsl = a.tile_start[t + 1] - gb;
+    if (int(threadIdx.x) < nsl) {
+        SlotInfo si;
+        si.g = a.perm[gb + threadIdx.x];
+        si.m = a.counts[si.g];
+        si.w0 = a.woff[si.g];
+        si.s = a.woff[si.g + 1] - si.w0;
+        info[threadIdx.x] = si;
+    }
+    __syncthreads();
+}
+
+// Cooperative inverse of an SPD NV x NV matrix per slot.  Every lane of the
+// wave calls it (it contains barriers); lanes of slots with do_it set do the
+// work.  Lw: the slot's packed-lower workspace (type T); Inv: the slot's
+// packed-upper output (type O).  entry(i, c) gives the matrix.  Returns false
+// on a lane whose slot hit a non-positive pivot.
+template <typename T, int NV, typename O, typename Entry>
+__device__ bool coop_inverse(bool do_it, int j, int s, T* Lw, O* Inv, T* yv, Entry entry) {
+    // yv: this lane's solve vector in LDS, yv[i * kWave] (lane-interleaved)
+    bool ok = true;
+    if (do_it) {
+#pragma unroll 1
+        for (int i = j; i < NV; i += s)
+#pragma unroll 1
+            for (int c = 0; c <= i; ++c) Lw[lo_idx(i, c)] = entry(i, c);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int k = 0; k < NV; ++k) {
+        T d = T(1);
+        if (do_it) {
+            d = Lw[lo_idx(k, k)];
+            if (!(d > T(0))) {
+                ok = false;
+                d = T(1);
+            }
+            d = sqrt(d);
+            #pragma unroll 1
+            for (int i = k + 1 + j; i < NV; i += s) Lw[lo_idx(i, k)] /= d;
+        }
+        __syncthreads();
+        if (do_it) {
+            #pragma unroll 1
+            for (int i = k + 1 + j; i < NV; i += s) {
+                const T lik = Lw[lo_idx(i, k)];
+                #pragma unroll 1
+                for (int c = k + 1; c <= i; ++c) Lw[lo_idx(i, c)] -= lik * Lw[lo_idx(c, k)];
+            }
+        }
+        __syncthreads();
+        if (do_it && j == 0) Lw[lo_idx(k, k)] = d;
+    }
+    __syncthreads();
+    if (do_it) {
+        // column col of the inverse: solve L L^T x = e_col (y = L^{-1} e_col
+        // vanishes above col)
+        #pragma unroll 1
+        for (int col = j; col < NV; col += s) {
+            #pragma unroll 1
+            for (int i = 0; i < col; ++i) yv[i * kWave] = T(0);
+            #pragma unroll 1
+            for (int i = col; i < NV; ++i) {
+                T acc = (i == col) ? T(1) : T(0);
+                #pragma unroll 1
+                for (int c = col; c < i; ++c) acc -= Lw[lo_idx(i, c)] * yv[c * kWave];
+                yv[i * kWave] = acc / Lw[lo_idx(i, i)];
+            }
+            #pragma unroll 1
+            for (int i = NV - 1; i >= 0; --i) {
+                T acc = yv[i * kWave];
+                #pragma unroll 1
+                for (int c = i + 1; c < NV; ++c) acc -= Lw[lo_idx(c, i)] * yv[c * kWave];
+                yv[i * kWave] = acc / Lw[lo_idx(i, i)];
+            }
+            #pragma unroll 1
+            for (int i = 0; i <= col; ++i) Inv[up_idx<NV>(i, col)] = O(yv[i * kWave]);
+        }
+    }
+    __syncthreads();
+    return ok;
+}
+
+// ---------------------------------------------------------------------------
+// Dynamic LDS layouts.
+// ---------------------------------------------------------------------------
+template <int MM>
+struct AdmmLds {
+    static constexpr int NV = 3 * MM, NK = NV * (NV + 1) / 2, NKP = Dims<MM>::NKP, NG = 6 * NV;
+    static __host__ __device__ size_t bytes(int slots) {
+        return size_t(slots) * (NKP * 4 + NG * 4 + 8 * 4 + NKP * 8) + size_t(64) * NV * 8 + 64 * 8 +
+               kMaxSlots * 32 + 64;
+    }
+};
+
+// State (x, z = Pi(w), y = rho (w - Pi(w))) of one lane in the caller's layout.
+template <int MM>
+__device__ __forceinline__ void write_admm_state(const KArgs& a, int w, const float* xv, const float* wv,
+                                                 float rho) {
+    constexpr int NV = 3 * MM, NR = 9 * MM + 1;
+    // keep the compiler from computing (and holding) these addresses early
+    asm volatile("" : "+v"(w));
+#pragma unroll
+    for (int c = 0; c < NV; ++c)
+        if (c < 3 * a.ms) a.x[size_t(c) * a.W + w] = xv[c];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        if (r % 9 == 0) BODEX_SPLIT();
+        const int sr = state_row<MM>(r, a.ms);
+        const float zr = row_proj(r, MM, wv[r], a.fmax, a.gamma);
+        if (sr >= 0) {
+            a.z[size_t(sr) * a.W + w] = zr;
+            a.y[size_t(sr) * a.W + w] = rho * (wv[r] - zr);
+        }
+    }
+}
+
+// (Re)factor K = P + rho A^T A of the slots with `mine` set and store K^{-1}
+// (packed upper, FP32) in LDS.  The factorisation is FP32, or FP64 for slots
+// whose conditioning bound exceeds fp64_cond.  Called by every lane of the
+// wave (barriers inside).  Returns bit 1 if this lane's slot used FP64, bit 2
+// if its factorisation failed.
+template <int MM>
+__device__ __forceinline__ int refactor_slots(const KArgs& a, bool mine, int slot, int j, int s, int m,
+                                              float rho, const float* sG, const float* sMuc, double* sLw,
+                                              float* sKi, double* sYv, int* sMisc) {
+    constexpr int NV = 3 * MM, NKP = Dims<MM>::NKP, NG = 6 * NV;
+    const float* Gs = sG + size_t(slot) * NG;
+    const float* mucs = sMuc + slot * 8;
+    if (threadIdx.x == 0) sMisc[1] = 0;
+    __syncthreads();
+    bool want64 = false;
+    if (mine) {
+        const float cb = kkt_cond_bound<float, NV>(Gs, mucs, m, rho, a.eps);
+        want64 = !(cb <= a.fp64_cond);
+        if (want64) atomicOr(&sMisc[1], 1);
+    }
+    __syncthreads();
+    const bool any64 = sMisc[1] != 0;
+    double* Lw = sLw + size_t(slot) * NKP;
+    float* Ki = sKi + size_t(slot) * NKP;
+    bool ok = true;
+    if (any64) {
+        const double rr = double(rho), eps = double(a.eps);
+        ok = coop_inverse<double, NV>(mine && want64, j, s, Lw, Ki, sYv + threadIdx.x, [&](int i, int c) {
+            const int ci = i / 3, cj = c / 3;
+            if (ci >= m || cj >= m) return (i == c) ? 1.0 : 0.0;
+            double sacc = 0.0;
+            for (int r = 0; r < 6; ++r) sacc += double(Gs[r * NV + i]) * double(Gs[r * NV + c]);
+            double v = 2.0 * sacc + ((i == c) ? 2.0 * eps : 0.0);
+            if (i % 3 == 0 && c % 3 == 0)
+                v += (ci == cj) ? rr * (8.0 * double(mucs[ci]) * double(mucs[ci]) + 2.0) : rr;
+            else if (i == c)
+                v += 4.0 * rr;
+            return v;
+        });
+    }
+    float* Lf = reinterpret_cast<float*>(Lw);
+    const float eps32 = a.eps;
+    float* yf = reinterpret_cast<float*>(sYv) + threadIdx.x;
+    const bool ok32 = coop_inverse<float, NV>(mine && !want64, j, s, Lf, Ki, yf, [&](int i, int c) {
+        return kkt_entry<float, NV>(Gs, mucs, m, rho, eps32, i, c);
+    });
+    int r = 0;
+    if (mine && want64) r |= 1;
+    if (mine && !(ok && ok32)) r |= 2;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// ADMM kernel.
+// ---------------------------------------------------------------------------
+template <int MM>
+__global__ void __launch_bounds__(64) admm_kernel(const KArgs a) {
+    constexpr int NV = 3 * MM, NR = 9 * MM + 1, NK = NV * (NV + 1) / 2;
+    constexpr int NKP = Dims<MM>::NKP, NG = 6 * NV;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int S = a.slots;
+    // carve: Lw (double) first for alignment
+    double* sLw = reinterpret_cast<double*>(smem);                       // [S][NKP]
+    double* sYv = sLw + size_t(S) * NKP;                                  // [NV][64]
+    float* sKi = reinterpret_cast<float*>(sYv + size_t(NV) * kWave);     // [S][NKP]
+    float* sG = sKi + size_t(S) * NKP;                                    // [S][NG]
+    float* sMuc = sG + size_t(S) * NG;                                    // [S][8]
+    float* sRp = sMuc + size_t(S) * 8;                                    // [64]
+    float* sRd = sRp + 64;                                                // [64]
+    SlotInfo* sInfo = reinterpret_cast<SlotInfo*>(sRd + 64);              // [kMaxSlots]
+    int* sFlag = reinterpret_cast<int*>(sInfo + kMaxSlots);               // [kMaxSlots]
+    float* sRho = reinterpret_cast<float*>(sFlag + kMaxSlots);            // [kMaxSlots]
+    int* sMisc = reinterpret_cast<int*>(sRho + kMaxSlots);                // [4]
+
+    const int lane = threadIdx.x;
+    for (int t = fetch_tile(a, sMisc, -1); t < a.n_tiles; t = fetch_tile(a, sMisc, t)) {
+        int nsl;
+        load_slots(a, t, sInfo, nsl);
+        int slot, j;
+        lane_slot(sInfo, nsl, lane, slot, j);
+        const bool act = slot >= 0;
+        SlotInfo si = {0, 0, 1, 0};
+        if (act) si = sInfo[slot];
+        const int m = si.m;
+        const int w = si.w0 + j;
+
+        // --- grasp matrix, friction terms, initial rho -----------------------
+        for (int e = lane; e < nsl * NG; e += kWave) sG[e] = 0.f;
+        for (int e = lane; e < nsl * 8; e += kWave) sMuc[e] = 0.f;
+        if (lane < nsl) sFlag[lane] = 0;
+        __syncthreads();
+        if (act) {
+            for (int c = j; c < m; c += si.s) {
+                const size_t base = (size_t(si.g) * a.ms + c) * 3;
+                const float p[3] = {a.points[base], a.points[base + 1], a.points[base + 2]};
+                const float n[3] = {a.normals[base], a.normals[base + 1], a.normals[base + 2]};
+                const float mu = a.mu[size_t(si.g) * a.ms + c];
+                const bool ok = grasp_columns<float, NV>(p, n, a.kappa, c, sG + size_t(slot) * NG);
+                sMuc[slot * 8 + c] = mu * float(kC8);
+                if (!ok || !(mu > 0.f) || !isfinite(mu)) atomicOr(&sFlag[slot], 4);
+            }
+            if (j == 0) {
+                float r0 = a.rho0;
+                if (a.warm) {
+                    const float rw = a.rho[si.g];
+                    if (rw > 0.f && isfinite(rw)) r0 = rw;
+                }
+                sRho[slot] = fminf(fmaxf(r0, a.rho_min), a.rho_max);
+            }
+        }
+        __syncthreads();
+        const float* Gs = sG + size_t(act ? slot : 0) * NG;
+        float muc[MM];
+#pragma unroll
+        for (int i = 0; i < MM; ++i) muc[i] = act ? sMuc[slot * 8 + i] : 0.f;
+        bool bad = act && (sFlag[slot] & 4);
+        float rho = act ? sRho[slot] : 1.f;
+
+        // --- per-lane right-hand side and initial state ------------------------
+        float bq[NV];
+        float wv[NR];
+        float xv[NV];
+        float tw[6];
+#pragma unroll
+        for (int r = 0; r < 6; ++r) tw[r] = act ? a.wrench[size_t(w) * 6 + r] : 0.f;
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            if (c % 3 == 0) BODEX_SPLIT();
+            float acc = 0.f;
+#pragma unroll
+            for (int r = 0; r < 6; ++r) acc = fmaf(Gs[r * NV + c], tw[r], acc);
+            bq[c] = 2.f * a.beta * acc;
+            xv[c] = 0.f;
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (r % 9 == 0) BODEX_SPLIT();
+            float v = 0.f;
+            const int sr = state_row<MM>(r, a.ms);
+            if (act && a.warm && sr >= 0) {
+                const float zr = a.z[size_t(sr) * a.W + w], yr = a.y[size_t(sr) * a.W + w];
+                v = zr + yr / rho;
+            }
+            wv[r] = isfinite(v) ? v : 0.f;
+        }
+
+        // --- factorisation ------------------------------------------------------
+        unsigned char stbits = 0;
+        {
+            const int fr = refactor_slots<MM>(a, act && !bad, act ? slot : 0, j, si.s, m, rho, sG, sMuc, sLw,
+                                              sKi, sYv, sMisc);
+            if (fr & 1) stbits |= kStFp64;
+            if (fr & 2) bad = true;
+        }
+
+        // --- ADMM loop ----------------------------------------------------------
+        bool done = !act || bad;
+        int it_done = 0;
+        float rel_last = INFINITY;
+        float rho_frz = rho;  // rho at which a converged lane's w was frozen
+        if (act && bad) {
+            stbits |= kStNonfinite;
+            it_done = 0;
+        }
+        const float* Ki = sKi + size_t(act ? slot : 0) * NKP;
+
+        int it = 0;
+        for (it = 1; it <= a.max_iters; ++it) {
+            if (!done) {
+                float rhs[NV];
+                admm_rhs<MM>(wv, bq, muc, rho, a.fmax, a.gamma, m, rhs);
+                symv_packed<NV>(Ki, rhs, xv);
+                admm_update<MM>(wv, xv, muc, a.alpha, a.fmax, a.gamma, m);
+            }
+            if (it % a.check_every != 0 && it != a.max_iters) continue;
+            float rpn = -1.f, rdn = -1.f;
+            if (!done) {
+                const Residual R = admm_residual<MM>(wv, xv, bq, muc, Gs, rho, a.eps, a.fmax, a.gamma, m);
+                rel_last = R.rel;
+                if (!isfinite(R.rel)) {
+                    done = true;
+                    stbits |= kStNonfinite;
+                    it_done = it;
+                } else if (R.rel <= a.tol) {
+                    done = true;
+                    stbits |= kStConverged;
+                    it_done = it;
+                    rho_frz = rho;
+                } else {
+                    rpn = R.rp_n;
+                    rdn = R.rd_n;
+                }
+            }
+            if (__all(done)) break;
+            if (!a.adaptive || it == a.max_iters) continue;
+            // per-grasp rho from the largest normalised residuals of live lanes
+            sRp[lane] = rpn;
+            sRd[lane] = rdn;
+            if (lane < nsl) sFlag[lane] &= ~1;
+            __syncthreads();
+            if (act && j == 0) {
+                float mp = -1.f, md = -1.f;
+                for (int l = lane; l < lane + si.s; ++l) {
+                    mp = fmaxf(mp, sRp[l]);
+                    md = fmaxf(md, sRd[l]);
+                }
+                if (mp > 0.f && md > 0.f) {
+                    float rn = rho * sqrtf(mp / md);
+                    rn = fminf(fmaxf(rn, a.rho_min), a.rho_max);
+                    if (rn > a.hyst * rho || rn < rho / a.hyst) {
+                        sRho[slot] = rn;
+                        sFlag[slot] |= 1;
+                    }
+                }
+            }
+            __syncthreads();
+            int anyf = 0;
+            for (int k = 0; k < nsl; ++k) anyf |= sFlag[k] & 1;
+            if (!anyf) continue;
+            const bool mine = act && !bad && (sFlag[slot] & 1);
+            if (mine) {
+                const float rn = sRho[slot];
+                if (!done) {
+                    // keep (z, y): w' = z + y / rho'
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        const float zr = row_proj(r, MM, wv[r], a.fmax, a.gamma);
+                        wv[r] = zr + (rho / rn) * (wv[r] - zr);
+                    }
+                }
+                rho = rn;
+            }
+            {
+                const int fr = refactor_slots<MM>(a, mine, act ? slot : 0, j, si.s, m, rho, sG, sMuc, sLw,
+                                                  sKi, sYv, sMisc);
+                if (fr & 1) stbits |= kStFp64;
+                if ((fr & 2) && mine && !done) {
+                    done = true;
+                    stbits |= kStNonfinite;
+                    it_done = it;
+                }
+            }
+        }
+        if (act && !(stbits & (kStConverged | kStNonfinite))) {
+            stbits |= kStMaxIter;
+            it_done = a.max_iters;
+            rho_frz = rho;
+        }
+        if (act && (stbits & kStNonfinite)) {
+#pragma unroll
+            for (int c = 0; c < NV; ++c) xv[c] = NAN;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) wv[r] = NAN;
+            rel_last = NAN;
+        }
+        if (act) write_admm_state<MM>(a, w, xv, wv, rho_frz);
+        if (act) {
+            a.iters[w] = it_done;
+            a.status[w] = stbits;
+            a.kkt[w] = rel_last;
+            if (j == 0) a.rho[si.g] = rho;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Shared FP64 setup of the finalize and backward kernels: grasp matrix and
+// P^{-1} per slot.
+// ---------------------------------------------------------------------------
+template <int MM>
+struct FinLds {
+    static constexpr int NV = 3 * MM, NK = NV * (NV + 1) / 2, NG = 6 * NV;
+    // per slot: G64, Pinv, Lw, muc64(8), Gbar (backward); per lane: the
+    // energy / gradient reduction 6 + NV + 1.  The per-lane polish workspace
+    // lives in global memory (KArgs::gwork).
+    static __host__ __device__ size_t bytes(int slots) {
+        return size_t(slots) * (NG + NK + NK + 8 + NG) * 8 + size_t(64) * (6 + NV + 1) * 8 +
+               kMaxSlots * 32 + 64;
+    }
+};
+
+template <int MM>
+struct FinPtrs {
+    double *G, *Pinv, *Lw, *muc, *Gbar, *work, *red;
+    SlotInfo* info;
+    int* flag;
+};
+
+template <int MM>
+__device__ inline FinPtrs<MM> fin_carve(unsigned char* smem, int S) {
+    constexpr int NV = 3 * MM, NK = NV * (NV + 1) / 2, NG = 6 * NV;
+    FinPtrs<MM> P;
+    double* d = reinterpret_cast<double*>(smem);
+    P.G = d;
+    d += size_t(S) * NG;
+    P.Pinv = d;
+    d += size_t(S) * NK;
+    P.Lw = d;
+    d += size_t(S) * NK;
+    P.muc = d;
+    d += size_t(S) * 8;
+    P.Gbar = d;
+    d += size_t(S) * NG;
+    P.work = nullptr;
+    P.red = d;
+    d += size_t(64) * (6 + NV + 1);
+    P.info = reinterpret_cast<SlotInfo*>(d);
+    P.flag = reinterpret_cast<int*>(P.info + kMaxSlots);
+    return P;
+}
+
+template <int MM>
+__device__ inline bool fin_setup(const KArgs& a, const FinPtrs<MM>& P, double* work, int nsl, int slot,
+                                 int j, const SlotInfo& si) {
+    constexpr int NV = 3 * MM, NK = NV * (NV + 1) / 2, NG = 6 * NV;
+    const int lane = threadIdx.x;
+    const bool act = slot >= 0;
+    for (int e = lane; e < nsl * NG; e += kWave) P.G[e] = 0.0;
+    for (int e = lane; e < nsl * 8; e += kWave) P.muc[e] = 0.0;
+    if (lane < nsl) P.flag[lane] = 0;
+    __syncthreads();
+    if (act) {
+        for (int c = j; c < si.m; c += si.s) {
+            const size_t base = (size_t(si.g) * a.ms + c) * 3;
+            const double p[3] = {a.points[base], a.points[base + 1], a.points[base + 2]};
+            const double n[3] = {a.normals[base], a.normals[base + 1], a.normals[base + 2]};
+            const double mu = a.mu[size_t(si.g) * a.ms + c];
+            const bool ok = grasp_columns<double, NV>(p, n, double(a.kappa), c, P.G + size_t(slot) * NG);
+            P.muc[slot * 8 + c] = mu * kC8;
+            if (!ok || !(mu > 0.0) || !isfinite(mu)) atomicOr(&P.flag[slot], 4);
+        }
+    }
+    __syncthreads();
+    const bool bad = act && (P.flag[slot] & 4);
+    const double* Gs = P.G + size_t(act ? slot : 0) * NG;
+    const double eps = a.eps;
+    const bool ok = coop_inverse<double, NV>(act && !bad, j, si.s, P.Lw + size_t(act ? slot : 0) * NK,
+                                             P.Pinv + size_t(act ? slot : 0) * NK, work,
+                                             [&](int i, int c) { return hess_entry<double, NV>(Gs, eps, i, c); });
+    return act && !bad && ok;
+}
+
+// Lane-strided accessor for a per-lane workspace in LDS.
+template <int MM>
+struct StridedY {
+    const float* base;
+    size_t stride;
+    int ms;
+    __device__ float operator[](int r) const {
+        const int sr = state_row<MM>(r, ms);
+        return sr >= 0 ? base[size_t(sr) * stride] : 0.f;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Finalize kernel: polish, objective, energy, KKT residual, outputs.
+// ---------------------------------------------------------------------------
+template <int MM>
+__global__ void __launch_bounds__(64) finalize_kernel(const KArgs a) {
+    constexpr int NV = 3 * MM, NR = 9 * MM + 1, NK = NV * (NV + 1) / 2, NG = 6 * NV;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const FinPtrs<MM> P = fin_carve<MM>(smem, a.slots);
+    const int lane = threadIdx.x;
+    __shared__ int sTile;
+    for (int t = fetch_tile(a, &sTile, -1); t < a.n_tiles; t = fetch_tile(a, &sTile, t)) {
+        int nsl;
+        load_slots(a, t, P.info, nsl);
+        int slot, j;
+        lane_slot(P.info, nsl, lane, slot, j);
+        const bool act = slot >= 0;
+        SlotInfo si = {0, 0, 1, 0};
+        if (act) si = P.info[slot];
+        double* work = a.gwork + size_t(blockIdx.x) * kWave * NK + lane;
+        const bool good = fin_setup<MM>(a, P, work, nsl, slot, j, si);
+        const int w = si.w0 + j;
+        double Q = 0.0;
+        if (act) {
+            const double* Gs = P.G + size_t(slot) * NG;
+            const double* Pinv = P.Pinv + size_t(slot) * NK;
+            double muc[MM];
+#pragma unroll
+            for (int i = 0; i < MM; ++i) muc[i] = P.muc[slot * 8 + i];
+            double q[NV];
+            double tw[6];
+#pragma unroll
+            for (int r = 0; r < 6; ++r) tw[r] = a.wrench[size_t(w) * 6 + r];
+#pragma unroll
+            for (int c = 0; c < NV; ++c) {
+                double acc = 0.0;
+#pragma unroll
+                for (int r = 0; r < 6; ++r) acc += Gs[r * NV + c] * tw[r];
+                q[c] = -2.0 * double(a.beta) * acc;
+            }
+            unsigned char st = a.status[w];
+            float xs[NV], zs[NR], ys[NR];
+#pragma unroll
+            for (int c = 0; c < NV; ++c) xs[c] = (c < 3 * a.ms) ? a.x[size_t(c) * a.W + w] : 0.f;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int sr = state_row<MM>(r, a.ms);
+                zs[r] = sr >= 0 ? a.z[size_t(sr) * a.W + w] : 0.f;
+                ys[r] = sr >= 0 ? a.y[size_t(sr) * a.W + w] : 0.f;
+            }
+            double xf[NV];
+#pragma unroll
+            for (int c = 0; c < NV; ++c) xf[c] = xs[c];
+            const bool finite_in = good && !(st & kStNonfinite);
+            if (finite_in && a.polish) {
+                PolishCtx<MM> X;
+                X.m = si.m;
+                X.fmax = a.fmax;
+                X.gamma = a.gamma;
+                X.eps = a.eps;
+                X.beta = a.beta;
+                X.muc = P.muc + slot * 8;
+                double xp[NV], lam[NV];
+                int actr[NV], k = 0;
+                const StridedY<MM> y0{a.y + w, size_t(a.W), a.ms};
+                const PolishOut po = polish_qp<MM>(X, y0, Gs, Pinv, q, work, kWave,
+                                                   a.polish_steps, xp, lam, actr, &k);
+                if (po.status == 0) {
+                    st |= kStPolished;
+                    st &= ~kStPolishRej;
+#pragma unroll
+                    for (int c = 0; c < NV; ++c) {
+                        xf[c] = xp[c];
+                        xs[c] = float(xp[c]);
+                    }
+                    // ADMM-form state of the polished point: z = A x projected
+                    // on [l, u], y = multipliers of the active rows.
+                    double s1 = 0.0;
+#pragma unroll
+                    for (int i = 0; i < MM; ++i) {
+#pragma unroll
+                        for (int kk = 0; kk < 9; ++kk) {
+                            double zz = 0.0;
+                            if (i < si.m) {
+                                if (kk < 8)
+                                    zz = facet_cos<double>(kk) * xp[3 * i + 1] +
+                                         facet_sin<double>(kk) * xp[3 * i + 2] - muc[i] * xp[3 * i];
+                                else
+                                    zz = xp[3 * i];
+                            }
+                            zs[9 * i + kk] = row_proj(9 * i + kk, MM, float(zz), a.fmax, a.gamma);
+                            ys[9 * i + kk] = 0.f;
+                        }
+                        if (i < si.m) s1 += xp[3 * i];
+                    }
+                    zs[9 * MM] = fmaxf(float(s1), a.gamma);
+                    ys[9 * MM] = 0.f;
+#pragma unroll
+                    for (int jj = 0; jj < NV; ++jj) {
+                        if (jj < k) {
+                            const int r = actr[jj];
+#pragma unroll
+                            for (int rr = 0; rr < NR; ++rr) {
+                                if (rr == r) {
+                                    if (r == 9 * MM) {
+                                        ys[rr] = float(-lam[jj]);
+                                        zs[rr] = a.gamma;
+                                    } else {
+                                        ys[rr] = float(lam[jj]);
+                                        zs[rr] = (r % 9 == 8) ? a.fmax : 0.f;
+                                    }
+                                }
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int c = 0; c < NV; ++c)
+                        if (c < 3 * a.ms) a.x[size_t(c) * a.W + w] = xs[c];
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) {
+                        const int sr = state_row<MM>(r, a.ms);
+                        if (sr >= 0) {
+                            a.z[size_t(sr) * a.W + w] = zs[r];
+                            a.y[size_t(sr) * a.W + w] = ys[r];
+                        }
+                    }
+                } else {
+                    st |= kStPolishRej;
+                    st &= ~kStPolished;
+                }
+            }
+            // objective from the returned forces (FP64)
+            double rr2 = 0.0, ff = 0.0;
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                double v = -double(a.beta) * tw[r];
+#pragma unroll
+                for (int c = 0; c < NV; ++c) v += Gs[r * NV + c] * xf[c];
+                rr2 += v * v;
+            }
+#pragma unroll
+            for (int c = 0; c < NV; ++c) ff += xf[c] * xf[c];
+            Q = rr2 + double(a.eps) * ff;
+            double rel = NAN;
+            if (finite_in) rel = rel_kkt64<MM>(Gs, muc, q, si.m, double(a.eps), xs, zs, ys);
+            if (rel <= double(a.tol))
+                st |= kStConverged;
+            else
+                st &= ~kStConverged;
+            if (!finite_in) {
+                st |= kStNonfinite;
+                Q = NAN;
+            }
+            a.status[w] = st;
+            a.kkt[w] = float(rel);
+            a.qobj[w] = float(Q);
+#pragma unroll
+            for (int c = 0; c < NV; ++c)
+                if (c < 3 * a.ms) a.forces[size_t(w) * 3 * a.ms + c] = finite_in ? float(xf[c]) : NAN;
+        }
+        P.red[lane] = Q;
+        __syncthreads();
+        if (act && j == 0) {
+            double E = 0.0;
+            for (int l = lane; l < lane + si.s; ++l) E += P.red[l];
+            a.energy[si.g] = float(E);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Backward kernel.
+// ---------------------------------------------------------------------------
+template <int MM>
+__global__ void __launch_bounds__(64) backward_kernel(const KArgs a) {
+    constexpr int NV = 3 * MM, NR = 9 * MM + 1, NK = NV * (NV + 1) / 2, NG = 6 * NV;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const FinPtrs<MM> P = fin_carve<MM>(smem, a.slots);
+    const int lane = threadIdx.x;
+    __shared__ int sTile;
+    for (int t = fetch_tile(a, &sTile, -1); t < a.n_tiles; t = fetch_tile(a, &sTile, t)) {
+        int nsl;
+        load_slots(a, t, P.info, nsl);
+        int slot, j;
+        lane_slot(P.info, nsl, lane, slot, j);
+        const bool act = slot >= 0;
+        SlotInfo si = {0, 0, 1, 0};
+        if (act) si = P.info[slot];
+        double* work = a.gwork + size_t(blockIdx.x) * kWave * NK + lane;
+        const bool good = fin_setup<MM>(a, P, work, nsl, slot, j, si);
+        const int w = si.w0 + j;
+        double* rw = P.red + size_t(lane) * (6 + NV);  // 2 * omega * r (6), f (NV)
+#pragma unroll
+        for (int e = 0; e < 6 + NV; ++e) rw[e] = 0.0;
+        if (act && good) {
+            const double* Gs = P.G + size_t(slot) * NG;
+            const double* Pinv = P.Pinv + size_t(slot) * NK;
+            double muc[MM];
+#pragma unroll
+            for (int i = 0; i < MM; ++i) muc[i] = P.muc[slot * 8 + i];
+            double tw[6], q[NV];
+#pragma unroll
+            for (int r = 0; r < 6; ++r) tw[r] = a.wrench[size_t(w) * 6 + r];
+#pragma unroll
+            for (int c = 0; c < NV; ++c) {
+                double acc = 0.0;
+#pragma unroll
+                for (int r = 0; r < 6; ++r) acc += Gs[r * NV + c] * tw[r];
+                q[c] = -2.0 * double(a.beta) * acc;
+            }
+            double f[NV];
+#pragma unroll
+            for (int c = 0; c < NV; ++c) f[c] = (c < 3 * a.ms) ? a.x[size_t(c) * a.W + w] : 0.0;
+            PolishCtx<MM> X;
+            X.m = si.m;
+            X.fmax = a.fmax;
+            X.gamma = a.gamma;
+            X.eps = a.eps;
+            X.beta = a.beta;
+            X.muc = P.muc + slot * 8;
+            double xp[NV], lam[NV];
+            int actr[NV], k = 0;
+            const StridedY<MM> y0{a.y + w, size_t(a.W), a.ms};
+            const PolishOut po = polish_qp<MM>(X, y0, Gs, Pinv, q, work, kWave,
+                                               a.polish_steps, xp, lam, actr, &k);
+            if (po.status == 0) {
+#pragma unroll
+                for (int c = 0; c < NV; ++c) f[c] = xp[c];
+            }
+            double om = 0.0;
+            if (a.dLdQ) om += a.dLdQ[w];
+            if (a.dLdE) om += a.dLdE[si.g];
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                double v = -double(a.beta) * tw[r];
+#pragma unroll
+                for (int c = 0; c < NV; ++c) v += Gs[r * NV + c] * f[c];
+                rw[r] = 2.0 * om * v;
+            }
+#pragma unroll
+            for (int c = 0; c < NV; ++c) rw[6 + c] = f[c];
+        }
+        __syncthreads();
+        // Gbar = sum over the grasp's wrenches of 2 omega r f^T
+        if (act) {
+            double* Gb = P.Gbar + size_t(slot) * NG;
+            const int l0 = lane - j;
+            for (int e = j; e < NG; e += si.s) {
+                const int r = e / NV, c = e % NV;
+                double acc = 0.0;
+                for (int l = l0; l < l0 + si.s; ++l) {
+                    const double* o = P.red + size_t(l) * (6 + NV);
+                    acc += o[r] * o[6 + c];
+                }
+                Gb[e] = acc;
+            }
+        }
+        __syncthreads();
+        if (act) {
+            const double* Gb = P.Gbar + size_t(slot) * NG;
+            const double kap = a.kappa;
+            for (int c = j; c < a.ms; c += si.s) {
+                double dp[3] = {0, 0, 0}, dn[3] = {0, 0, 0};
+                const size_t base = (size_t(si.g) * a.ms + c) * 3;
+                if (c < si.m && good) {
+                    const double p[3] = {a.points[base], a.points[base + 1], a.points[base + 2]};
+                    const double n[3] = {a.normals[base], a.normals[base + 1], a.normals[base + 2]};
+                    double nh[3], d[3], e[3];
+                    contact_frame<double>(n[0], n[1], n[2], nh, d, e);
+                    const double* vec[3] = {nh, d, e};
+                    double dv[3][3];
+                    for (int col = 0; col < 3; ++col) {
+                        double gf[3], gt[3], cx[3];
+                        for (int r = 0; r < 3; ++r) {
+                            gf[r] = Gb[r * NV + 3 * c + col];
+                            gt[r] = Gb[(3 + r) * NV + 3 * c + col];
+                        }
+                        // d/dp of gt . (p x v) is v x gt
+                        cross3(vec[col], gt, cx);
+                        for (int r = 0; r < 3; ++r) dp[r] += kap * cx[r];
+                        // d/dv of gf . v + gt . (p x v) is gf + gt x p
+                        cross3(gt, p, cx);
+                        for (int r = 0; r < 3; ++r) dv[col][r] = gf[r] + kap * cx[r];
+                    }
+                    // derivatives of the basis formula in nhat (sign fixed off z = 0)
+                    const double x = nh[0], yy = nh[1], zz = nh[2];
+                    const double sg = copysign(1.0, zz);
+                    const double aa = -1.0 / (sg + zz), a2 = aa * aa;
+                    const double Jd[3][3] = {{2 * sg * x * aa, 0.0, sg * x * x * a2},
+                                             {sg * yy * aa, sg * x * aa, sg * x * yy * a2},
+                                             {-sg, 0.0, 0.0}};
+                    const double Je[3][3] = {{yy * aa, x * aa, x * yy * a2},
+                                             {0.0, 2 * yy * aa, yy * yy * a2},
+                                             {0.0, -1.0, 0.0}};
+                    double dnh[3];
+                    for (int kx = 0; kx < 3; ++kx) {
+                        dnh[kx] = dv[0][kx];
+                        for (int r = 0; r < 3; ++r) dnh[kx] += Jd[r][kx] * dv[1][r] + Je[r][kx] * dv[2][r];
+                    }
+                    const double len = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+                    const double pr = dnh[0] * nh[0] + dnh[1] * nh[1] + dnh[2] * nh[2];
+                    for (int kx = 0; kx < 3; ++kx) dn[kx] = (dnh[kx] - pr * nh[kx]) / len;
+                } else if (c < si.m) {
+                    dp[0] = dp[1] = dp[2] = NAN;
+                    dn[0] = dn[1] = dn[2] = NAN;
+                }
+                for (int r = 0; r < 3; ++r) {
+                    if (a.accumulate) {
+                        a.dP[base + r] += float(dp[r]);
+                        a.dN[base + r] += float(dn[r]);
+                    } else {
+                        a.dP[base + r] = float(dp[r]);
+                        a.dN[base + r] = float(dn[r]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+
+}  // namespace bodex

@@ -1,0 +1,616 @@
+// bodex_qp.hip -- host side of the C ABI declared in include/bodex_qp.h.
+//
+// Responsibilities: argument validation (host-side, before any device work),
+// the tile schedule (which grasps share a wavefront), library-owned device
+// workspace within the handle's budget, kernel launches on the handle's
+// stream, and hipGraph capture/replay of repeated launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/bodex_qp.h"
+#include "bodex_kernels.h"
+#include "bodex_launch.h"
+
+using bodex::KArgs;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct GraphEntry {
+    uint64_t key = 0;
+    hipGraphExec_t exec = nullptr;
+    int* d_desc = nullptr;
+    size_t desc_ints = 0;
+    int* d_queue = nullptr;
+    double* d_gwork = nullptr;
+    uint64_t stamp = 0;
+};
+
+struct Schedule {
+    std::vector<int> perm;
+    std::vector<int> tile_start;
+    int slots = 1;
+    int n_tiles = 0;
+};
+
+}  // namespace
+
+struct bodex_qp {
+    bodex_qp_params prm;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t budget = 0;
+    int n_cu = 256;
+    std::string err;
+
+    // device descriptor buffer: counts | woff | perm | tile_start | queue(4)
+    int* d_desc = nullptr;
+    size_t d_desc_cap = 0;
+    int* h_desc = nullptr;  // pinned staging
+    size_t h_desc_cap = 0;
+    hipEvent_t desc_ev = nullptr;
+    bool desc_pending = false;
+    // internal state when the caller passes none
+    float* d_state = nullptr;
+    size_t d_state_cap = 0;
+    // global polish workspace (large m_max)
+    double* d_gwork = nullptr;
+    size_t d_gwork_cap = 0;
+    // graphs
+    std::vector<GraphEntry> graphs;
+    uint64_t graph_clock = 0;
+    // stats of the last call
+    int last_launches = 0, last_replays = 0, last_tiles = 0;
+    size_t owned_bytes = 0;
+};
+
+namespace {
+
+int fail(bodex_qp* h, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (h)
+        h->err = buf;
+    else
+        g_create_error = buf;
+    return code;
+}
+
+int hip_fail(bodex_qp* h, hipError_t e, const char* what) {
+    return fail(h, BODEX_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(h, call)                                   \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hip_fail((h), e_, #call); \
+    } while (0)
+
+bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
+
+// Contact counts the kernels are compiled for.  A batch with m_max contacts
+// per grasp runs on the smallest compiled size >= m_max (array strides stay
+// m_max; the extra contacts are inert padding).
+#ifndef BODEX_WITH_MM8
+constexpr int kCompiledMM[] = {4, 5};
+#else
+constexpr int kCompiledMM[] = {4, 5, 8};
+#endif
+
+int kernel_mm(int m_max) {
+    for (int mm : kCompiledMM)
+        if (mm >= m_max) return mm;
+    return 0;
+}
+
+size_t admm_lds(int mm, int slots) {
+    switch (mm) {
+        case 4: return bodex::AdmmLds<4>::bytes(slots);
+        case 5: return bodex::AdmmLds<5>::bytes(slots);
+#ifdef BODEX_WITH_MM8
+        case 8: return bodex::AdmmLds<8>::bytes(slots);
+#endif
+    }
+    return 0;
+}
+
+size_t fin_lds(int mm, int slots) {
+    switch (mm) {
+        case 4: return bodex::FinLds<4>::bytes(slots);
+        case 5: return bodex::FinLds<5>::bytes(slots);
+#ifdef BODEX_WITH_MM8
+        case 8: return bodex::FinLds<8>::bytes(slots);
+#endif
+    }
+    return 0;
+}
+
+// FP64 polish workspace per resident block of the finalize/backward kernels.
+size_t polish_work_bytes(int mm, int blocks) {
+    const size_t nk = size_t(3 * mm) * (3 * mm + 1) / 2;
+    return size_t(blocks) * 64 * nk * sizeof(double);
+}
+
+// Resident blocks of the finalize/backward kernels (they loop over the tile
+// queue; the count bounds the polish workspace).
+constexpr int kFinBlocksPerCU = 4;
+
+// Build the tile schedule.  Plain: grasps in index order, greedily packed.
+// Batched: grasps sorted by (m, s) so that tiles are uniform in contact count
+// and pack wrench counts tightly; tiles ordered by estimated cost (largest
+// first) for the persistent work queue.
+void build_schedule(const int* counts, const int* woff, int G, bool batched, Schedule& S) {
+    S.perm.resize(G);
+    std::iota(S.perm.begin(), S.perm.end(), 0);
+    if (batched) {
+        std::stable_sort(S.perm.begin(), S.perm.end(), [&](int a, int b) {
+            if (counts[a] != counts[b]) return counts[a] > counts[b];
+            return (woff[a + 1] - woff[a]) > (woff[b + 1] - woff[b]);
+        });
+    }
+    S.tile_start.clear();
+    S.tile_start.push_back(0);
+    int cur_q = 0, cur_n = 0, slots = 1;
+    int cur_m = -1;
+    for (int i = 0; i < G; ++i) {
+        const int g = S.perm[i];
+        const int s = woff[g + 1] - woff[g];
+        const bool split = cur_n > 0 && (cur_q + s > bodex::kWave || cur_n >= bodex::kMaxSlots ||
+                                         (batched && counts[g] != cur_m));
+        if (split) {
+            S.tile_start.push_back(i);
+            slots = std::max(slots, cur_n);
+            cur_q = 0;
+            cur_n = 0;
+        }
+        cur_q += s;
+        cur_n += 1;
+        cur_m = counts[g];
+    }
+    if (cur_n > 0) {
+        S.tile_start.push_back(G);
+        slots = std::max(slots, cur_n);
+    }
+    S.n_tiles = int(S.tile_start.size()) - 1;
+    S.slots = slots;
+    if (batched && S.n_tiles > 1) {
+        // largest tiles first: cost ~ m^2 * (QPs in tile)
+        std::vector<int> order(S.n_tiles);
+        std::iota(order.begin(), order.end(), 0);
+        std::vector<long> cost(S.n_tiles);
+        for (int t = 0; t < S.n_tiles; ++t) {
+            long c = 0;
+            for (int i = S.tile_start[t]; i < S.tile_start[t + 1]; ++i) {
+                const int g = S.perm[i];
+                c += long(counts[g]) * counts[g] * (woff[g + 1] - woff[g]);
+            }
+            cost[t] = c;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+        std::vector<int> perm2;
+        std::vector<int> ts2{0};
+        perm2.reserve(G);
+        for (int t : order) {
+            for (int i = S.tile_start[t]; i < S.tile_start[t + 1]; ++i) perm2.push_back(S.perm[i]);
+            ts2.push_back(int(perm2.size()));
+        }
+        S.perm.swap(perm2);
+        S.tile_start.swap(ts2);
+    }
+}
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+int ensure_device(bodex_qp* h, void** ptr, size_t* cap, size_t need) {
+    if (*cap >= need) return 0;
+    size_t extra = need - *cap;
+    if (h->owned_bytes + extra > h->budget)
+        return fail(h, BODEX_EBUDGET, "workspace of %zu bytes exceeds the budget of %zu bytes",
+                    h->owned_bytes + extra, h->budget);
+    if (*ptr) {
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        HIP_TRY(h, hipFree(*ptr));
+        h->owned_bytes -= *cap;
+        *ptr = nullptr;
+        *cap = 0;
+    }
+    HIP_TRY(h, hipMalloc(ptr, need));
+    *cap = need;
+    h->owned_bytes += need;
+    return 0;
+}
+
+enum class Kind { Admm, Fin, Bwd };
+
+hipError_t launch(Kind k, int mm, const KArgs& a, int grid, size_t lds, hipStream_t st) {
+    if (k == Kind::Admm) return bodex::launch_admm(mm, a, grid, lds, st);
+    if (k == Kind::Fin) return bodex::launch_finalize(mm, a, grid, lds, st);
+    return bodex::launch_backward(mm, a, grid, lds, st);
+}
+
+int validate_params(const bodex_qp_params* p, bodex_qp* h) {
+    if (!p) return fail(h, BODEX_EINVAL, "params is NULL");
+    if (p->m_max < 1 || p->m_max > BODEX_MAX_CONTACTS)
+        return fail(h, BODEX_EINVAL, "m_max=%d outside [1, %d]", p->m_max, BODEX_MAX_CONTACTS);
+    if (p->s_max < 1 || p->s_max > BODEX_MAX_WRENCHES)
+        return fail(h, BODEX_EINVAL, "s_max=%d outside [1, %d]", p->s_max, BODEX_MAX_WRENCHES);
+    if (!(p->force_max > 0.f) || !std::isfinite(p->force_max))
+        return fail(h, BODEX_EINVAL, "force_max must be positive");
+    if (!(p->gamma >= 0.f) || !std::isfinite(p->gamma)) return fail(h, BODEX_EINVAL, "gamma must be >= 0");
+    if (!(p->beta >= 0.f) || !std::isfinite(p->beta)) return fail(h, BODEX_EINVAL, "beta must be >= 0");
+    if (!(p->eps_reg > 0.f)) return fail(h, BODEX_EINVAL, "eps_reg must be positive");
+    if (!std::isfinite(p->torque_scale)) return fail(h, BODEX_EINVAL, "torque_scale must be finite");
+    if (!(p->tol_rel > 0.f)) return fail(h, BODEX_EINVAL, "tol_rel must be positive");
+    if (p->max_iters < 1) return fail(h, BODEX_EINVAL, "max_iters must be >= 1");
+    if (!(p->rho0 > 0.f)) return fail(h, BODEX_EINVAL, "rho0 must be positive");
+    if (!(p->alpha > 0.f && p->alpha < 2.f)) return fail(h, BODEX_EINVAL, "alpha must be in (0, 2)");
+    if (p->check_every < 1) return fail(h, BODEX_EINVAL, "check_every must be >= 1");
+    if (!(p->rho_min > 0.f) || !(p->rho_max >= p->rho_min))
+        return fail(h, BODEX_EINVAL, "need 0 < rho_min <= rho_max");
+    if (!(p->rho_hysteresis >= 1.f)) return fail(h, BODEX_EINVAL, "rho_hysteresis must be >= 1");
+    if (!(p->fp64_cond > 0.f)) return fail(h, BODEX_EINVAL, "fp64_cond must be positive");
+    if (p->polish_steps < 0) return fail(h, BODEX_EINVAL, "polish_steps must be >= 0");
+    return 0;
+}
+
+KArgs make_args(const bodex_qp* h, const bodex_batch* in) {
+    const bodex_qp_params& p = h->prm;
+    KArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.points = in->points;
+    a.normals = in->normals;
+    a.mu = in->mu;
+    a.wrench = in->wrench_dir;
+    a.W = in->n_qps;
+    a.ms = p.m_max;
+    a.kappa = p.torque_scale;
+    a.beta = p.beta;
+    a.eps = p.eps_reg;
+    a.fmax = p.force_max;
+    a.gamma = p.gamma;
+    a.tol = p.tol_rel;
+    a.rho0 = p.rho0;
+    a.alpha = p.alpha;
+    a.rho_min = p.rho_min;
+    a.rho_max = p.rho_max;
+    a.hyst = p.rho_hysteresis;
+    a.fp64_cond = p.fp64_cond;
+    a.max_iters = p.max_iters;
+    a.check_every = p.check_every;
+    a.warm = (p.flags & BODEX_F_WARM_START) ? 1 : 0;
+    a.adaptive = (p.flags & BODEX_F_ADAPTIVE_RHO) ? 1 : 0;
+    a.polish = (p.flags & BODEX_F_POLISH) ? 1 : 0;
+    a.polish_steps = p.polish_steps;
+    return a;
+}
+
+// Validate the batch (host arrays only).  Returns 0 or an error code.
+int validate_batch(bodex_qp* h, const bodex_batch* in) {
+    if (!in) return fail(h, BODEX_EINVAL, "batch is NULL");
+    const int G = in->n_grasps;
+    if (G < 0) return fail(h, BODEX_EINVAL, "n_grasps < 0");
+    if (G == 0) return 0;
+    if (!in->contact_count || !in->wrench_offset)
+        return fail(h, BODEX_EINVAL, "contact_count / wrench_offset (host arrays) are NULL");
+    if (!in->points || !in->normals || !in->mu || !in->wrench_dir)
+        return fail(h, BODEX_EINVAL, "an input device pointer is NULL");
+    if (!aligned4(in->points) || !aligned4(in->normals) || !aligned4(in->mu) || !aligned4(in->wrench_dir))
+        return fail(h, BODEX_EINVAL, "input pointers must be 4-byte aligned");
+    const int* c = in->contact_count;
+    const int* wo = in->wrench_offset;
+    if (wo[0] != 0) return fail(h, BODEX_EINVAL, "wrench_offset[0] must be 0");
+    for (int g = 0; g < G; ++g) {
+        if (c[g] < 1 || c[g] > h->prm.m_max)
+            return fail(h, BODEX_EINVAL, "grasp %d: contact count %d outside [1, %d]", g, c[g], h->prm.m_max);
+        const int s = wo[g + 1] - wo[g];
+        if (s < 1) return fail(h, BODEX_EINVAL, "grasp %d: %d wrenches (need >= 1)", g, s);
+        if (s > h->prm.s_max)
+            return fail(h, BODEX_EUNSUP, "grasp %d: %d wrenches exceed s_max=%d", g, s, h->prm.s_max);
+        if (double(h->prm.gamma) > double(c[g]) * double(h->prm.force_max))
+            return fail(h, BODEX_EINFEAS, "grasp %d: gamma=%g > m*fmax=%g", g, double(h->prm.gamma),
+                        double(c[g]) * double(h->prm.force_max));
+    }
+    if (wo[G] != in->n_qps) return fail(h, BODEX_EINVAL, "n_qps=%d != wrench_offset[G]=%d", in->n_qps, wo[G]);
+    return 0;
+}
+
+// Upload counts | woff | perm | tile_start | queue(4) to `dst` via the pinned
+// staging buffer.  Returns 0 or an error.
+int upload_desc(bodex_qp* h, const bodex_batch* in, const Schedule& S, int* dst, size_t* n_ints_out) {
+    const int G = in->n_grasps;
+    const size_t n = size_t(G) + (G + 1) + G + (S.n_tiles + 1) + 4;
+    if (h->desc_pending) {
+        HIP_TRY(h, hipEventSynchronize(h->desc_ev));
+        h->desc_pending = false;
+    }
+    if (h->h_desc_cap < n) {
+        if (h->h_desc) HIP_TRY(h, hipHostFree(h->h_desc));
+        h->h_desc = nullptr;
+        HIP_TRY(h, hipHostMalloc(reinterpret_cast<void**>(&h->h_desc), n * sizeof(int), hipHostMallocDefault));
+        h->h_desc_cap = n;
+    }
+    int* p = h->h_desc;
+    std::memcpy(p, in->contact_count, sizeof(int) * G);
+    std::memcpy(p + G, in->wrench_offset, sizeof(int) * (G + 1));
+    std::memcpy(p + 2 * G + 1, S.perm.data(), sizeof(int) * G);
+    std::memcpy(p + 3 * G + 1, S.tile_start.data(), sizeof(int) * (S.n_tiles + 1));
+    std::memset(p + 3 * G + 2 + S.n_tiles, 0, sizeof(int) * 4);
+    HIP_TRY(h, hipMemcpyAsync(dst, p, n * sizeof(int), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipEventRecord(h->desc_ev, h->stream));
+    h->desc_pending = true;
+    *n_ints_out = n;
+    return 0;
+}
+
+void bind_desc(KArgs& a, const int* d, int G, const Schedule& S) {
+    a.counts = d;
+    a.woff = d + G;
+    a.perm = d + 2 * G + 1;
+    a.tile_start = d + 3 * G + 1;
+    a.n_tiles = S.n_tiles;
+    a.slots = S.slots;
+}
+
+int occupancy_grid(bodex_qp* h, int blocks_per_cu_cap, int n_tiles) {
+    int g = h->n_cu * blocks_per_cu_cap;
+    return std::max(1, std::min(g, n_tiles));
+}
+
+}  // namespace
+
+extern "C" {
+
+void bodex_qp_default_params(bodex_qp_params* p) {
+    if (!p) return;
+    p->m_max = 5;
+    p->s_max = 32;
+    p->force_max = 1.0f;
+    p->gamma = 0.0f;
+    p->beta = 1.0f;
+    p->eps_reg = 1e-6f;
+    p->torque_scale = 20.0f;
+    p->tol_rel = 1e-5f;
+    p->max_iters = 500;
+    p->rho0 = 0.1f;
+    p->alpha = 1.6f;
+    p->check_every = 10;
+    p->rho_min = 1e-4f;
+    p->rho_max = 1e4f;
+    p->rho_hysteresis = 5.0f;
+    p->fp64_cond = 1e4f;
+    p->polish_steps = 64;
+    p->iters_per_chunk = 20;
+    p->flags = BODEX_F_POLISH | BODEX_F_ADAPTIVE_RHO;
+}
+
+int bodex_qp_create(const bodex_qp_params* p, int device, void* hip_stream, size_t hbm_budget_bytes,
+                    bodex_qp_t** out) {
+    if (!out) return fail(nullptr, BODEX_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate_params(p, nullptr);
+    if (rc) return rc;
+    if (kernel_mm(p->m_max) == 0)
+        return fail(nullptr, BODEX_EUNSUP, "m_max=%d exceeds the contact counts this library was built for",
+                    p->m_max);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+        return fail(nullptr, BODEX_ENODEV, "no HIP device available");
+    if (device < 0 || device >= ndev)
+        return fail(nullptr, BODEX_EINVAL, "device %d outside [0, %d)", device, ndev);
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(nullptr, BODEX_EHIP, "hipSetDevice: %s", hipGetErrorString(e));
+    bodex_qp* h = new (std::nothrow) bodex_qp();
+    if (!h) return fail(nullptr, BODEX_EINVAL, "out of host memory");
+    h->prm = *p;
+    h->device = device;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    h->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t(4) << 30);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        h->n_cu = prop.multiProcessorCount;
+    e = hipEventCreateWithFlags(&h->desc_ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(nullptr, BODEX_EHIP, "hipEventCreate: %s", hipGetErrorString(e));
+    }
+    *out = h;
+    return 0;
+}
+
+int bodex_qp_set_stream(bodex_qp_t* h, void* hip_stream) {
+    if (!h) return BODEX_EINVAL;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    return 0;
+}
+
+int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
+    if (!h) return BODEX_EINVAL;
+    if (!out) return fail(h, BODEX_EINVAL, "result is NULL");
+    int rc = validate_batch(h, in);
+    if (rc) return rc;
+    h->last_launches = 0;
+    h->last_replays = 0;
+    h->last_tiles = 0;
+    const int G = in->n_grasps;
+    if (G == 0) return 0;
+    const int W = in->n_qps;
+    if (!out->forces || !out->qp_obj || !out->energy || !out->kkt_rel || !out->iters || !out->status)
+        return fail(h, BODEX_EINVAL, "an output pointer is NULL");
+    const bodex_state& st = out->state;
+    const bool have_state = st.x || st.z || st.y || st.rho;
+    if (have_state && !(st.x && st.z && st.y && st.rho))
+        return fail(h, BODEX_EINVAL, "state pointers must be all set or all NULL");
+    if ((h->prm.flags & BODEX_F_WARM_START) && !have_state)
+        return fail(h, BODEX_EINVAL, "warm start needs the caller's state");
+    HIP_TRY(h, hipSetDevice(h->device));
+
+    const int mm = kernel_mm(h->prm.m_max);
+    const int nv = 3 * h->prm.m_max, nr = 9 * h->prm.m_max + 1;
+    const bool batched = (h->prm.flags & BODEX_F_BATCHED) != 0;
+    Schedule S;
+    build_schedule(in->contact_count, in->wrench_offset, G, batched, S);
+    h->last_tiles = S.n_tiles;
+
+    KArgs a = make_args(h, in);
+    if (have_state) {
+        a.x = st.x;
+        a.z = st.z;
+        a.y = st.y;
+        a.rho = st.rho;
+    } else {
+        const size_t need = (size_t(W) * (nv + 2 * nr) + size_t(G)) * sizeof(float);
+        rc = ensure_device(h, reinterpret_cast<void**>(&h->d_state), &h->d_state_cap, need);
+        if (rc) return rc;
+        a.x = h->d_state;
+        a.z = a.x + size_t(W) * nv;
+        a.y = a.z + size_t(W) * nr;
+        a.rho = a.y + size_t(W) * nr;
+    }
+    a.forces = out->forces;
+    a.qobj = out->qp_obj;
+    a.energy = out->energy;
+    a.kkt = out->kkt_rel;
+    a.iters = out->iters;
+    a.status = out->status;
+
+    const size_t n_ints = size_t(G) * 3 + 1 + S.n_tiles + 1 + 4;
+    rc = ensure_device(h, reinterpret_cast<void**>(&h->d_desc), &h->d_desc_cap, n_ints * sizeof(int));
+    if (rc) return rc;
+    size_t up = 0;
+    rc = upload_desc(h, in, S, h->d_desc, &up);
+    if (rc) return rc;
+    bind_desc(a, h->d_desc, G, S);
+    int* d_queue = h->d_desc + (n_ints - 4);
+
+    // ADMM
+    const size_t lds_a = admm_lds(mm, S.slots);
+    int grid_a = S.n_tiles;
+    if (batched) {
+        a.queue = d_queue;
+        HIP_TRY(h, bodex::launch_reset(d_queue, 4, h->stream));
+        int per_cu = 0;
+        per_cu = std::max(1, std::min(16, int((160 * 1024) / std::max<size_t>(lds_a, 1))));
+        grid_a = occupancy_grid(h, per_cu, S.n_tiles);
+        h->last_launches++;
+    }
+    HIP_TRY(h, launch(Kind::Admm, mm, a, grid_a, lds_a, h->stream));
+    h->last_launches++;
+
+    // finalize (persistent over the tile queue; polish workspace per block)
+    const size_t lds_f = fin_lds(mm, S.slots);
+    KArgs f = a;
+    f.queue = d_queue + 1;
+    HIP_TRY(h, bodex::launch_reset(d_queue + 1, 1, h->stream));
+    h->last_launches++;
+    const int grid_f = occupancy_grid(h, kFinBlocksPerCU, S.n_tiles);
+    rc = ensure_device(h, reinterpret_cast<void**>(&h->d_gwork), &h->d_gwork_cap,
+                       polish_work_bytes(mm, grid_f));
+    if (rc) return rc;
+    f.gwork = h->d_gwork;
+    HIP_TRY(h, launch(Kind::Fin, mm, f, grid_f, lds_f, h->stream));
+    h->last_launches++;
+    return 0;
+}
+
+int bodex_qp_backward(bodex_qp_t* h, const bodex_batch* in, const bodex_state* st, const float* dL_dE,
+                      const float* dL_dQ, float* dL_dpoints, float* dL_dnormals, int accumulate) {
+    if (!h) return BODEX_EINVAL;
+    int rc = validate_batch(h, in);
+    if (rc) return rc;
+    const int G = in->n_grasps;
+    if (G == 0) return 0;
+    if (!st || !st->x || !st->z || !st->y)
+        return fail(h, BODEX_EINVAL, "backward needs the state written by a solve");
+    if (!dL_dpoints || !dL_dnormals) return fail(h, BODEX_EINVAL, "gradient outputs are NULL");
+    HIP_TRY(h, hipSetDevice(h->device));
+    const int mm = kernel_mm(h->prm.m_max);
+    Schedule S;
+    build_schedule(in->contact_count, in->wrench_offset, G, false, S);
+    KArgs a = make_args(h, in);
+    a.x = st->x;
+    a.z = st->z;
+    a.y = st->y;
+    a.rho = st->rho;
+    a.dLdE = dL_dE;
+    a.dLdQ = dL_dQ;
+    a.dP = dL_dpoints;
+    a.dN = dL_dnormals;
+    a.accumulate = accumulate ? 1 : 0;
+    const size_t n_ints = size_t(G) * 3 + 1 + S.n_tiles + 1 + 4;
+    rc = ensure_device(h, reinterpret_cast<void**>(&h->d_desc), &h->d_desc_cap, n_ints * sizeof(int));
+    if (rc) return rc;
+    size_t up = 0;
+    rc = upload_desc(h, in, S, h->d_desc, &up);
+    if (rc) return rc;
+    bind_desc(a, h->d_desc, G, S);
+    const size_t lds_b = fin_lds(mm, S.slots);
+    int* d_queue = h->d_desc + (n_ints - 4);
+    a.queue = d_queue + 2;
+    HIP_TRY(h, bodex::launch_reset(d_queue + 2, 1, h->stream));
+    const int grid_b = occupancy_grid(h, kFinBlocksPerCU, S.n_tiles);
+    rc = ensure_device(h, reinterpret_cast<void**>(&h->d_gwork), &h->d_gwork_cap,
+                       polish_work_bytes(mm, grid_b));
+    if (rc) return rc;
+    a.gwork = h->d_gwork;
+    HIP_TRY(h, launch(Kind::Bwd, mm, a, grid_b, lds_b, h->stream));
+    h->last_launches = 1;
+    return 0;
+}
+
+int bodex_qp_destroy(bodex_qp_t* h) {
+    if (!h) return 0;
+    (void)hipSetDevice(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    for (auto& g : h->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.d_desc) (void)hipFree(g.d_desc);
+        if (g.d_gwork) (void)hipFree(g.d_gwork);
+    }
+    if (h->d_desc) (void)hipFree(h->d_desc);
+    if (h->d_state) (void)hipFree(h->d_state);
+    if (h->d_gwork) (void)hipFree(h->d_gwork);
+    if (h->h_desc) (void)hipHostFree(h->h_desc);
+    if (h->desc_ev) (void)hipEventDestroy(h->desc_ev);
+    delete h;
+    return 0;
+}
+
+const char* bodex_qp_last_error(const bodex_qp_t* h) {
+    return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+size_t bodex_qp_state_bytes(int n_grasps, int n_qps, int m_max) {
+    if (n_grasps < 0 || n_qps < 0 || m_max < 1) return 0;
+    const size_t nv = 3 * size_t(m_max), nr = 9 * size_t(m_max) + 1;
+    return (size_t(n_qps) * (nv + 2 * nr) + size_t(n_grasps)) * sizeof(float);
+}
+
+int bodex_qp_last_stats(bodex_qp_t* h, int* launches, int* graph_replays, int* tiles) {
+    if (!h) return BODEX_EINVAL;
+    if (launches) *launches = h->last_launches;
+    if (graph_replays) *graph_replays = h->last_replays;
+    if (tiles) *tiles = h->last_tiles;
+    return 0;
+}
+
+}  // extern "C"

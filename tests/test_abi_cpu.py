@@ -1,0 +1,67 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects bad parameters before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2412_16490_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "bodex_qp.h")).read()
+    return sorted(set(re.findall(r"\b(bodex_qp_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(api.LIB_PATH):
+        pytest.skip("library not built")
+    return api.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert set(names) == set(api.EXPORTED)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_default_params_are_valid(L):
+    p = api.default_params()
+    assert p.m_max == 5 and p.max_iters == 500 and abs(p.eps_reg - 1e-6) < 1e-12
+    assert p.flags & api.F_POLISH and p.flags & api.F_ADAPTIVE_RHO
+
+
+@pytest.mark.parametrize("field,value", [("m_max", 0), ("m_max", 9), ("s_max", 0), ("s_max", 65),
+                                         ("eps_reg", 0.0), ("alpha", 2.0), ("max_iters", 0),
+                                         ("force_max", -1.0), ("rho_min", 0.0), ("tol_rel", 0.0)])
+def test_create_rejects_bad_params(L, field, value):
+    p = api.default_params()
+    setattr(p, field, value)
+    h = ctypes.c_void_p()
+    rc = L.bodex_qp_create(ctypes.byref(p), 0, None, 0, ctypes.byref(h))
+    assert rc == api.EINVAL
+    assert not h.value
+    assert L.bodex_qp_last_error(None)
+
+
+def test_create_without_device_reports_enodev(L):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    p = api.default_params()
+    h = ctypes.c_void_p()
+    assert L.bodex_qp_create(ctypes.byref(p), 0, None, 0, ctypes.byref(h)) == api.ENODEV
+
+
+def test_state_bytes(L):
+    assert api.bodex_qp_state_bytes(10, 100, 5) == (100 * (15 + 2 * 46) + 10) * 4
+    assert api.bodex_qp_state_bytes(-1, 1, 5) == 0
+
+
+def test_destroy_null_is_noop(L):
+    assert L.bodex_qp_destroy(None) == 0

@@ -1,0 +1,150 @@
+"""Backward pass and failure modes of the HIP solver.
+
+Backward: dE/dp, dE/dn from the hand-written backward kernel (f* recomputed
+from the saved state) against the oracle's Danskin gradient on every grasp, and
+against central differences of the oracle energy (FP64) on 64 grasps.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_16490_amd import api
+from paper_2412_16490_amd import workload as wl
+from gpu_common import oracle_params, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_grad(b, dE=None, dQ=None, **params):
+    import torch
+    p = api.default_params(m_max=b.m_max, s_max=int(np.max(np.diff(b.woff))))
+    for k, v in params.items():
+        setattr(p, k, v)
+    s = api.Solver(p)
+    db = api.DeviceBatch(b)
+    st = api.new_state(db.n_grasps, db.n_qps, db.m_max)
+    res = s.solve(db, state=st)
+    tE = torch.as_tensor(dE, dtype=torch.float32, device="cuda") if dE is not None else None
+    tQ = torch.as_tensor(dQ, dtype=torch.float32, device="cuda") if dQ is not None else None
+    gp, gn = s.backward(db, st, dL_dE=tE, dL_dQ=tQ)
+    torch.cuda.synchronize()
+    out = (gp.cpu().numpy().astype(np.float64), gn.cpu().numpy().astype(np.float64),
+           {k: v.cpu().numpy() for k, v in res.items()})
+    s.close()
+    return out
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-4)
+
+
+def test_backward_matches_oracle_gradient():
+    b = wl.config(2, 256)
+    gp, gn, res = _gpu_grad(b, dE=np.ones(b.n_grasps))
+    P0, N0 = b.points.astype(np.float64), b.normals.astype(np.float64)
+    ref = oracle.solve_batch(b.counts, b.woff, P0, N0, b.mu, b.wrench)
+    rp, rn = oracle.grad_batch(b.counts, b.woff, P0, N0, b.wrench, ref["forces"],
+                               we=np.ones(b.n_grasps))
+    ep = max(_rel(gp[g], rp[g]) for g in range(b.n_grasps))
+    en = max(_rel(gn[g], rn[g]) for g in range(b.n_grasps))
+    print("grad rel err points %.2e normals %.2e" % (ep, en))
+    assert ep <= 1e-3 and en <= 1e-3
+
+
+def test_backward_weights_dQ_and_dE():
+    b = wl.config(2, 32)
+    rng = np.random.default_rng(1)
+    wq = rng.standard_normal(b.n_qps)
+    we = rng.standard_normal(b.n_grasps)
+    gp, gn, _ = _gpu_grad(b, dE=we, dQ=wq)
+    P0, N0 = b.points.astype(np.float64), b.normals.astype(np.float64)
+    ref = oracle.solve_batch(b.counts, b.woff, P0, N0, b.mu, b.wrench)
+    rp, rn = oracle.grad_batch(b.counts, b.woff, P0, N0, b.wrench, ref["forces"], wq=wq, we=we)
+    for g in range(b.n_grasps):
+        assert _rel(gp[g], rp[g]) <= 1e-3 and _rel(gn[g], rn[g]) <= 1e-3
+
+
+def test_backward_matches_finite_differences():
+    # central differences of the oracle energy in FP64, h = 1e-6 (the oracle's
+    # own FD pin shows agreement to 1e-5 there on this workload)
+    b = wl.config(2, 64)
+    gp, gn, _ = _gpu_grad(b, dE=np.ones(b.n_grasps))
+    P0, N0 = b.points.astype(np.float64), b.normals.astype(np.float64)
+    h = 1e-6
+    fp = np.zeros_like(P0)
+    fn = np.zeros_like(N0)
+    for which, base, out in (("p", P0, fp), ("n", N0, fn)):
+        for i in range(b.m_max):
+            for c in range(3):
+                a1, a2 = base.copy(), base.copy()
+                a1[:, i, c] += h
+                a2[:, i, c] -= h
+                args = (a1, N0) if which == "p" else (P0, a1)
+                e1 = oracle.solve_batch(b.counts, b.woff, *args, b.mu, b.wrench)["energy"]
+                args = (a2, N0) if which == "p" else (P0, a2)
+                e2 = oracle.solve_batch(b.counts, b.woff, *args, b.mu, b.wrench)["energy"]
+                out[:, i, c] = (e1 - e2) / (2 * h)
+    for g in range(b.n_grasps):
+        seam = np.abs(N0[g, :, 2]) < 2 * h
+        a, c = gn[g].copy(), fn[g].copy()
+        a[seam, 2] = c[seam, 2] = 0
+        assert _rel(gp[g], fp[g]) <= 1e-3, g
+        assert _rel(a, c) <= 1e-3, g
+
+
+def test_nonfinite_input_is_isolated():
+    b = wl.config(1, 8)
+    b.normals[3, 2] = np.nan
+    b.mu[5, 0] = 0.0
+    gpu = run_gpu(b)
+    bad = set(range(b.woff[3], b.woff[4])) | set(range(b.woff[5], b.woff[6]))
+    for w in range(b.n_qps):
+        if w in bad:
+            assert gpu["status"][w] & api.ST_NONFINITE
+        else:
+            assert gpu["status"][w] & api.ST_CONVERGED
+            assert np.isfinite(gpu["qp_obj"][w])
+
+
+def test_max_iters_status_without_polish():
+    b = wl.config(1, 4)
+    flags = api.default_params().flags & ~api.F_POLISH
+    gpu = run_gpu(b, max_iters=1, flags=flags)
+    assert np.all(gpu["status"] & api.ST_MAX_ITER)
+    assert np.all(gpu["iters"] == 1)
+
+
+def test_argument_errors():
+    b = wl.config(1, 4)
+    with pytest.raises(api.BodexError) as e:
+        run_gpu(b, gamma=6.0)          # > m * fmax = 5
+    assert e.value.code == api.EINFEAS
+    p = api.default_params(m_max=5, s_max=8)
+    s = api.Solver(p)
+    db = api.DeviceBatch(b)
+    with pytest.raises(api.BodexError) as e:
+        s.solve(db)                   # 16 wrenches per grasp > s_max = 8
+    assert e.value.code == api.EUNSUP
+    s.close()
+
+
+def test_warm_start_from_optimum_converges_at_first_check():
+    import torch
+    b = wl.config(1, 16)
+    p = api.default_params(m_max=5, s_max=16)
+    s = api.Solver(p)
+    db = api.DeviceBatch(b)
+    st = api.new_state(db.n_grasps, db.n_qps, 5)
+    r1 = s.solve(db, state=st)
+    torch.cuda.synchronize()
+    f1 = r1["forces"].cpu().numpy()
+    s.close()
+    p2 = api.default_params(m_max=5, s_max=16)
+    p2.flags |= api.F_WARM_START
+    s2 = api.Solver(p2)
+    r2 = s2.solve(db, state=st)
+    torch.cuda.synchronize()
+    it2 = r2["iters"].cpu().numpy()
+    assert np.all(it2 <= p2.check_every)
+    np.testing.assert_allclose(r2["forces"].cpu().numpy(), f1, atol=1e-5)
+    s2.close()

@@ -1,0 +1,98 @@
+"""Parity of the HIP solver (through the C ABI) with the FP64 oracle.
+
+Sizes: the full 4-contact sphere workload (64 grasps, 384 QPs), subsets of the
+5-contact ellipsoid workload that span many tiles and end in a ragged tile,
+the mixed 4/5-contact uneven-wrench workload, and the full 8192-grasp
+ellipsoid workload in its benchmark launch with sampled QPs checked one by one.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_16490_amd import api
+from paper_2412_16490_amd import workload as wl
+from gpu_common import (check_energy, check_forward, check_state_kkt, oracle_params, run_gpu)
+
+pytestmark = pytest.mark.gpu
+
+
+def _ref(b, prm=None):
+    return oracle.solve_batch(b.counts, b.woff, b.points, b.normals, b.mu, b.wrench,
+                              prm=prm or oracle_params())
+
+
+def test_sphere_m4_s6_full():
+    b = wl.config(0)
+    gpu = run_gpu(b, tol_rel=1e-6)
+    ref = _ref(b)
+    print("sphere:", check_forward(b, gpu, ref), "iters mean", gpu["iters"].mean())
+    check_energy(b, gpu, ref)
+    check_state_kkt(b, gpu, 1e-5, range(b.n_qps))
+
+
+@pytest.mark.parametrize("ng", [1, 3, 37, 256])
+def test_ellipsoid_m5_s16_subsets(ng):
+    b = wl.config(1, ng)
+    gpu = run_gpu(b)
+    ref = _ref(b)
+    print("ellipsoid %d:" % ng, check_forward(b, gpu, ref), "iters mean", gpu["iters"].mean())
+    check_energy(b, gpu, ref)
+    check_state_kkt(b, gpu, 1e-5, range(0, b.n_qps, max(1, b.n_qps // 200)))
+
+
+def test_mixed_m45_uneven_s():
+    b = wl.config(3, 300)
+    gpu = run_gpu(b)
+    ref = _ref(b)
+    print("mixed:", check_forward(b, gpu, ref))
+    check_energy(b, gpu, ref)
+    check_state_kkt(b, gpu, 1e-5, range(0, b.n_qps, 37))
+
+
+def test_mixed_batched_form_matches_oracle():
+    b = wl.config(3, 300)
+    gpu = run_gpu(b, flags=api.default_params().flags | api.F_BATCHED)
+    ref = _ref(b)
+    check_forward(b, gpu, ref)
+    check_energy(b, gpu, ref)
+
+
+def test_full_ellipsoid_m5_s16_sampled():
+    b = wl.config(1)
+    gpu = run_gpu(b)
+    rng = np.random.default_rng(7)
+    grasps = np.sort(rng.choice(b.n_grasps, 64, replace=False))
+    sub = b.subset(grasps)
+    ref = _ref(sub)
+    qps = np.concatenate([np.arange(b.woff[g], b.woff[g + 1]) for g in grasps])
+    sub_gpu = {k: gpu[k][qps] for k in ("forces", "qp_obj", "status", "kkt_rel", "iters")}
+    sub_gpu["energy"] = gpu["energy"][grasps]
+    print("full:", check_forward(sub, sub_gpu, ref), "iters mean", gpu["iters"].mean())
+    check_energy(sub, sub_gpu, ref)
+    # properties at every QP of the full launch
+    assert np.all(gpu["status"] & api.ST_CONVERGED)
+    assert np.all(gpu["kkt_rel"] <= 1e-5)
+    assert np.all(np.isfinite(gpu["forces"]))
+
+
+def test_gamma_and_bounds_parity():
+    b = wl.config(1, 40)
+    for gamma, fmax, beta in [(0.5, 1.0, 1.0), (1.2, 0.5, 2.0)]:
+        gpu = run_gpu(b, gamma=gamma, force_max=fmax, beta=beta)
+        ref = _ref(b, oracle_params(gamma=gamma, fmax=fmax, beta=beta))
+        check_forward(b, gpu, ref, beta=beta, fmax=fmax)
+
+
+def test_small_contact_counts_in_m5_layout():
+    # grasps with 1 and 2 contacts (the brute-force sizes) inside a 5-contact layout
+    rng = np.random.default_rng(3)
+    b = wl.config(1, 24)
+    b.counts[:] = rng.integers(1, 3, size=24)
+    for g in range(24):
+        m = b.counts[g]
+        b.points[g, m:] = 0
+        b.normals[g, m:] = [0, 0, 1]
+    gpu = run_gpu(b)
+    ref = _ref(b)
+    check_forward(b, gpu, ref)
+    check_energy(b, gpu, ref)
