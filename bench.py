@@ -1,0 +1,327 @@
+"""Benchmark: contact-force QPs/s at relative KKT residual <= 1e-5.
+
+Workload (one step): the plain solve of 8192 grasps x 5 contacts x 16 desired
+wrenches = 131,072 QPs (ellipsoid contacts, mu ~ U[0.3, 0.8], seed 16491), inputs
+resident in HBM.  A step is one call of the library's solve: grasp matrices,
+per-grasp factorisation, fused ADMM with residual checks and rho adaptation,
+FP64 polish, objectives, energies and state.
+
+Prints one JSON line.  Besides the contract fields it carries:
+  roofline      the ADMM kernel (dominant) against the FP32 vector ALU peak
+  cpu_baseline  the FP64 oracle on the host cores over the same QPs
+  forms         the uneven batch (50,000 grasps) in one persistent graph launch
+                vs per-(m, s) plain launches, and forward+backward on the
+                differentiation workload
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMDs x 16 FP32 lanes x 2.4 GHz = 39.3e12 VALU lane-ops/s;
+# an FMA counts 2 flops -> 78.6 TFLOP/s without packed FP32 (which this build
+# does not use; the 157.3 TFLOP/s vendor figure assumes packed FMA).
+PEAK_FP32_TFLOPS = 78.6
+
+
+def admm_flops(m: int, iters: np.ndarray, check_every: int) -> float:
+    """Algorithmic flops of the ADMM kernel, counted from the arithmetic each
+    lane performs (FMA = 2 flops, every other add/mul/min/max/select = 1):
+      per iteration   18 m^2 + 92 m + 7   (917 at m = 5)
+        right-hand side 28m + 2 ops (7m + 1 FMA), K^{-1} product n^2 ops
+        (n(n-1) FMA, n = 3m), row update 47m + 3 ops (13m + 1 FMA)
+      per residual check  246 m + 19      (1249 at m = 5)
+    Factorisations (about n^3/3 per grasp and rho change) are left out."""
+    it = iters.astype(np.float64)
+    checks = np.floor(it / check_every)
+    per_iter = 18 * m * m + 92 * m + 7
+    per_check = 246 * m + 19
+    return float(np.sum(it * per_iter + checks * per_check))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-forms", action="store_true", help="skip the extra forms")
+    ap.add_argument("--serve-seconds", type=float, default=0.5,
+                    help="length of the Poisson arrival window of the served form")
+    ap.add_argument("--admm-waves", type=int, default=0, help="ADMM register budget (0 = default)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run device copies of MIB MiB (to scale HBM byte counters)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only (got --gpus %d, WORLD_SIZE %d); "
+              "the path shards by grasps with no exchange, see DESIGN.md" % (args.gpus, world),
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4,
+                          "launches": 3}), flush=True)
+        return
+
+    from paper_2412_16490_amd import api, build as hip_build
+    from paper_2412_16490_amd import workload as wl
+
+    if not os.path.exists(hip_build.LIB):
+        hip_build.build()
+    assert torch.cuda.is_available(), "no GPU"
+
+    batch = wl.config(1)
+    db = api.DeviceBatch(batch)
+    p = api.default_params(m_max=5, s_max=16)
+    p.flags |= api.F_TIMING
+    p.admm_waves = args.admm_waves
+    stream = torch.cuda.current_stream()
+    solver = api.Solver(p, stream=stream.cuda_stream)
+    st = api.new_state(db.n_grasps, db.n_qps, db.m_max)
+    res = api.new_result(db.n_grasps, db.n_qps, db.m_max)
+
+    for _ in range(args.warmup):
+        solver.solve(db, state=st, result=res)
+    torch.cuda.synchronize()
+
+    admm_ms, fin_ms = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solver.solve(db, state=st, result=res)
+        kt = solver.kernel_times()       # waits for this step's events
+        admm_ms.append(kt["admm_ms"])
+        fin_ms.append(kt["finalize_ms"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+
+    status = res["status"].cpu().numpy()
+    iters = res["iters"].cpu().numpy()
+    kkt = res["kkt_rel"].cpu().numpy()
+    converged = int(np.sum((status & api.ST_CONVERGED) != 0))
+    value = converged / (ms_step / 1e3)
+
+    admm_avg = float(np.mean(admm_ms))
+    flops = admm_flops(5, iters, p.check_every)
+    achieved = flops / (admm_avg / 1e3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "kernel": "admm_kernel<5>", "kernel_ms": round(admm_avg, 4),
+                "algorithmic_flops": flops}
+
+    out = {
+        "metric": "contact-force QPs/sec at rel. KKT resid <=1e-5 (plain vs batched/served); p50/p99",
+        "value": round(value, 1),
+        "unit": "QPs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "ellipsoid-m5-s16 (8192 grasps x 5 contacts x 16 wrenches, seed 16491)",
+                   "qps": int(db.n_qps), "tol_rel": float(p.tol_rel), "form": "plain",
+                   "polish": "fp64", "converged": converged,
+                   "kkt_rel_max": float(np.max(kkt)),
+                   "iters_mean": float(np.mean(iters)), "iters_p99": float(np.percentile(iters, 99)),
+                   "finalize_ms": round(float(np.mean(fin_ms)), 4)},
+        "roofline": roofline,
+    }
+    solver.close()
+
+    if not args.no_forms:
+        out["forms"] = forms(torch, api, wl)
+        out["forms"]["tuning"] = tuning(torch, api, db)
+        out["forms"].update(served(torch, wl, args.serve_seconds))
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(batch)
+
+    print(json.dumps(out), flush=True)
+
+
+def forms(torch, api, wl):
+    """Uneven batch: persistent graph launch vs per-(m, s) plain launches; and
+    forward + backward on the differentiation workload."""
+    res = {}
+    b3 = wl.config(3)
+    db3 = api.DeviceBatch(b3)
+    s_max = int(np.max(np.diff(b3.woff)))
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        pb = api.default_params(m_max=5, s_max=s_max)
+        pb.flags |= api.F_BATCHED | api.F_GRAPH
+        sb = api.Solver(pb, stream=side.cuda_stream)
+        st3 = api.new_state(db3.n_grasps, db3.n_qps, 5)
+        r3 = api.new_result(db3.n_grasps, db3.n_qps, 5)
+        for _ in range(2):
+            sb.solve(db3, state=st3, result=r3)
+        side.synchronize()
+        t0 = time.perf_counter()
+        n = 5
+        for _ in range(n):
+            sb.solve(db3, state=st3, result=r3)
+        side.synchronize()
+        tb = (time.perf_counter() - t0) / n
+        conv = int(np.sum((r3["status"].cpu().numpy() & api.ST_CONVERGED) != 0))
+        res["batched"] = {"workload": "ellipsoid-m45-s6to32 (50,000 grasps, %d QPs)" % db3.n_qps,
+                          "ms": round(tb * 1e3, 3), "qps_per_s": round(conv / tb, 1),
+                          "converged": conv, "graph_replays": sb.stats()["graph_replays"]}
+        sb.close()
+        # per-(m, s) plain launches of the same grasps
+        groups = {}
+        s_of = np.diff(b3.woff)
+        for g in range(b3.n_grasps):
+            groups.setdefault((int(b3.counts[g]), int(s_of[g])), []).append(g)
+        subs = []
+        for (m, s), gl in sorted(groups.items()):
+            sub = b3.subset(gl)
+            pp = api.default_params(m_max=5, s_max=s)
+            subs.append((api.Solver(pp, stream=side.cuda_stream), api.DeviceBatch(sub)))
+        outs = [(sv, d, api.new_state(d.n_grasps, d.n_qps, 5), api.new_result(d.n_grasps, d.n_qps, 5))
+                for sv, d in subs]
+        for sv, d, st, rr in outs:
+            sv.solve(d, state=st, result=rr)
+        side.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            for sv, d, st, rr in outs:
+                sv.solve(d, state=st, result=rr)
+        side.synchronize()
+        tp = (time.perf_counter() - t0) / n
+        convp = sum(int(np.sum((rr["status"].cpu().numpy() & api.ST_CONVERGED) != 0)) for _, _, _, rr in outs)
+        res["per_size_plain"] = {"launches": len(outs), "ms": round(tp * 1e3, 3),
+                                 "qps_per_s": round(convp / tp, 1), "converged": convp}
+        for sv, _, _, _ in outs:
+            sv.close()
+    # forward + backward (differentiation workload, same shape as the headline)
+    b2 = wl.config(2)
+    db2 = api.DeviceBatch(b2)
+    p2 = api.default_params(m_max=5, s_max=16)
+    p2.flags |= api.F_TIMING
+    s2 = api.Solver(p2)
+    st2 = api.new_state(db2.n_grasps, db2.n_qps, 5)
+    r2 = api.new_result(db2.n_grasps, db2.n_qps, 5)
+    ones = torch.ones(db2.n_grasps, device="cuda")
+    gp = torch.zeros_like(db2.points)
+    gn = torch.zeros_like(db2.normals)
+    for _ in range(2):
+        s2.solve(db2, state=st2, result=r2)
+        s2.backward(db2, st2, dL_dE=ones, out=(gp, gn))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bw = []
+    for _ in range(5):
+        s2.solve(db2, state=st2, result=r2)
+        s2.backward(db2, st2, dL_dE=ones, out=(gp, gn))
+        bw.append(s2.kernel_times()["backward_ms"])
+    torch.cuda.synchronize()
+    tfb = (time.perf_counter() - t0) / 5
+    res["fwd_bwd"] = {"workload": "ellipsoid-m5-s16 (seed 16492)", "ms": round(tfb * 1e3, 3),
+                      "backward_kernel_ms": round(float(np.mean(bw)), 4),
+                      "grasps_per_s": round(db2.n_grasps / tfb, 1)}
+    s2.close()
+    return res
+
+
+def tuning(torch, api, db):
+    """Headline solve time for each ADMM register budget (waves per SIMD)."""
+    res = {}
+    for occ in (1, 2, 3, 4):
+        p = api.default_params(m_max=5, s_max=16)
+        p.flags |= api.F_TIMING
+        p.admm_waves = occ
+        s = api.Solver(p)
+        st = api.new_state(db.n_grasps, db.n_qps, 5)
+        r = api.new_result(db.n_grasps, db.n_qps, 5)
+        s.solve(db, state=st, result=r)
+        torch.cuda.synchronize()
+        ks = []
+        for _ in range(5):
+            s.solve(db, state=st, result=r)
+            ks.append(s.kernel_times()["admm_ms"])
+        res["admm_waves_%d_ms" % occ] = round(float(np.median(ks)), 4)
+        s.close()
+    # ADMM stopped at a looser tolerance, the FP64 polish lifting every QP to
+    # the 1e-5 bar (same final criterion as the headline)
+    for atol in (1e-3, 1e-4):
+        p = api.default_params(m_max=5, s_max=16)
+        p.admm_tol = atol
+        s = api.Solver(p)
+        st = api.new_state(db.n_grasps, db.n_qps, 5)
+        r = api.new_result(db.n_grasps, db.n_qps, 5)
+        s.solve(db, state=st, result=r)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            s.solve(db, state=st, result=r)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 5
+        conv = int(np.sum((r["status"].cpu().numpy() & api.ST_CONVERGED) != 0))
+        res["admm_tol_%g" % atol] = {"ms": round(dt * 1e3, 4), "qps_per_s": round(conv / dt, 1),
+                                     "converged": conv,
+                                     "iters_mean": float(r["iters"].float().mean().item())}
+        s.close()
+    return res
+
+
+def served(torch, wl, seconds):
+    """Continuous batching vs FIFO plain launches on the same Poisson stream
+    (200 requests/s, 50 steps each, sizes log-U[16, 4096] grasps)."""
+    from paper_2412_16490_amd.serve import Server, serve_fifo_plain
+    reqs = list(wl.request_stream(rate=200.0, duration=seconds))
+    srv = Server(m_max=5, s_max=32, budget_bytes=4 << 30)
+    st = srv.run(reqs, realtime=True)
+    srv.close()
+    fifo = serve_fifo_plain(reqs[: max(1, len(reqs) // 4)], m_max=5, s_max=32, realtime=True)
+    return {"served": {"stream": "%d requests over %.2f s, 50 steps" % (len(reqs), seconds),
+                       "qp_solves_per_s": round(st["qps_per_s"], 1),
+                       "latency_p50_s": st["latency_p50_s"], "latency_p99_s": st["latency_p99_s"],
+                       "wall_s": round(st["wall_s"], 3), "ticks": st["ticks"],
+                       "peak_device_bytes": st["peak_device_bytes"]},
+            "fifo_plain": {"stream": "first %d of the same requests" % fifo["requests"],
+                           "qp_solves_per_s": round(fifo["qps_per_s"], 1),
+                           "latency_p50_s": fifo["latency_p50_s"], "latency_p99_s": fifo["latency_p99_s"],
+                           "wall_s": round(fifo["wall_s"], 3)}}
+
+
+def cpu_baseline(batch):
+    """The FP64 oracle (as it stands) on the host cores over the same QPs."""
+    import oracle
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        threads = os.cpu_count() or 1
+    threads = max(1, min(threads, 16))
+    t0 = time.perf_counter()
+    oracle.solve_batch(batch.counts, batch.woff, batch.points, batch.normals, batch.mu,
+                       batch.wrench, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": round(batch.n_qps / dt, 1), "unit": "QPs/s", "cores": threads, "kind": "oracle",
+            "sample": "all %d QPs of the 8192-grasp workload, %.1f s wall on %d threads"
+                      % (batch.n_qps, dt, threads)}
+
+
+if __name__ == "__main__":
+    main()

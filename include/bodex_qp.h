@@ -75,6 +75,7 @@ extern "C" {
 #define BODEX_F_BATCHED 0x08      /* persistent cost-sorted launch (uneven m,s)*/
 #define BODEX_F_GRAPH 0x10        /* capture launches in a hipGraph and replay */
                                   /* it while the batch shape is unchanged     */
+#define BODEX_F_TIMING 0x20       /* record HIP events around each kernel      */
 
 typedef struct {
     int m_max;            /* contacts per grasp, 1..8 (array padding)        */
@@ -96,6 +97,10 @@ typedef struct {
     int polish_steps;     /* cap on active-set corrections in the polish      */
     int iters_per_chunk;  /* batched form: iterations between queue checks    */
     unsigned flags;       /* BODEX_F_*                                        */
+    int admm_waves;       /* ADMM kernel register budget as resident waves   */
+                          /* per SIMD: 1, 2, 3 or 4 (0 = library default)     */
+    float admm_tol;       /* ADMM stops a QP at this relative KKT residual;   */
+                          /* the polish then lifts it to tol_rel (0 = tol_rel) */
 } bodex_qp_params;
 
 /* One batch of grasps (CSR over wrenches). */
@@ -137,7 +142,8 @@ typedef struct bodex_qp bodex_qp_t;
 /* Fill *p with the defaults: m_max 5, s_max 32, fmax 1, gamma 0, beta 1,
  * eps 1e-6, torque_scale 20, tol 1e-5, 500 iterations, rho0 0.1, alpha 1.6,
  * check every 10, rho in [1e-4, 1e4], hysteresis 5, fp64_cond 1e4, 64 polish
- * steps, 20 iterations per chunk, flags POLISH | ADAPTIVE_RHO. */
+ * steps, 20 iterations per chunk, flags POLISH | ADAPTIVE_RHO, admm_waves 0,
+ * admm_tol 0 (ADMM runs to tol_rel). */
 void bodex_qp_default_params(bodex_qp_params *p);
 
 /* Create a handle on `device` that enqueues on `hip_stream` (a hipStream_t;
@@ -185,6 +191,14 @@ size_t bodex_qp_state_bytes(int n_grasps, int n_qps, int m_max);
  * launches.  Any pointer may be NULL.  Synchronises the handle's stream. */
 int bodex_qp_last_stats(bodex_qp_t *h, int *launches, int *graph_replays,
                         int *tiles);
+
+/* Kernel durations (milliseconds) of the last solve and backward on this
+ * handle, measured with HIP events recorded on the handle's stream around each
+ * kernel when BODEX_F_TIMING is set (otherwise reported as -1).  With
+ * BODEX_F_GRAPH the events bracket the whole graph launch and are reported as
+ * the ADMM time.  Synchronises on the events.  Any pointer may be NULL. */
+int bodex_qp_kernel_times(bodex_qp_t *h, float *admm_ms, float *finalize_ms,
+                          float *backward_ms);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libbodex_qp.so")
 OK, EINVAL, EHIP, EBUDGET, EINFEAS, EUNSUP, ENODEV = 0, -1, -2, -3, -4, -5, -6
 ST_CONVERGED, ST_MAX_ITER, ST_NONFINITE, ST_FP64_CHOL, ST_POLISH_REJ, ST_POLISHED = (
     0x01, 0x02, 0x04, 0x08, 0x10, 0x20)
-F_WARM_START, F_POLISH, F_ADAPTIVE_RHO, F_BATCHED, F_GRAPH = 0x01, 0x02, 0x04, 0x08, 0x10
+F_WARM_START, F_POLISH, F_ADAPTIVE_RHO, F_BATCHED, F_GRAPH, F_TIMING = 0x01, 0x02, 0x04, 0x08, 0x10, 0x20
 
 
 class BodexError(RuntimeError):
@@ -41,7 +41,8 @@ class Params(ctypes.Structure):
         ("rho_min", ctypes.c_float), ("rho_max", ctypes.c_float),
         ("rho_hysteresis", ctypes.c_float), ("fp64_cond", ctypes.c_float),
         ("polish_steps", ctypes.c_int), ("iters_per_chunk", ctypes.c_int),
-        ("flags", ctypes.c_uint),
+        ("flags", ctypes.c_uint), ("admm_waves", ctypes.c_int),
+        ("admm_tol", ctypes.c_float),
     ]
 
 
@@ -104,13 +105,17 @@ def lib():
         L.bodex_qp_last_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
                                           ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         L.bodex_qp_last_stats.restype = ctypes.c_int
+        L.bodex_qp_kernel_times.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
+                                            ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
+        L.bodex_qp_kernel_times.restype = ctypes.c_int
         _lib = L
         return L
 
 
 EXPORTED = ("bodex_qp_default_params", "bodex_qp_create", "bodex_qp_set_stream",
             "bodex_qp_solve", "bodex_qp_backward", "bodex_qp_destroy",
-            "bodex_qp_last_error", "bodex_qp_state_bytes", "bodex_qp_last_stats")
+            "bodex_qp_last_error", "bodex_qp_state_bytes", "bodex_qp_last_stats",
+            "bodex_qp_kernel_times")
 
 
 def default_params(**overrides) -> Params:
@@ -243,6 +248,12 @@ def last_stats(h):
     return {"launches": a.value, "graph_replays": b.value, "tiles": c.value}
 
 
+def bodex_qp_kernel_times(h):
+    a, b, c = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
+    _check(lib().bodex_qp_kernel_times(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), h)
+    return {"admm_ms": a.value, "finalize_ms": b.value, "backward_ms": c.value}
+
+
 class Solver:
     """A handle on one device and stream (torch's current stream by default)."""
 
@@ -275,6 +286,9 @@ class Solver:
 
     def stats(self):
         return last_stats(self.h)
+
+    def kernel_times(self):
+        return bodex_qp_kernel_times(self.h)
 
     def close(self):
         if getattr(self, "h", None):

@@ -71,7 +71,7 @@ struct KArgs {
     // polish workspace, NK doubles per lane, one 64-lane region per block
     double* gwork;
     // parameters
-    float kappa, beta, eps, fmax, gamma, tol, rho0, alpha, rho_min, rho_max, hyst, fp64_cond;
+    float kappa, beta, eps, fmax, gamma, tol, admm_tol, rho0, alpha, rho_min, rho_max, hyst, fp64_cond;
     int max_iters, check_every, warm, adaptive, polish, polish_steps;
 };
 
@@ -203,29 +203,34 @@ template <int MM>
 struct AdmmLds {
     static constexpr int NV = 3 * MM, NK = NV * (NV + 1) / 2, NKP = Dims<MM>::NKP, NG = 6 * NV;
     static __host__ __device__ size_t bytes(int slots) {
-        return size_t(slots) * (NKP * 4 + NG * 4 + 8 * 4 + NKP * 8) + size_t(64) * NV * 8 + 64 * 8 +
-               kMaxSlots * 32 + 64;
+        return size_t(slots) * (NKP * 4 + NG * 4 + 8 * 4 + NKP * 8) + size_t(64) * NV * 8 +
+               size_t(64) * NV * 4 + 64 * 8 + kMaxSlots * 32 + 64;
     }
 };
 
-// State (x, z = Pi(w), y = rho (w - Pi(w))) of one lane in the caller's layout.
+// State of one lane in the caller's layout: x, and z = Pi(w), y = rho (w - Pi(w)).
+// Row bases are uniform across the wave; only the lane's offset is per lane.
 template <int MM>
-__device__ __forceinline__ void write_admm_state(const KArgs& a, int w, const float* xv, const float* wv,
-                                                 float rho) {
-    constexpr int NV = 3 * MM, NR = 9 * MM + 1;
-    // keep the compiler from computing (and holding) these addresses early
+__device__ __forceinline__ void write_admm_x(const KArgs& a, unsigned w, const float* xv) {
+    constexpr int NV = 3 * MM;
     asm volatile("" : "+v"(w));
 #pragma unroll
     for (int c = 0; c < NV; ++c)
-        if (c < 3 * a.ms) a.x[size_t(c) * a.W + w] = xv[c];
+        if (c < 3 * a.ms) (a.x + size_t(c) * a.W)[w] = xv[c];
+}
+
+template <int MM>
+__device__ __forceinline__ void write_admm_zy(const KArgs& a, unsigned w, const float* wv, float rho) {
+    constexpr int NR = 9 * MM + 1;
+    asm volatile("" : "+v"(w));
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         if (r % 9 == 0) BODEX_SPLIT();
         const int sr = state_row<MM>(r, a.ms);
         const float zr = row_proj(r, MM, wv[r], a.fmax, a.gamma);
         if (sr >= 0) {
-            a.z[size_t(sr) * a.W + w] = zr;
-            a.y[size_t(sr) * a.W + w] = rho * (wv[r] - zr);
+            (a.z + size_t(sr) * a.W)[w] = zr;
+            (a.y + size_t(sr) * a.W)[w] = rho * (wv[r] - zr);
         }
     }
 }
@@ -285,8 +290,9 @@ __device__ __forceinline__ int refactor_slots(const KArgs& a, bool mine, int slo
 // ---------------------------------------------------------------------------
 // ADMM kernel.
 // ---------------------------------------------------------------------------
-template <int MM>
-__global__ void __launch_bounds__(64) admm_kernel(const KArgs a) {
+// OCC: register budget expressed as resident waves per SIMD (1 = unlimited).
+template <int MM, int OCC>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) admm_kernel(const KArgs a) {
     constexpr int NV = 3 * MM, NR = 9 * MM + 1, NK = NV * (NV + 1) / 2;
     constexpr int NKP = Dims<MM>::NKP, NG = 6 * NV;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -295,7 +301,8 @@ __global__ void __launch_bounds__(64) admm_kernel(const KArgs a) {
     double* sLw = reinterpret_cast<double*>(smem);                       // [S][NKP]
     double* sYv = sLw + size_t(S) * NKP;                                  // [NV][64]
     float* sKi = reinterpret_cast<float*>(sYv + size_t(NV) * kWave);     // [S][NKP]
-    float* sG = sKi + size_t(S) * NKP;                                    // [S][NG]
+    float* sBq = sKi + size_t(S) * NKP;                                   // [NV][64]
+    float* sG = sBq + size_t(NV) * kWave;                                 // [S][NG]
     float* sMuc = sG + size_t(S) * NG;                                    // [S][8]
     float* sRp = sMuc + size_t(S) * 8;                                    // [64]
     float* sRd = sRp + 64;                                                // [64]
@@ -342,35 +349,37 @@ __global__ void __launch_bounds__(64) admm_kernel(const KArgs a) {
         }
         __syncthreads();
         const float* Gs = sG + size_t(act ? slot : 0) * NG;
-        float muc[MM];
-#pragma unroll
-        for (int i = 0; i < MM; ++i) muc[i] = act ? sMuc[slot * 8 + i] : 0.f;
+        const float* muc = sMuc + (act ? slot : 0) * 8;
         bool bad = act && (sFlag[slot] & 4);
         float rho = act ? sRho[slot] : 1.f;
+        const unsigned wl = unsigned(w);
 
-        // --- per-lane right-hand side and initial state ------------------------
-        float bq[NV];
+        // --- per-lane right-hand side (in LDS) and initial state ---------------
+        const Strided<float> bq{sBq + lane, kWave};
+        {
+            float tw[6];
+#pragma unroll
+            for (int r = 0; r < 6; ++r) tw[r] = act ? a.wrench[size_t(wl) * 6 + r] : 0.f;
+#pragma unroll
+            for (int c = 0; c < NV; ++c) {
+                if (c % 3 == 0) BODEX_SPLIT();
+                float acc = 0.f;
+#pragma unroll
+                for (int r = 0; r < 6; ++r) acc = fmaf(Gs[r * NV + c], tw[r], acc);
+                bq[c] = 2.f * a.beta * acc;
+            }
+        }
         float wv[NR];
         float xv[NV];
-        float tw[6];
 #pragma unroll
-        for (int r = 0; r < 6; ++r) tw[r] = act ? a.wrench[size_t(w) * 6 + r] : 0.f;
-#pragma unroll
-        for (int c = 0; c < NV; ++c) {
-            if (c % 3 == 0) BODEX_SPLIT();
-            float acc = 0.f;
-#pragma unroll
-            for (int r = 0; r < 6; ++r) acc = fmaf(Gs[r * NV + c], tw[r], acc);
-            bq[c] = 2.f * a.beta * acc;
-            xv[c] = 0.f;
-        }
+        for (int c = 0; c < NV; ++c) xv[c] = 0.f;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             if (r % 9 == 0) BODEX_SPLIT();
             float v = 0.f;
             const int sr = state_row<MM>(r, a.ms);
             if (act && a.warm && sr >= 0) {
-                const float zr = a.z[size_t(sr) * a.W + w], yr = a.y[size_t(sr) * a.W + w];
+                const float zr = (a.z + size_t(sr) * a.W)[wl], yr = (a.y + size_t(sr) * a.W)[wl];
                 v = zr + yr / rho;
             }
             wv[r] = isfinite(v) ? v : 0.f;
@@ -398,6 +407,7 @@ __global__ void __launch_bounds__(64) admm_kernel(const KArgs a) {
 
         int it = 0;
         for (it = 1; it <= a.max_iters; ++it) {
+            BODEX_SPLIT();
             if (!done) {
                 float rhs[NV];
                 admm_rhs<MM>(wv, bq, muc, rho, a.fmax, a.gamma, m, rhs);
@@ -413,11 +423,12 @@ __global__ void __launch_bounds__(64) admm_kernel(const KArgs a) {
                     done = true;
                     stbits |= kStNonfinite;
                     it_done = it;
-                } else if (R.rel <= a.tol) {
+                } else if (R.rel <= a.admm_tol) {
                     done = true;
                     stbits |= kStConverged;
                     it_done = it;
                     rho_frz = rho;
+                    write_admm_x<MM>(a, wl, xv);
                 } else {
                     rpn = R.rp_n;
                     rdn = R.rd_n;
@@ -477,6 +488,7 @@ __global__ void __launch_bounds__(64) admm_kernel(const KArgs a) {
             stbits |= kStMaxIter;
             it_done = a.max_iters;
             rho_frz = rho;
+            write_admm_x<MM>(a, wl, xv);
         }
         if (act && (stbits & kStNonfinite)) {
 #pragma unroll
@@ -484,8 +496,9 @@ __global__ void __launch_bounds__(64) admm_kernel(const KArgs a) {
 #pragma unroll
             for (int r = 0; r < NR; ++r) wv[r] = NAN;
             rel_last = NAN;
+            write_admm_x<MM>(a, wl, xv);
         }
-        if (act) write_admm_state<MM>(a, w, xv, wv, rho_frz);
+        if (act) write_admm_zy<MM>(a, wl, wv, rho_frz);
         if (act) {
             a.iters[w] = it_done;
             a.status[w] = stbits;

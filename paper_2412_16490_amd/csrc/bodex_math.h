@@ -43,6 +43,14 @@ namespace bodex {
 constexpr double kC8 = 0.92387953251128673848;
 constexpr double kS8 = 0.38268343236508978178;
 
+// Lane-interleaved array in memory: element i at p[i * stride].
+template <typename T>
+struct Strided {
+    T* p;
+    int stride;
+    BODEX_FI T& operator[](int i) const { return p[i * stride]; }
+};
+
 template <int MM>
 struct Dims {
     static constexpr int NV = 3 * MM;             // variables
@@ -211,8 +219,8 @@ BODEX_FI T kkt_cond_bound(const T* G, const T* muc, int m, T rho, T eps) {
 // their G columns are zero and their block of K^{-1} is the identity, so every
 // row update leaves them at zero.  Only the normal-sum row couples contacts,
 // and it is masked to the real ones.
-template <int MM>
-BODEX_FI void admm_rhs(const float* w, const float* bq, const float* muc,
+template <int MM, typename BQ, typename MU>
+BODEX_FI void admm_rhs(const float* w, BQ bq, MU muc,
                        float rho, float fmax, float gamma, int m, float* rhs) {
     const float wg = w[9 * MM];
     const float vg = 2.f * fmaxf(wg, gamma) - wg;
@@ -239,13 +247,15 @@ BODEX_FI void admm_rhs(const float* w, const float* bq, const float* muc,
 }
 
 // x = K r with K symmetric, packed upper triangle (each off-diagonal entry is
-// read once and used twice).
+// read once and used twice).  The split every three rows bounds the loads of
+// K that are in flight (and held in registers) at any point.
 template <int N, typename KPtr>
 BODEX_FI void symv_packed(KPtr K, const float* r, float* x) {
 #pragma unroll
     for (int i = 0; i < N; ++i) x[i] = K[up_idx<N>(i, i)] * r[i];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
+        if (i % 3 == 2) BODEX_SPLIT();
 #pragma unroll
         for (int j = i + 1; j < N; ++j) {
             const float k = K[up_idx<N>(i, j)];
@@ -256,8 +266,8 @@ BODEX_FI void symv_packed(KPtr K, const float* r, float* x) {
 }
 
 // w <- w + alpha (A x - Pi(w)).
-template <int MM>
-BODEX_FI void admm_update(float* w, const float* x, const float* muc, float alpha,
+template <int MM, typename MU>
+BODEX_FI void admm_update(float* w, const float* x, MU muc, float alpha,
                           float fmax, float gamma, int m) {
     float s1 = 0.f;
 #pragma unroll
@@ -301,9 +311,9 @@ struct Residual {
 //   rel = max(r_p / (1 + max(||Ax||, ||z||)),
 //             r_d / (1 + max(||Px||, ||A^T y||, ||q||))).
 // P x is formed from G directly: 2 (G^T (G x) + eps x).
-template <int MM, typename GPtr>
-BODEX_FI Residual admm_residual(const float* w, const float* x, const float* bq,
-                                const float* muc, GPtr G, float rho, float eps,
+template <int MM, typename BQ, typename MU, typename GPtr>
+BODEX_FI Residual admm_residual(const float* w, const float* x, BQ bq,
+                                MU muc, GPtr G, float rho, float eps,
                                 float fmax, float gamma, int m) {
     constexpr int NV = 3 * MM;
     float rp = 0.f, nAx = 0.f, nz = 0.f;

@@ -71,6 +71,9 @@ struct bodex_qp {
     // stats of the last call
     int last_launches = 0, last_replays = 0, last_tiles = 0;
     size_t owned_bytes = 0;
+    // timing events: admm begin/end, finalize begin/end, backward begin/end
+    hipEvent_t tev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool t_admm = false, t_fin = false, t_bwd = false;
 };
 
 namespace {
@@ -220,8 +223,22 @@ uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
     return h;
 }
 
+void drop_graphs(bodex_qp* h) {
+    for (auto& g : h->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.d_desc) (void)hipFree(g.d_desc);
+        h->owned_bytes -= g.desc_ints * sizeof(int);
+    }
+    h->graphs.clear();
+}
+
 int ensure_device(bodex_qp* h, void** ptr, size_t* cap, size_t need) {
     if (*cap >= need) return 0;
+    // captured graphs hold the old pointers
+    if (!h->graphs.empty()) {
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        drop_graphs(h);
+    }
     size_t extra = need - *cap;
     if (h->owned_bytes + extra > h->budget)
         return fail(h, BODEX_EBUDGET, "workspace of %zu bytes exceeds the budget of %zu bytes",
@@ -241,8 +258,10 @@ int ensure_device(bodex_qp* h, void** ptr, size_t* cap, size_t need) {
 
 enum class Kind { Admm, Fin, Bwd };
 
-hipError_t launch(Kind k, int mm, const KArgs& a, int grid, size_t lds, hipStream_t st) {
-    if (k == Kind::Admm) return bodex::launch_admm(mm, a, grid, lds, st);
+constexpr int kDefaultAdmmWaves = 2;
+
+hipError_t launch(Kind k, int mm, const KArgs& a, int grid, size_t lds, hipStream_t st, int occ = 0) {
+    if (k == Kind::Admm) return bodex::launch_admm(mm, occ > 0 ? occ : kDefaultAdmmWaves, a, grid, lds, st);
     if (k == Kind::Fin) return bodex::launch_finalize(mm, a, grid, lds, st);
     return bodex::launch_backward(mm, a, grid, lds, st);
 }
@@ -269,6 +288,8 @@ int validate_params(const bodex_qp_params* p, bodex_qp* h) {
     if (!(p->rho_hysteresis >= 1.f)) return fail(h, BODEX_EINVAL, "rho_hysteresis must be >= 1");
     if (!(p->fp64_cond > 0.f)) return fail(h, BODEX_EINVAL, "fp64_cond must be positive");
     if (p->polish_steps < 0) return fail(h, BODEX_EINVAL, "polish_steps must be >= 0");
+    if (p->admm_waves < 0 || p->admm_waves > 4) return fail(h, BODEX_EINVAL, "admm_waves must be in [0, 4]");
+    if (!(p->admm_tol >= 0.f)) return fail(h, BODEX_EINVAL, "admm_tol must be >= 0");
     return 0;
 }
 
@@ -288,6 +309,8 @@ KArgs make_args(const bodex_qp* h, const bodex_batch* in) {
     a.fmax = p.force_max;
     a.gamma = p.gamma;
     a.tol = p.tol_rel;
+    // without the polish nothing lifts a QP past the ADMM tolerance
+    a.admm_tol = (p.admm_tol > 0.f && (p.flags & BODEX_F_POLISH)) ? p.admm_tol : p.tol_rel;
     a.rho0 = p.rho0;
     a.alpha = p.alpha;
     a.rho_min = p.rho_min;
@@ -400,6 +423,8 @@ void bodex_qp_default_params(bodex_qp_params* p) {
     p->polish_steps = 64;
     p->iters_per_chunk = 20;
     p->flags = BODEX_F_POLISH | BODEX_F_ADAPTIVE_RHO;
+    p->admm_waves = 0;
+    p->admm_tol = 0.0f;
 }
 
 int bodex_qp_create(const bodex_qp_params* p, int device, void* hip_stream, size_t hbm_budget_bytes,
@@ -493,41 +518,108 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
     a.status = out->status;
 
     const size_t n_ints = size_t(G) * 3 + 1 + S.n_tiles + 1 + 4;
-    rc = ensure_device(h, reinterpret_cast<void**>(&h->d_desc), &h->d_desc_cap, n_ints * sizeof(int));
-    if (rc) return rc;
-    size_t up = 0;
-    rc = upload_desc(h, in, S, h->d_desc, &up);
-    if (rc) return rc;
-    bind_desc(a, h->d_desc, G, S);
-    int* d_queue = h->d_desc + (n_ints - 4);
-
-    // ADMM
+    const bool timing = (h->prm.flags & BODEX_F_TIMING) != 0;
+    const bool graph = (h->prm.flags & BODEX_F_GRAPH) != 0 && h->stream != nullptr;
     const size_t lds_a = admm_lds(mm, S.slots);
-    int grid_a = S.n_tiles;
-    if (batched) {
-        a.queue = d_queue;
-        HIP_TRY(h, bodex::launch_reset(d_queue, 4, h->stream));
-        int per_cu = 0;
-        per_cu = std::max(1, std::min(16, int((160 * 1024) / std::max<size_t>(lds_a, 1))));
-        grid_a = occupancy_grid(h, per_cu, S.n_tiles);
-        h->last_launches++;
-    }
-    HIP_TRY(h, launch(Kind::Admm, mm, a, grid_a, lds_a, h->stream));
-    h->last_launches++;
-
-    // finalize (persistent over the tile queue; polish workspace per block)
     const size_t lds_f = fin_lds(mm, S.slots);
-    KArgs f = a;
-    f.queue = d_queue + 1;
-    HIP_TRY(h, bodex::launch_reset(d_queue + 1, 1, h->stream));
-    h->last_launches++;
+    int per_cu = std::max(1, std::min(16, int((160 * 1024) / std::max<size_t>(lds_a, 1))));
+    const int grid_a = batched ? occupancy_grid(h, per_cu, S.n_tiles) : S.n_tiles;
     const int grid_f = occupancy_grid(h, kFinBlocksPerCU, S.n_tiles);
     rc = ensure_device(h, reinterpret_cast<void**>(&h->d_gwork), &h->d_gwork_cap,
                        polish_work_bytes(mm, grid_f));
     if (rc) return rc;
-    f.gwork = h->d_gwork;
-    HIP_TRY(h, launch(Kind::Fin, mm, f, grid_f, lds_f, h->stream));
-    h->last_launches++;
+
+    // Enqueue the launch sequence (reset counters, ADMM, finalize) for the
+    // descriptors at d.
+    auto enqueue = [&](int* d, bool with_events) -> int {
+        bind_desc(a, d, G, S);
+        int* d_queue = d + (n_ints - 4);
+        HIP_TRY(h, bodex::launch_reset(d_queue, 4, h->stream));
+        KArgs aa = a;
+        aa.queue = batched ? d_queue : nullptr;
+        if (with_events) HIP_TRY(h, hipEventRecord(h->tev[0], h->stream));
+        HIP_TRY(h, launch(Kind::Admm, mm, aa, grid_a, lds_a, h->stream, h->prm.admm_waves));
+        if (with_events) HIP_TRY(h, hipEventRecord(h->tev[1], h->stream));
+        KArgs f = a;
+        f.queue = d_queue + 1;
+        f.gwork = h->d_gwork;
+        if (with_events) HIP_TRY(h, hipEventRecord(h->tev[2], h->stream));
+        HIP_TRY(h, launch(Kind::Fin, mm, f, grid_f, lds_f, h->stream));
+        if (with_events) HIP_TRY(h, hipEventRecord(h->tev[3], h->stream));
+        return 0;
+    };
+
+    if (timing && !h->tev[0]) {
+        for (auto& e : h->tev) HIP_TRY(h, hipEventCreate(&e));
+    }
+    h->t_admm = h->t_fin = false;
+
+    if (!graph) {
+        rc = ensure_device(h, reinterpret_cast<void**>(&h->d_desc), &h->d_desc_cap, n_ints * sizeof(int));
+        if (rc) return rc;
+        size_t up = 0;
+        rc = upload_desc(h, in, S, h->d_desc, &up);
+        if (rc) return rc;
+        rc = enqueue(h->d_desc, timing);
+        if (rc) return rc;
+        h->last_launches = 3;
+        h->t_admm = h->t_fin = timing;
+        return 0;
+    }
+
+    // Graph path: key on everything the captured launches depend on.
+    uint64_t key = 1469598103934665603ull;
+    key = fnv1a(key, &G, sizeof(G));
+    key = fnv1a(key, in->contact_count, sizeof(int) * G);
+    key = fnv1a(key, in->wrench_offset, sizeof(int) * (G + 1));
+    key = fnv1a(key, &a, sizeof(a));
+    key = fnv1a(key, &h->prm, sizeof(h->prm));
+    GraphEntry* hit = nullptr;
+    for (auto& g : h->graphs)
+        if (g.key == key) hit = &g;
+    if (!hit) {
+        if (h->graphs.size() >= 8) {
+            auto oldest = std::min_element(h->graphs.begin(), h->graphs.end(),
+                                           [](const GraphEntry& x, const GraphEntry& y) { return x.stamp < y.stamp; });
+            HIP_TRY(h, hipStreamSynchronize(h->stream));
+            if (oldest->exec) HIP_TRY(h, hipGraphExecDestroy(oldest->exec));
+            if (oldest->d_desc) HIP_TRY(h, hipFree(oldest->d_desc));
+            h->owned_bytes -= oldest->desc_ints * sizeof(int);
+            h->graphs.erase(oldest);
+        }
+        GraphEntry e;
+        e.key = key;
+        e.desc_ints = n_ints;
+        if (h->owned_bytes + n_ints * sizeof(int) > h->budget)
+            return fail(h, BODEX_EBUDGET, "graph descriptors exceed the budget");
+        HIP_TRY(h, hipMalloc(reinterpret_cast<void**>(&e.d_desc), n_ints * sizeof(int)));
+        h->owned_bytes += n_ints * sizeof(int);
+        size_t up = 0;
+        rc = upload_desc(h, in, S, e.d_desc, &up);
+        if (rc) {
+            (void)hipFree(e.d_desc);
+            return rc;
+        }
+        hipGraph_t gr = nullptr;
+        HIP_TRY(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        rc = enqueue(e.d_desc, false);
+        hipError_t ce = hipStreamEndCapture(h->stream, &gr);
+        if (rc) return rc;
+        if (ce != hipSuccess) return hip_fail(h, ce, "hipStreamEndCapture");
+        ce = hipGraphInstantiate(&e.exec, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (ce != hipSuccess) return hip_fail(h, ce, "hipGraphInstantiate");
+        h->graphs.push_back(e);
+        hit = &h->graphs.back();
+    } else {
+        h->last_replays = 1;
+    }
+    hit->stamp = ++h->graph_clock;
+    if (timing) HIP_TRY(h, hipEventRecord(h->tev[0], h->stream));
+    HIP_TRY(h, hipGraphLaunch(hit->exec, h->stream));
+    if (timing) HIP_TRY(h, hipEventRecord(h->tev[1], h->stream));
+    h->t_admm = timing;
+    h->last_launches = 1;
     return 0;
 }
 
@@ -571,8 +663,15 @@ int bodex_qp_backward(bodex_qp_t* h, const bodex_batch* in, const bodex_state* s
                        polish_work_bytes(mm, grid_b));
     if (rc) return rc;
     a.gwork = h->d_gwork;
+    const bool timing = (h->prm.flags & BODEX_F_TIMING) != 0;
+    if (timing && !h->tev[0]) {
+        for (auto& e : h->tev) HIP_TRY(h, hipEventCreate(&e));
+    }
+    if (timing) HIP_TRY(h, hipEventRecord(h->tev[4], h->stream));
     HIP_TRY(h, launch(Kind::Bwd, mm, a, grid_b, lds_b, h->stream));
-    h->last_launches = 1;
+    if (timing) HIP_TRY(h, hipEventRecord(h->tev[5], h->stream));
+    h->t_bwd = timing;
+    h->last_launches = 2;
     return 0;
 }
 
@@ -591,6 +690,8 @@ int bodex_qp_destroy(bodex_qp_t* h) {
     if (h->d_gwork) (void)hipFree(h->d_gwork);
     if (h->h_desc) (void)hipHostFree(h->h_desc);
     if (h->desc_ev) (void)hipEventDestroy(h->desc_ev);
+    for (auto& e : h->tev)
+        if (e) (void)hipEventDestroy(e);
     delete h;
     return 0;
 }
@@ -603,6 +704,22 @@ size_t bodex_qp_state_bytes(int n_grasps, int n_qps, int m_max) {
     if (n_grasps < 0 || n_qps < 0 || m_max < 1) return 0;
     const size_t nv = 3 * size_t(m_max), nr = 9 * size_t(m_max) + 1;
     return (size_t(n_qps) * (nv + 2 * nr) + size_t(n_grasps)) * sizeof(float);
+}
+
+int bodex_qp_kernel_times(bodex_qp_t* h, float* admm_ms, float* finalize_ms, float* backward_ms) {
+    if (!h) return BODEX_EINVAL;
+    auto span = [&](bool valid, int i0, float* out) -> int {
+        if (!out) return 0;
+        *out = -1.f;
+        if (!valid) return 0;
+        HIP_TRY(h, hipEventSynchronize(h->tev[i0 + 1]));
+        HIP_TRY(h, hipEventElapsedTime(out, h->tev[i0], h->tev[i0 + 1]));
+        return 0;
+    };
+    int rc = span(h->t_admm, 0, admm_ms);
+    if (!rc) rc = span(h->t_fin, 2, finalize_ms);
+    if (!rc) rc = span(h->t_bwd, 4, backward_ms);
+    return rc;
 }
 
 int bodex_qp_last_stats(bodex_qp_t* h, int* launches, int* graph_replays, int* tiles) {

@@ -10,16 +10,27 @@ __global__ void reset_counter_kernel(int* q, int n) {
     if (int(threadIdx.x) < n) q[threadIdx.x] = 0;
 }
 
-hipError_t launch_admm(int mm, const KArgs& a, int grid, size_t lds, hipStream_t st) {
-    switch (mm) {
-        case 4: hipLaunchKernelGGL(admm_kernel<4>, dim3(grid), dim3(64), lds, st, a); break;
-        case 5: hipLaunchKernelGGL(admm_kernel<5>, dim3(grid), dim3(64), lds, st, a); break;
-#ifdef BODEX_WITH_MM8
-        case 8: hipLaunchKernelGGL(admm_kernel<8>, dim3(grid), dim3(64), lds, st, a); break;
-#endif
+template <int MM>
+static hipError_t launch_admm_mm(int occ, const KArgs& a, int grid, size_t lds, hipStream_t st) {
+    switch (occ) {
+        case 1: hipLaunchKernelGGL((admm_kernel<MM, 1>), dim3(grid), dim3(64), lds, st, a); break;
+        case 2: hipLaunchKernelGGL((admm_kernel<MM, 2>), dim3(grid), dim3(64), lds, st, a); break;
+        case 3: hipLaunchKernelGGL((admm_kernel<MM, 3>), dim3(grid), dim3(64), lds, st, a); break;
+        case 4: hipLaunchKernelGGL((admm_kernel<MM, 4>), dim3(grid), dim3(64), lds, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_admm(int mm, int occ, const KArgs& a, int grid, size_t lds, hipStream_t st) {
+    switch (mm) {
+        case 4: return launch_admm_mm<4>(occ, a, grid, lds, st);
+        case 5: return launch_admm_mm<5>(occ, a, grid, lds, st);
+#ifdef BODEX_WITH_MM8
+        case 8: return launch_admm_mm<8>(occ, a, grid, lds, st);
+#endif
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_reset(int* q, int n, hipStream_t st) {

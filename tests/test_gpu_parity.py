@@ -96,3 +96,48 @@ def test_small_contact_counts_in_m5_layout():
     ref = _ref(b)
     check_forward(b, gpu, ref)
     check_energy(b, gpu, ref)
+
+
+def test_graph_replay_matches_direct_launch():
+    # capture on a side stream, replay several times with eager work between,
+    # and compare every replay with a direct launch
+    import torch
+    b = wl.config(3, 500)
+    s_max = int(np.max(np.diff(b.woff)))
+    db = api.DeviceBatch(b)
+    direct = run_gpu(b, flags=api.default_params().flags | api.F_BATCHED)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        p = api.default_params(m_max=5, s_max=s_max)
+        p.flags |= api.F_BATCHED | api.F_GRAPH
+        s = api.Solver(p, stream=side.cuda_stream)
+        st = api.new_state(db.n_grasps, db.n_qps, 5)
+        r = api.new_result(db.n_grasps, db.n_qps, 5)       # same buffers every call
+        replays = 0
+        for rep in range(4):
+            s.solve(db, state=st, result=r)
+            replays += s.stats()["graph_replays"]
+            junk = torch.randn(1000, device="cuda").sum()   # eager work in between
+            side.synchronize()
+            assert torch.isfinite(junk)
+            np.testing.assert_array_equal(r["forces"].cpu().numpy(), direct["forces"])
+            np.testing.assert_array_equal(r["qp_obj"].cpu().numpy(), direct["qp_obj"])
+            np.testing.assert_array_equal(r["energy"].cpu().numpy(), direct["energy"])
+            np.testing.assert_array_equal(r["status"].cpu().numpy(), direct["status"])
+        assert replays == 3
+        s.close()
+
+
+def test_kernel_timing_flag():
+    import torch
+    b = wl.config(1, 64)
+    p = api.default_params(m_max=5, s_max=16)
+    p.flags |= api.F_TIMING
+    s = api.Solver(p)
+    db = api.DeviceBatch(b)
+    st = api.new_state(db.n_grasps, db.n_qps, 5)
+    s.solve(db, state=st)
+    s.backward(db, st, dL_dE=torch.ones(db.n_grasps, device="cuda"))
+    kt = s.kernel_times()
+    assert kt["admm_ms"] > 0 and kt["finalize_ms"] > 0 and kt["backward_ms"] > 0
+    s.close()
