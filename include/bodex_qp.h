@@ -78,7 +78,7 @@ extern "C" {
 #define BODEX_F_TIMING 0x20       /* record HIP events around each kernel      */
 
 typedef struct {
-    int m_max;            /* contacts per grasp, 1..8 (array padding)        */
+    int m_max;            /* contacts per grasp, 1..5 (array padding)        */
     int s_max;            /* wrenches per grasp, 1..64                        */
     float force_max;      /* fmax, upper bound of f_i1 (Eq. 1: 1.0)           */
     float gamma;          /* lower bound of sum_i f_i1 (Eq. 9); 0 = unused    */
@@ -141,14 +141,15 @@ typedef struct bodex_qp bodex_qp_t;
 
 /* Fill *p with the defaults: m_max 5, s_max 32, fmax 1, gamma 0, beta 1,
  * eps 1e-6, torque_scale 20, tol 1e-5, 500 iterations, rho0 0.1, alpha 1.6,
- * check every 10, rho in [1e-4, 1e4], hysteresis 5, fp64_cond 1e4, 64 polish
+ * check every 10, rho in [1e-4, 1e4], hysteresis 5, fp64_cond 1e4, 128 polish
  * steps, 20 iterations per chunk, flags POLISH | ADAPTIVE_RHO, admm_waves 0,
  * admm_tol 0 (ADMM runs to tol_rel). */
 void bodex_qp_default_params(bodex_qp_params *p);
 
 /* Create a handle on `device` that enqueues on `hip_stream` (a hipStream_t;
  * NULL = the default stream).  hbm_budget_bytes caps the library-owned
- * workspace (0 = 4 GiB).  Errors: EINVAL (bad params), ENODEV, EHIP. */
+ * workspace (0 = 4 GiB).  Errors: EINVAL (bad params), EUNSUP (m_max above
+ * the contact counts the kernels are compiled for: 4 and 5), ENODEV, EHIP. */
 int bodex_qp_create(const bodex_qp_params *p, int device, void *hip_stream,
                     size_t hbm_budget_bytes, bodex_qp_t **out);
 

@@ -1,7 +1,7 @@
 """Build the HIP library in-tree: paper_2412_16490_amd/libbodex_qp.so (gfx950).
 
 Each kernel family is its own translation unit so the units compile in
-parallel; the host part of the C ABI is a fifth unit.
+parallel; the host part of the C ABI is one more unit.
 """
 from __future__ import annotations
 
@@ -13,7 +13,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-UNITS = ["bodex_qp.hip", "k_admm.hip", "k_finalize.hip", "k_backward.hip"]
+UNITS = ["bodex_qp.hip", "k_admm.hip", "k_finalize.hip", "k_finalize_sum.hip", "k_backward.hip",
+         "k_backward_sum.hip"]
 LIB = os.path.join(HERE, "libbodex_qp.so")
 OBJDIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -68,8 +68,6 @@ struct KArgs {
     float* dP;
     float* dN;
     int accumulate;
-    // polish workspace, NK doubles per lane, one 64-lane region per block
-    double* gwork;
     // parameters
     float kappa, beta, eps, fmax, gamma, tol, admm_tol, rho0, alpha, rho_min, rho_max, hyst, fp64_cond;
     int max_iters, check_every, warm, adaptive, polish, polish_steps;
@@ -509,55 +507,71 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) 
 }
 
 // ---------------------------------------------------------------------------
-// Shared FP64 setup of the finalize and backward kernels: grasp matrix and
-// P^{-1} per slot.
+// Shared FP64 setup of the finalize and backward kernels: per slot the grasp
+// matrix G and mu_i cos(pi/8).
 // ---------------------------------------------------------------------------
 template <int MM>
 struct FinLds {
-    static constexpr int NV = 3 * MM, NK = NV * (NV + 1) / 2, NG = 6 * NV;
-    // per slot: G64, Pinv, Lw, muc64(8), Gbar (backward); per lane: the
-    // energy / gradient reduction 6 + NV + 1.  The per-lane polish workspace
-    // lives in global memory (KArgs::gwork).
-    static __host__ __device__ size_t bytes(int slots) {
-        return size_t(slots) * (NG + NK + NK + 8 + NG) * 8 + size_t(64) * (6 + NV + 1) * 8 +
+    static constexpr int NV = 3 * MM, NG = 6 * NV, NW = 3 * NV * kWave;
+    // per slot: G64, muc64 (8); per lane (lane-interleaved): the polish's x,
+    // z and multipliers; finalize: the energy reduction (one per lane);
+    // backward: Gbar per slot, and the gradient reduction 6 + NV per lane,
+    // which reuses the polish space once every lane has finished it.
+    static __host__ __device__ size_t bytes(int slots, bool bwd) {
+        return size_t(slots) * (NG + 8) * 8 + size_t(NW) * 8 + (bwd ? size_t(slots) * NG * 8 : 64 * 8) +
                kMaxSlots * 32 + 64;
     }
 };
 
 template <int MM>
 struct FinPtrs {
-    double *G, *Pinv, *Lw, *muc, *Gbar, *work, *red;
+    double *G, *muc, *work, *Gbar, *red;
     SlotInfo* info;
     int* flag;
 };
 
 template <int MM>
-__device__ inline FinPtrs<MM> fin_carve(unsigned char* smem, int S) {
-    constexpr int NV = 3 * MM, NK = NV * (NV + 1) / 2, NG = 6 * NV;
+__device__ inline FinPtrs<MM> fin_carve(unsigned char* smem, int S, bool bwd) {
+    constexpr int NG = FinLds<MM>::NG, NW = FinLds<MM>::NW;
+    static_assert(kWave * (6 + 3 * MM) <= NW, "reduction buffer must fit in the polish space");
     FinPtrs<MM> P;
     double* d = reinterpret_cast<double*>(smem);
     P.G = d;
     d += size_t(S) * NG;
-    P.Pinv = d;
-    d += size_t(S) * NK;
-    P.Lw = d;
-    d += size_t(S) * NK;
     P.muc = d;
     d += size_t(S) * 8;
-    P.Gbar = d;
-    d += size_t(S) * NG;
-    P.work = nullptr;
-    P.red = d;
-    d += size_t(64) * (6 + NV + 1);
+    P.work = d;
+    d += NW;
+    if (bwd) {
+        P.Gbar = d;
+        d += size_t(S) * NG;
+        P.red = P.work;
+    } else {
+        P.Gbar = nullptr;
+        P.red = d;
+        d += 64;
+    }
     P.info = reinterpret_cast<SlotInfo*>(d);
     P.flag = reinterpret_cast<int*>(P.info + kMaxSlots);
     return P;
 }
 
+// This lane's polish vectors in the shared polish space.
 template <int MM>
-__device__ inline bool fin_setup(const KArgs& a, const FinPtrs<MM>& P, double* work, int nsl, int slot,
-                                 int j, const SlotInfo& si) {
-    constexpr int NV = 3 * MM, NK = NV * (NV + 1) / 2, NG = 6 * NV;
+__device__ inline PolishWork polish_work(const FinPtrs<MM>& P, int lane) {
+    constexpr int NV = 3 * MM;
+    PolishWork W;
+    W.x = LaneVec{P.work + lane, kWave};
+    W.z = LaneVec{P.work + NV * kWave + lane, kWave};
+    W.lam = LaneVec{P.work + 2 * NV * kWave + lane, kWave};
+    return W;
+}
+
+// Returns whether the lane's grasp has finite, valid inputs.
+template <int MM>
+__device__ inline bool fin_setup(const KArgs& a, const FinPtrs<MM>& P, int nsl, int slot, int j,
+                                 const SlotInfo& si) {
+    constexpr int NV = 3 * MM, NG = 6 * NV;
     const int lane = threadIdx.x;
     const bool act = slot >= 0;
     for (int e = lane; e < nsl * NG; e += kWave) P.G[e] = 0.0;
@@ -576,16 +590,10 @@ __device__ inline bool fin_setup(const KArgs& a, const FinPtrs<MM>& P, double* w
         }
     }
     __syncthreads();
-    const bool bad = act && (P.flag[slot] & 4);
-    const double* Gs = P.G + size_t(act ? slot : 0) * NG;
-    const double eps = a.eps;
-    const bool ok = coop_inverse<double, NV>(act && !bad, j, si.s, P.Lw + size_t(act ? slot : 0) * NK,
-                                             P.Pinv + size_t(act ? slot : 0) * NK, work,
-                                             [&](int i, int c) { return hess_entry<double, NV>(Gs, eps, i, c); });
-    return act && !bad && ok;
+    return act && !(P.flag[slot] & 4);
 }
 
-// Lane-strided accessor for a per-lane workspace in LDS.
+// Lane-strided accessor for the ADMM-form duals in global memory.
 template <int MM>
 struct StridedY {
     const float* base;
@@ -597,15 +605,36 @@ struct StridedY {
     }
 };
 
+template <int MM, bool GAM>
+using LdsPolishData = PolishData<MM, const double*, GAM>;
+
+template <int MM, bool GAM>
+__device__ inline LdsPolishData<MM, GAM> polish_data(const KArgs& a, const FinPtrs<MM>& P, int slot,
+                                                     const SlotInfo& si, const double* bt) {
+    constexpr int NG = 6 * 3 * MM;
+    LdsPolishData<MM, GAM> D;
+    D.G = P.G + size_t(slot) * NG;
+    D.muc = P.muc + slot * 8;
+#pragma unroll
+    for (int r = 0; r < 6; ++r) D.bt[r] = bt[r];
+    D.m = si.m;
+    D.fmax = a.fmax;
+    D.gamma = a.gamma;
+    D.eps = a.eps;
+    return D;
+}
+
 // ---------------------------------------------------------------------------
-// Finalize kernel: polish, objective, energy, KKT residual, outputs.
+// Finalize kernel: polish, objective, energy, KKT residual, outputs.  GAM:
+// the polish handles the normal-sum row (gamma > 0).
 // ---------------------------------------------------------------------------
-template <int MM>
+template <int MM, bool GAM>
 __global__ void __launch_bounds__(64) finalize_kernel(const KArgs a) {
-    constexpr int NV = 3 * MM, NR = 9 * MM + 1, NK = NV * (NV + 1) / 2, NG = 6 * NV;
+    constexpr int NG = 6 * 3 * MM;
     extern __shared__ __align__(16) unsigned char smem[];
-    const FinPtrs<MM> P = fin_carve<MM>(smem, a.slots);
+    const FinPtrs<MM> P = fin_carve<MM>(smem, a.slots, false);
     const int lane = threadIdx.x;
+    const PolishWork W = polish_work<MM>(P, lane);
     __shared__ int sTile;
     for (int t = fetch_tile(a, &sTile, -1); t < a.n_tiles; t = fetch_tile(a, &sTile, t)) {
         int nsl;
@@ -615,132 +644,97 @@ __global__ void __launch_bounds__(64) finalize_kernel(const KArgs a) {
         const bool act = slot >= 0;
         SlotInfo si = {0, 0, 1, 0};
         if (act) si = P.info[slot];
-        double* work = a.gwork + size_t(blockIdx.x) * kWave * NK + lane;
-        const bool good = fin_setup<MM>(a, P, work, nsl, slot, j, si);
+        const bool good = fin_setup<MM>(a, P, nsl, slot, j, si);
         const int w = si.w0 + j;
         double Q = 0.0;
         if (act) {
             const double* Gs = P.G + size_t(slot) * NG;
-            const double* Pinv = P.Pinv + size_t(slot) * NK;
-            double muc[MM];
+            const double* muc = P.muc + slot * 8;
+            const size_t W_ = size_t(a.W);
+            double bt[6];
 #pragma unroll
-            for (int i = 0; i < MM; ++i) muc[i] = P.muc[slot * 8 + i];
-            double q[NV];
-            double tw[6];
-#pragma unroll
-            for (int r = 0; r < 6; ++r) tw[r] = a.wrench[size_t(w) * 6 + r];
-#pragma unroll
-            for (int c = 0; c < NV; ++c) {
-                double acc = 0.0;
-#pragma unroll
-                for (int r = 0; r < 6; ++r) acc += Gs[r * NV + c] * tw[r];
-                q[c] = -2.0 * double(a.beta) * acc;
-            }
+            for (int r = 0; r < 6; ++r) bt[r] = double(a.beta) * double(a.wrench[size_t(w) * 6 + r]);
             unsigned char st = a.status[w];
-            float xs[NV], zs[NR], ys[NR];
-#pragma unroll
-            for (int c = 0; c < NV; ++c) xs[c] = (c < 3 * a.ms) ? a.x[size_t(c) * a.W + w] : 0.f;
-#pragma unroll
-            for (int r = 0; r < NR; ++r) {
-                const int sr = state_row<MM>(r, a.ms);
-                zs[r] = sr >= 0 ? a.z[size_t(sr) * a.W + w] : 0.f;
-                ys[r] = sr >= 0 ? a.y[size_t(sr) * a.W + w] : 0.f;
-            }
-            double xf[NV];
-#pragma unroll
-            for (int c = 0; c < NV; ++c) xf[c] = xs[c];
+            bool polished = false;
             const bool finite_in = good && !(st & kStNonfinite);
             if (finite_in && a.polish) {
-                PolishCtx<MM> X;
-                X.m = si.m;
-                X.fmax = a.fmax;
-                X.gamma = a.gamma;
-                X.eps = a.eps;
-                X.beta = a.beta;
-                X.muc = P.muc + slot * 8;
-                double xp[NV], lam[NV];
-                int actr[NV], k = 0;
-                const StridedY<MM> y0{a.y + w, size_t(a.W), a.ms};
-                const PolishOut po = polish_qp<MM>(X, y0, Gs, Pinv, q, work, kWave,
-                                                   a.polish_steps, xp, lam, actr, &k);
+                const LdsPolishData<MM, GAM> D = polish_data<MM, GAM>(a, P, slot, si, bt);
+                double lg = 0.0;
+                ActiveSet S;
+                const StridedY<MM> y0{a.y + w, W_, a.ms};
+                const PolishOut po = polish_qp<MM>(D, y0, a.polish_steps, W, S, &lg);
                 if (po.status == 0) {
+                    polished = true;
                     st |= kStPolished;
                     st &= ~kStPolishRej;
-#pragma unroll
-                    for (int c = 0; c < NV; ++c) {
-                        xf[c] = xp[c];
-                        xs[c] = float(xp[c]);
-                    }
                     // ADMM-form state of the polished point: z = A x projected
-                    // on [l, u], y = multipliers of the active rows.
+                    // on [l, u] (the bound itself on active rows), y = the
+                    // multipliers of the active rows
                     double s1 = 0.0;
+#pragma unroll 1
+                    for (int i = 0; i < a.ms; ++i) {
+                        const bool live = i < si.m;
+                        const double f[3] = {live ? W.x[3 * i] : 0.0, live ? W.x[3 * i + 1] : 0.0,
+                                             live ? W.x[3 * i + 2] : 0.0};
+                        const unsigned mk = live ? contact_mask(S.mask, i) : 0u;
 #pragma unroll
-                    for (int i = 0; i < MM; ++i) {
+                        for (int c = 0; c < 3; ++c) a.x[size_t(3 * i + c) * W_ + w] = float(f[c]);
 #pragma unroll
                         for (int kk = 0; kk < 9; ++kk) {
-                            double zz = 0.0;
-                            if (i < si.m) {
-                                if (kk < 8)
-                                    zz = facet_cos<double>(kk) * xp[3 * i + 1] +
-                                         facet_sin<double>(kk) * xp[3 * i + 2] - muc[i] * xp[3 * i];
-                                else
-                                    zz = xp[3 * i];
-                            }
-                            zs[9 * i + kk] = row_proj(9 * i + kk, MM, float(zz), a.fmax, a.gamma);
-                            ys[9 * i + kk] = 0.f;
+                            const double zz = (kk < 8) ? facet_cos<double>(kk) * f[1] + facet_sin<double>(kk) * f[2] -
+                                                             muc[i] * f[0]
+                                                       : f[0];
+                            const bool on = (mk >> kk) & 1u;
+                            const int jr = __builtin_popcount(mk & ((1u << kk) - 1u));
+                            const float zv = on ? (kk == 8 ? a.fmax : 0.f)
+                                                : row_proj(9 * i + kk, MM, float(zz), a.fmax, a.gamma);
+                            const float yv = on ? float(W.lam[3 * i + jr]) : 0.f;
+                            a.z[size_t(9 * i + kk) * W_ + w] = zv;
+                            a.y[size_t(9 * i + kk) * W_ + w] = yv;
                         }
-                        if (i < si.m) s1 += xp[3 * i];
+                        s1 += f[0];
                     }
-                    zs[9 * MM] = fmaxf(float(s1), a.gamma);
-                    ys[9 * MM] = 0.f;
-#pragma unroll
-                    for (int jj = 0; jj < NV; ++jj) {
-                        if (jj < k) {
-                            const int r = actr[jj];
-#pragma unroll
-                            for (int rr = 0; rr < NR; ++rr) {
-                                if (rr == r) {
-                                    if (r == 9 * MM) {
-                                        ys[rr] = float(-lam[jj]);
-                                        zs[rr] = a.gamma;
-                                    } else {
-                                        ys[rr] = float(lam[jj]);
-                                        zs[rr] = (r % 9 == 8) ? a.fmax : 0.f;
-                                    }
-                                }
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int c = 0; c < NV; ++c)
-                        if (c < 3 * a.ms) a.x[size_t(c) * a.W + w] = xs[c];
-#pragma unroll
-                    for (int r = 0; r < NR; ++r) {
-                        const int sr = state_row<MM>(r, a.ms);
-                        if (sr >= 0) {
-                            a.z[size_t(sr) * a.W + w] = zs[r];
-                            a.y[size_t(sr) * a.W + w] = ys[r];
-                        }
-                    }
+                    const bool gam = GAM && S.gam;
+                    a.z[size_t(9 * a.ms) * W_ + w] = gam ? a.gamma : fmaxf(float(s1), a.gamma);
+                    a.y[size_t(9 * a.ms) * W_ + w] = gam ? float(-lg) : 0.f;
                 } else {
                     st |= kStPolishRej;
                     st &= ~kStPolished;
                 }
             }
-            // objective from the returned forces (FP64)
-            double rr2 = 0.0, ff = 0.0;
+            // objective and forces from the returned point (FP64: the polished
+            // point, else the ADMM iterate)
+            auto xval = [&](int c) -> double {
+                return polished ? (c < 3 * si.m ? W.x[c] : 0.0) : double(a.x[size_t(c) * W_ + w]);
+            };
+            double r6[6];
 #pragma unroll
-            for (int r = 0; r < 6; ++r) {
-                double v = -double(a.beta) * tw[r];
+            for (int k = 0; k < 6; ++k) r6[k] = -bt[k];
+            double ff = 0.0;
+#pragma unroll 1
+            for (int c = 0; c < 3 * a.ms; ++c) {
+                const double xc = xval(c);
+                if (c < 3 * si.m) {
 #pragma unroll
-                for (int c = 0; c < NV; ++c) v += Gs[r * NV + c] * xf[c];
-                rr2 += v * v;
+                    for (int k = 0; k < 6; ++k) r6[k] += Gs[k * 3 * MM + c] * xc;
+                }
+                ff += xc * xc;
+                a.forces[size_t(w) * 3 * a.ms + c] = finite_in ? float(xc) : NAN;
             }
+            double rr2 = 0.0;
 #pragma unroll
-            for (int c = 0; c < NV; ++c) ff += xf[c] * xf[c];
+            for (int k = 0; k < 6; ++k) rr2 += r6[k] * r6[k];
             Q = rr2 + double(a.eps) * ff;
             double rel = NAN;
-            if (finite_in) rel = rel_kkt64<MM>(Gs, muc, q, si.m, double(a.eps), xs, zs, ys);
+            if (finite_in) {
+                const float* xs = a.x + w;
+                const float* zs = a.z + w;
+                const float* ys = a.y + w;
+                rel = rel_kkt64<MM>(
+                    Gs, muc, bt, si.m, double(a.eps), [&](int c) { return double(xs[size_t(c) * W_]); },
+                    [&](int r) { return double(zs[size_t(r) * W_]); }, [&](int r) { return double(ys[size_t(r) * W_]); },
+                    double(zs[size_t(9 * a.ms) * W_]), double(ys[size_t(9 * a.ms) * W_]));
+            }
             if (rel <= double(a.tol))
                 st |= kStConverged;
             else
@@ -752,9 +746,6 @@ __global__ void __launch_bounds__(64) finalize_kernel(const KArgs a) {
             a.status[w] = st;
             a.kkt[w] = float(rel);
             a.qobj[w] = float(Q);
-#pragma unroll
-            for (int c = 0; c < NV; ++c)
-                if (c < 3 * a.ms) a.forces[size_t(w) * 3 * a.ms + c] = finite_in ? float(xf[c]) : NAN;
         }
         P.red[lane] = Q;
         __syncthreads();
@@ -770,12 +761,13 @@ __global__ void __launch_bounds__(64) finalize_kernel(const KArgs a) {
 // ---------------------------------------------------------------------------
 // Backward kernel.
 // ---------------------------------------------------------------------------
-template <int MM>
+template <int MM, bool GAM>
 __global__ void __launch_bounds__(64) backward_kernel(const KArgs a) {
-    constexpr int NV = 3 * MM, NR = 9 * MM + 1, NK = NV * (NV + 1) / 2, NG = 6 * NV;
+    constexpr int NV = 3 * MM, NG = 6 * NV;
     extern __shared__ __align__(16) unsigned char smem[];
-    const FinPtrs<MM> P = fin_carve<MM>(smem, a.slots);
+    const FinPtrs<MM> P = fin_carve<MM>(smem, a.slots, true);
     const int lane = threadIdx.x;
+    const PolishWork W = polish_work<MM>(P, lane);
     __shared__ int sTile;
     for (int t = fetch_tile(a, &sTile, -1); t < a.n_tiles; t = fetch_tile(a, &sTile, t)) {
         int nsl;
@@ -785,50 +777,37 @@ __global__ void __launch_bounds__(64) backward_kernel(const KArgs a) {
         const bool act = slot >= 0;
         SlotInfo si = {0, 0, 1, 0};
         if (act) si = P.info[slot];
-        double* work = a.gwork + size_t(blockIdx.x) * kWave * NK + lane;
-        const bool good = fin_setup<MM>(a, P, work, nsl, slot, j, si);
+        const bool good = fin_setup<MM>(a, P, nsl, slot, j, si);
         const int w = si.w0 + j;
-        double* rw = P.red + size_t(lane) * (6 + NV);  // 2 * omega * r (6), f (NV)
+        double f[NV], tw[6], om = 0.0;
 #pragma unroll
-        for (int e = 0; e < 6 + NV; ++e) rw[e] = 0.0;
+        for (int c = 0; c < NV; ++c) f[c] = 0.0;
+#pragma unroll
+        for (int r = 0; r < 6; ++r) tw[r] = 0.0;
         if (act && good) {
-            const double* Gs = P.G + size_t(slot) * NG;
-            const double* Pinv = P.Pinv + size_t(slot) * NK;
-            double muc[MM];
-#pragma unroll
-            for (int i = 0; i < MM; ++i) muc[i] = P.muc[slot * 8 + i];
-            double tw[6], q[NV];
 #pragma unroll
             for (int r = 0; r < 6; ++r) tw[r] = a.wrench[size_t(w) * 6 + r];
 #pragma unroll
-            for (int c = 0; c < NV; ++c) {
-                double acc = 0.0;
-#pragma unroll
-                for (int r = 0; r < 6; ++r) acc += Gs[r * NV + c] * tw[r];
-                q[c] = -2.0 * double(a.beta) * acc;
-            }
-            double f[NV];
-#pragma unroll
             for (int c = 0; c < NV; ++c) f[c] = (c < 3 * a.ms) ? a.x[size_t(c) * a.W + w] : 0.0;
-            PolishCtx<MM> X;
-            X.m = si.m;
-            X.fmax = a.fmax;
-            X.gamma = a.gamma;
-            X.eps = a.eps;
-            X.beta = a.beta;
-            X.muc = P.muc + slot * 8;
-            double xp[NV], lam[NV];
-            int actr[NV], k = 0;
+            double bt[6];
+#pragma unroll
+            for (int r = 0; r < 6; ++r) bt[r] = double(a.beta) * tw[r];
+            const LdsPolishData<MM, GAM> D = polish_data<MM, GAM>(a, P, slot, si, bt);
+            double lg = 0.0;
+            ActiveSet S;
             const StridedY<MM> y0{a.y + w, size_t(a.W), a.ms};
-            const PolishOut po = polish_qp<MM>(X, y0, Gs, Pinv, q, work, kWave,
-                                               a.polish_steps, xp, lam, actr, &k);
+            const PolishOut po = polish_qp<MM>(D, y0, a.polish_steps, W, S, &lg);
             if (po.status == 0) {
 #pragma unroll
-                for (int c = 0; c < NV; ++c) f[c] = xp[c];
+                for (int c = 0; c < NV; ++c) f[c] = (c < 3 * si.m) ? W.x[c] : 0.0;
             }
-            double om = 0.0;
             if (a.dLdQ) om += a.dLdQ[w];
             if (a.dLdE) om += a.dLdE[si.g];
+        }
+        __syncthreads();  // the polish space becomes the reduction buffer
+        double* rw = P.red + size_t(lane) * (6 + NV);  // 2 * omega * r (6), f (NV)
+        if (act && good) {
+            const double* Gs = P.G + size_t(slot) * NG;
 #pragma unroll
             for (int r = 0; r < 6; ++r) {
                 double v = -double(a.beta) * tw[r];
@@ -838,6 +817,9 @@ __global__ void __launch_bounds__(64) backward_kernel(const KArgs a) {
             }
 #pragma unroll
             for (int c = 0; c < NV; ++c) rw[6 + c] = f[c];
+        } else {
+#pragma unroll
+            for (int e = 0; e < 6 + NV; ++e) rw[e] = 0.0;
         }
         __syncthreads();
         // Gbar = sum over the grasp's wrenches of 2 omega r f^T

@@ -39,6 +39,7 @@
 
 namespace bodex {
 
+
 // cos(pi/8), sin(pi/8)
 constexpr double kC8 = 0.92387953251128673848;
 constexpr double kS8 = 0.38268343236508978178;
@@ -386,26 +387,12 @@ BODEX_FI Residual admm_residual(const float* w, const float* x, BQ bq,
 }
 
 // ---------------------------------------------------------------------------
-// FP64 polish: dual active-set (Goldfarb-Idnani) correction warm-started from
-// the active set that ADMM identified.
-//
-// One-sided rows C f <= b with the ADMM-form row ids: 9i+k facet k of contact
-// i (b = 0), 9i+8 the upper normal bound f_i1 <= fmax, 9 MM the normal-sum
-// row -sum f_i1 <= -gamma (used only when gamma > 0).  The lower normal bound
-// f_i1 >= 0 is implied by the facets and is not a separate row.
+// Constraint rows of the polish, one-sided C f <= b, with the ADMM-form row
+// ids: 9i+k facet k of contact i (b = 0), 9i+8 the upper normal bound
+// f_i1 <= fmax, 9 MM the normal-sum row -sum f_i1 <= -gamma (used only when
+// gamma > 0).  The lower normal bound f_i1 >= 0 is implied by the facets and
+// is not a separate row.
 // ---------------------------------------------------------------------------
-
-struct RowMask {
-    uint64_t lo, hi;
-    BODEX_FI void clear() { lo = hi = 0; }
-    BODEX_FI bool has(int r) const { return r < 64 ? ((lo >> r) & 1) : ((hi >> (r - 64)) & 1); }
-    BODEX_FI void set(int r) {
-        if (r < 64) lo |= (uint64_t(1) << r); else hi |= (uint64_t(1) << (r - 64));
-    }
-    BODEX_FI void unset(int r) {
-        if (r < 64) lo &= ~(uint64_t(1) << r); else hi &= ~(uint64_t(1) << (r - 64));
-    }
-};
 
 // Coefficients of a per-contact row on its contact's 3 variables.
 BODEX_FI void row3(int r, double muc, double fm, double c[3], double* b) {
@@ -421,271 +408,7 @@ BODEX_FI void row3(int r, double muc, double fm, double c[3], double* b) {
     }
 }
 
-// Accessors into a packed symmetric matrix stored in memory that the caller
-// chooses (LDS on the GPU).
-template <int N, typename P>
-BODEX_FI double sym_at(P A, int i, int j) {
-    return i <= j ? A[up_idx<N>(i, j)] : A[up_idx<N>(j, i)];
-}
-
-template <int MM>
-struct PolishCtx {
-    static constexpr int NV = 3 * MM;
-    static constexpr int GR = 9 * MM;  // id of the normal-sum row
-    int m;
-    double fmax, gamma, eps, beta;
-    const double* muc;  // [MM] mu_i cos(pi/8)
-};
-
-// out = P^{-1} c_r (dense NV-vector).
-template <int MM, typename PP>
-BODEX_FI void pinv_row(const PolishCtx<MM>& X, PP Pinv, int r, double* out) {
-    constexpr int NV = 3 * MM;
-    if (r == PolishCtx<MM>::GR) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            double s = 0.0;
-            for (int i = 0; i < X.m; ++i) s -= sym_at<NV>(Pinv, v, 3 * i);
-            out[v] = s;
-        }
-        return;
-    }
-    double c[3], b;
-    const int i = r / 9;
-    row3(r, X.muc[i], X.fmax, c, &b);
-#pragma unroll
-    for (int v = 0; v < NV; ++v)
-        out[v] = c[0] * sym_at<NV>(Pinv, v, 3 * i) + c[1] * sym_at<NV>(Pinv, v, 3 * i + 1) +
-                 c[2] * sym_at<NV>(Pinv, v, 3 * i + 2);
-}
-
-// C_r . v and the row's right-hand side.
-template <int MM>
-BODEX_FI double row_dot(const PolishCtx<MM>& X, int r, const double* v, double* b) {
-    if (r == PolishCtx<MM>::GR) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < MM; ++i)
-            if (i < X.m) s -= v[3 * i];
-        *b = -X.gamma;
-        return s;
-    }
-    double c[3];
-    const int i = r / 9;
-    row3(r, X.muc[i], X.fmax, c, b);
-    double s = 0.0;
-#pragma unroll
-    for (int ii = 0; ii < MM; ++ii)
-        if (ii == i) s = c[0] * v[3 * ii] + c[1] * v[3 * ii + 1] + c[2] * v[3 * ii + 2];
-    return s;
-}
-
-// v += a * C_r^T.
-template <int MM>
-BODEX_FI void row_axpy(const PolishCtx<MM>& X, int r, double a, double* v) {
-    if (r == PolishCtx<MM>::GR) {
-#pragma unroll
-        for (int i = 0; i < MM; ++i)
-            if (i < X.m) v[3 * i] -= a;
-        return;
-    }
-    double c[3], b;
-    const int i = r / 9;
-    row3(r, X.muc[i], X.fmax, c, &b);
-#pragma unroll
-    for (int ii = 0; ii < MM; ++ii)
-        if (ii == i) {
-            v[3 * ii] += a * c[0];
-            v[3 * ii + 1] += a * c[1];
-            v[3 * ii + 2] += a * c[2];
-        }
-}
-
-// C_r P^{-1} C_s^T.
-template <int MM, typename PP>
-BODEX_HD inline double row_pinv_row(const PolishCtx<MM>& X, PP Pinv, int r, int s) {
-    constexpr int NV = 3 * MM;
-    constexpr int GR = PolishCtx<MM>::GR;
-    if (r == GR || s == GR) {
-        double t[NV];
-        pinv_row<MM>(X, Pinv, r == GR ? s : r, t);
-        double b;
-        return row_dot<MM>(X, r == GR ? r : s, t, &b);
-    }
-    double cr[3], cs[3], b;
-    const int i = r / 9, j = s / 9;
-    row3(r, X.muc[i], X.fmax, cr, &b);
-    row3(s, X.muc[j], X.fmax, cs, &b);
-    double acc = 0.0;
-    for (int a = 0; a < 3; ++a)
-        for (int c = 0; c < 3; ++c) acc += cr[a] * cs[c] * sym_at<NV>(Pinv, 3 * i + a, 3 * j + c);
-    return acc;
-}
-
-// Dense helpers on NV-vectors.
-template <int NV, typename PP>
-BODEX_FI void symv64(PP A, const double* x, double* y) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < NV; ++j) s += sym_at<NV>(A, i, j) * x[j];
-        y[i] = s;
-    }
-}
-
-// act[j] for a run-time j, without dynamic indexing of the register array.
-template <int NV>
-BODEX_FI int act_at(const int* act, int j) {
-    int v = act[0];
-#pragma unroll
-    for (int i = 1; i < NV; ++i) v = (j == i) ? act[i] : v;
-    return v;
-}
-
-// Cholesky of the k x k matrix M_jl = C_{act_j} P^{-1} C_{act_l}^T into
-// packed-lower storage L (accessed through L[idx * stride]).  Returns false if
-// a pivot is not positive.
-template <int MM, typename PP, typename LP>
-BODEX_FI bool factor_active(const PolishCtx<MM>& X, PP Pinv, const int* act, int k, LP L,
-                            int stride) {
-    constexpr int NV = 3 * MM;
-#pragma unroll 1
-    for (int j = 0; j < k; ++j) {
-        const int rj = act_at<NV>(act, j);
-#pragma unroll 1
-        for (int l = 0; l <= j; ++l)
-            L[lo_idx(j, l) * stride] = row_pinv_row<MM>(X, Pinv, rj, act_at<NV>(act, l));
-    }
-#pragma unroll 1
-    for (int j = 0; j < k; ++j) {
-        double d = L[lo_idx(j, j) * stride];
-        for (int l = 0; l < j; ++l) {
-            const double v = L[lo_idx(j, l) * stride];
-            d -= v * v;
-        }
-        if (!(d > 0.0)) return false;
-        d = sqrt(d);
-        L[lo_idx(j, j) * stride] = d;
-        for (int i = j + 1; i < k; ++i) {
-            double s = L[lo_idx(i, j) * stride];
-            for (int l = 0; l < j; ++l) s -= L[lo_idx(i, l) * stride] * L[lo_idx(j, l) * stride];
-            L[lo_idx(i, j) * stride] = s / d;
-        }
-    }
-    return true;
-}
-
-// Solve (L L^T) x = v in place for the first k entries.
-template <int NV, typename LP>
-BODEX_FI void chol_solve(LP L, int stride, int k, double* v) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        if (i < k) {
-            double s = v[i];
-#pragma unroll
-            for (int l = 0; l < i; ++l) s -= L[lo_idx(i, l) * stride] * v[l];
-            v[i] = s / L[lo_idx(i, i) * stride];
-        }
-    }
-#pragma unroll
-    for (int i = NV - 1; i >= 0; --i) {
-        if (i < k) {
-            double s = v[i];
-#pragma unroll
-            for (int l = i + 1; l < NV; ++l)
-                if (l < k) s -= L[lo_idx(l, i) * stride] * v[l];
-            v[i] = s / L[lo_idx(i, i) * stride];
-        }
-    }
-}
-
-// Equality-constrained minimiser on the active rows (L already factored):
-//   lam = -M^{-1}(b_W + C_W g0),  x = -(g0 + P^{-1} C_W^T lam),  g0 = P^{-1} q.
-template <int MM, typename PP, typename LP>
-BODEX_FI void eqp_solve(const PolishCtx<MM>& X, PP Pinv, LP L, int stride, const int* act,
-                        int k, const double* g0, double* x, double* lam) {
-    constexpr int NV = 3 * MM;
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        if (j < k) {
-            double b;
-            const double cg = row_dot<MM>(X, act[j], g0, &b);
-            lam[j] = -(b + cg);
-        } else {
-            lam[j] = 0.0;
-        }
-    }
-    chol_solve<NV>(L, stride, k, lam);
-    double t[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) t[v] = 0.0;
-#pragma unroll
-    for (int j = 0; j < NV; ++j)
-        if (j < k) row_axpy<MM>(X, act[j], lam[j], t);
-    double pt[NV];
-    symv64<NV>(Pinv, t, pt);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) x[v] = -(g0[v] + pt[v]);
-}
-
-// One step of iterative refinement of the equality-constrained solve: the
-// residuals r1 = P x + q + C_W^T lam (P x formed from G, exactly) and
-// r2 = C_W x - b_W are removed with the same factors:
-//   dlam = M^{-1}(r2 - C_W P^{-1} r1),  dx = -P^{-1}(r1 + C_W^T dlam).
-template <int MM, typename GP, typename PP, typename LP>
-BODEX_FI void eqp_refine(const PolishCtx<MM>& X, GP G, PP Pinv, LP L, int stride, const int* act,
-                         int k, const double* q, double* x, double* lam) {
-    constexpr int NV = 3 * MM;
-    double gx[6];
-    for (int a = 0; a < 6; ++a) {
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < NV; ++c) s += G[a * NV + c] * x[c];
-        gx[a] = s;
-    }
-    double r1[NV];
-#pragma unroll
-    for (int c = 0; c < NV; ++c) {
-        double s = X.eps * x[c];
-        for (int a = 0; a < 6; ++a) s += G[a * NV + c] * gx[a];
-        r1[c] = 2.0 * s + q[c];
-    }
-#pragma unroll
-    for (int j = 0; j < NV; ++j)
-        if (j < k) row_axpy<MM>(X, act[j], lam[j], r1);
-    double pr1[NV];
-    symv64<NV>(Pinv, r1, pr1);
-    double dl[NV];
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        if (j < k) {
-            double b;
-            const double cx = row_dot<MM>(X, act[j], x, &b);
-            double bb;
-            const double cp = row_dot<MM>(X, act[j], pr1, &bb);
-            dl[j] = (cx - b) - cp;
-        } else {
-            dl[j] = 0.0;
-        }
-    }
-    chol_solve<NV>(L, stride, k, dl);
-    double t[NV];
-#pragma unroll
-    for (int c = 0; c < NV; ++c) t[c] = r1[c];
-#pragma unroll
-    for (int j = 0; j < NV; ++j)
-        if (j < k) row_axpy<MM>(X, act[j], dl[j], t);
-    double pt[NV];
-    symv64<NV>(Pinv, t, pt);
-#pragma unroll
-    for (int c = 0; c < NV; ++c) x[c] -= pt[c];
-#pragma unroll
-    for (int j = 0; j < NV; ++j)
-        if (j < k) lam[j] += dl[j];
-}
-
-// Three-vector helpers for the per-contact independence test.
+// Three-vector helpers.
 BODEX_FI double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 BODEX_FI void cross3(const double* a, const double* b, double* c) {
     c[0] = a[1] * b[2] - a[2] * b[1];
@@ -693,348 +416,897 @@ BODEX_FI void cross3(const double* a, const double* b, double* c) {
     c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-struct PolishOut {
-    int status;  // 0 accepted, 1 rejected by the KKT check, 2 step cap, 3 breakdown
-    int steps;
-    int k;
+// ---------------------------------------------------------------------------
+// FP64 polish (the finishing step of the solver).  A dual active-set method
+// (Goldfarb-Idnani) on the QP, warm-started from the ADMM duals, whose linear
+// algebra uses the structure of the problem instead of a dense reduced
+// matrix:
+//  * the active rows are kept per contact (at most three independent rows of
+//    the nine each), plus optionally the normal-sum row, which couples all
+//    contacts;
+//  * per contact, the projector Pi_i onto the null space of its active rows
+//    has a closed form (identity, minus one direction, one direction, zero),
+//    so with Pi = diag(Pi_i) and P = 2 (G^T G + eps I) the reduced inverse is
+//      H v = Z (Z^T P Z)^{-1} Z^T v
+//          = (Pi v - Pi G^T (eps I6 + G Pi G^T)^{-1} G Pi v) / (2 eps),
+//    one 6x6 Cholesky factor per active set (Woodbury identity);
+//  * an active normal-sum row a removes one more direction from Pi: the unit
+//    vector along u = Pi a (u lies in the contacts' null spaces).
+// Multipliers follow from stationarity: per contact from the closed-form
+// inverse of its <= 3 rows, the normal-sum multiplier from a least-squares
+// fit over the contacts' null spaces.
+// ---------------------------------------------------------------------------
+
+// Active rows of one contact, ascending row ids taken from the mask bits
+// (callers keep at most three); unused entries repeat row 8.
+struct ContactRows {
+    int n;
+    int id[3];
+    double c[3][3];
+    double b[3];
 };
 
-// The polish of one QP.  Inputs: y0 (ADMM-form duals, used to pick the warm
-// active set: rows with positive dual), G (FP64 [6][NV]), Pinv (FP64 packed
-// upper), q (FP64), L workspace (NV(NV+1)/2 entries at stride `stride`).
-// Outputs: x, lam (multipliers of act[0..k-1]), act, k.
-template <int MM, typename YP, typename GP, typename PP, typename LP>
-BODEX_FI PolishOut polish_qp(const PolishCtx<MM>& X, YP y0, GP G, PP Pinv, const double* q,
-                                    LP L, int stride, int max_steps, double* x, double* lam,
-                                    int* act, int* kout) {
+BODEX_FI void contact_rows(unsigned mask, double muc, double fm, ContactRows& R) {
+    R.n = __builtin_popcount(mask);
+    unsigned mk = mask;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int id = mk ? __builtin_ctz(mk) : 8;
+        mk &= mk - 1u;
+        R.id[j] = id;
+        row3(id, muc, fm, R.c[j], &R.b[j]);
+    }
+}
+
+// Null-space projector of one contact: n = 0 identity, 1 minus the row
+// direction e, 2 the direction e = c0 x c1, 3 zero.
+struct ContactProj {
+    int n;
+    double e[3];
+    double ie;  // 1 / (e . e)
+};
+
+BODEX_FI void contact_proj(const ContactRows& R, ContactProj& P) {
+    P.n = R.n;
+    if (R.n == 2) {
+        cross3(R.c[0], R.c[1], P.e);
+    } else {
+        P.e[0] = R.c[0][0];
+        P.e[1] = R.c[0][1];
+        P.e[2] = R.c[0][2];
+    }
+    P.ie = (R.n == 1 || R.n == 2) ? 1.0 / dot3(P.e, P.e) : 0.0;
+}
+
+BODEX_FI void proj_apply(const ContactProj& P, double* v) {
+    const double d = dot3(P.e, v) * P.ie;
+    if (P.n == 1) {
+        v[0] -= d * P.e[0];
+        v[1] -= d * P.e[1];
+        v[2] -= d * P.e[2];
+    } else if (P.n == 2) {
+        v[0] = d * P.e[0];
+        v[1] = d * P.e[1];
+        v[2] = d * P.e[2];
+    } else if (P.n >= 3) {
+        v[0] = v[1] = v[2] = 0.0;
+    }
+}
+
+// u_i = Pi_i a_i with a_i = (-1, 0, 0), the contact's share of the
+// normal-sum row.
+BODEX_FI void sum_row_complement(const ContactProj& P, double* u) {
+    u[0] = -1.0;
+    u[1] = 0.0;
+    u[2] = 0.0;
+    proj_apply(P, u);
+}
+
+// Coefficients r with sum_j r_j c_j = w for w in the span of the rows.
+BODEX_FI void rows_coeffs(const ContactRows& R, const double* w, double* r) {
+    r[0] = r[1] = r[2] = 0.0;
+    if (R.n == 1) {
+        r[0] = dot3(R.c[0], w) / dot3(R.c[0], R.c[0]);
+    } else if (R.n == 2) {
+        const double a = dot3(R.c[0], R.c[0]), b = dot3(R.c[0], R.c[1]), d = dot3(R.c[1], R.c[1]);
+        const double p = dot3(R.c[0], w), q = dot3(R.c[1], w);
+        const double id = 1.0 / (a * d - b * b);
+        r[0] = (d * p - b * q) * id;
+        r[1] = (a * q - b * p) * id;
+    } else if (R.n >= 3) {
+        double k[3], t[3];
+        cross3(R.c[1], R.c[2], k);
+        const double iD = 1.0 / dot3(R.c[0], k);
+        r[0] = dot3(w, k) * iD;
+        cross3(w, R.c[2], t);
+        r[1] = dot3(R.c[0], t) * iD;
+        cross3(R.c[1], w, t);
+        r[2] = dot3(R.c[0], t) * iD;
+    }
+}
+
+// Least-norm point of {c_j . f = b_j}.
+BODEX_FI void rows_point(const ContactRows& R, double* f) {
+    f[0] = f[1] = f[2] = 0.0;
+    if (R.n == 1) {
+        const double s = R.b[0] / dot3(R.c[0], R.c[0]);
+        for (int t = 0; t < 3; ++t) f[t] = s * R.c[0][t];
+    } else if (R.n == 2) {
+        const double a = dot3(R.c[0], R.c[0]), b = dot3(R.c[0], R.c[1]), d = dot3(R.c[1], R.c[1]);
+        const double id = 1.0 / (a * d - b * b);
+        const double y0 = (d * R.b[0] - b * R.b[1]) * id, y1 = (a * R.b[1] - b * R.b[0]) * id;
+        for (int t = 0; t < 3; ++t) f[t] = y0 * R.c[0][t] + y1 * R.c[1][t];
+    } else if (R.n >= 3) {
+        double k0[3], k1[3], k2[3];
+        cross3(R.c[1], R.c[2], k0);
+        cross3(R.c[2], R.c[0], k1);
+        cross3(R.c[0], R.c[1], k2);
+        const double iD = 1.0 / dot3(R.c[0], k0);
+        for (int t = 0; t < 3; ++t) f[t] = (R.b[0] * k0[t] + R.b[1] * k1[t] + R.b[2] * k2[t]) * iD;
+    }
+}
+
+// 6x6 symmetric positive definite matrix, packed lower, and its Cholesky.
+struct Sym6 {
+    double a[21];
+};
+
+BODEX_FI bool chol6(Sym6& M) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        double d = M.a[lo_idx(j, j)];
+#pragma unroll
+        for (int l = 0; l < j; ++l) d -= M.a[lo_idx(j, l)] * M.a[lo_idx(j, l)];
+        if (!(d > 0.0)) return false;
+        d = sqrt(d);
+        M.a[lo_idx(j, j)] = d;
+        const double id = 1.0 / d;
+#pragma unroll
+        for (int i = j + 1; i < 6; ++i) {
+            double s = M.a[lo_idx(i, j)];
+#pragma unroll
+            for (int l = 0; l < j; ++l) s -= M.a[lo_idx(i, l)] * M.a[lo_idx(j, l)];
+            M.a[lo_idx(i, j)] = s * id;
+        }
+    }
+    return true;
+}
+
+BODEX_FI void chol6_solve(const Sym6& L, double* v) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        double s = v[i];
+#pragma unroll
+        for (int l = 0; l < i; ++l) s -= L.a[lo_idx(i, l)] * v[l];
+        v[i] = s / L.a[lo_idx(i, i)];
+    }
+#pragma unroll
+    for (int i = 5; i >= 0; --i) {
+        double s = v[i];
+#pragma unroll
+        for (int l = i + 1; l < 6; ++l) s -= L.a[lo_idx(l, i)] * v[l];
+        v[i] = s / L.a[lo_idx(i, i)];
+    }
+}
+
+// The problem data the polish reads: G in FP64 [6][3 MM] (row-major), mu_i
+// cos(pi/8), beta t of the lane's wrench, and the scalars.  GAM: code for the
+// normal-sum row is compiled in.
+template <int MM, typename GP, bool GAM>
+struct PolishData {
+    static constexpr bool kGam = GAM;
+    GP G;
+    const double* muc;
+    double bt[6];
+    int m;
+    double fmax, gamma, eps;
+};
+
+// One lane's vector in memory: element c at p[c * stride] (lane-interleaved
+// LDS on the GPU, so that loops over contacts need not be unrolled).
+struct LaneVec {
+    double* p;
+    int stride;
+    BODEX_FI double& operator[](int c) const { return p[c * stride]; }
+};
+
+// The polish's per-lane vectors: x and z (3 m each) and the multipliers of
+// the active rows (3 per contact, ascending row order).
+struct PolishWork {
+    LaneVec x, z, lam;
+};
+
+// Active set: bit 9i+kk of mask is row kk of contact i; gam: the normal-sum
+// row; L: the factor of eps I6 + G Pi G^T.
+struct ActiveSet {
+    uint64_t mask;
+    bool gam;
+    Sym6 L;
+};
+
+BODEX_FI unsigned contact_mask(uint64_t mask, int i) { return unsigned(mask >> (9 * i)) & 0x1FFu; }
+
+template <typename D>
+BODEX_FI void contact_geom(const D& Dt, const ActiveSet& S, int i, ContactRows& R, ContactProj& P) {
+    contact_rows(contact_mask(S.mask, i), Dt.muc[i], Dt.fmax, R);
+    contact_proj(R, P);
+}
+
+// Contact i's 6x3 block of G.
+template <int MM, typename D>
+BODEX_FI void contact_block(const D& Dt, int i, double b[6][3]) {
     constexpr int NV = 3 * MM;
-    constexpr int GR = PolishCtx<MM>::GR;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int t = 0; t < 3; ++t) b[k][t] = Dt.G[k * NV + 3 * i + t];
+}
+
+// r6 = G v (minus beta t when with_t).
+template <int MM, typename D>
+BODEX_FI void g_times(const D& Dt, const LaneVec& v, bool with_t, double* r6) {
+    constexpr int NV = 3 * MM;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) r6[k] = with_t ? -Dt.bt[k] : 0.0;
+#pragma unroll 1
+    for (int c = 0; c < 3 * Dt.m; ++c) {
+        const double vc = v[c];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) r6[k] += Dt.G[k * NV + c] * vc;
+    }
+}
+
+// Contact i's part of 2 (G^T r6 + eps v).
+template <int MM, typename D>
+BODEX_FI void contact_grad(const D& Dt, int i, const double* r6, const LaneVec& v, double* g) {
+    constexpr int NV = 3 * MM;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        double s = Dt.eps * v[3 * i + t];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) s += Dt.G[k * NV + 3 * i + t] * r6[k];
+        g[t] = 2.0 * s;
+    }
+}
+
+// In place: v <- H v.
+template <int MM, typename D>
+BODEX_FI void apply_h(const D& Dt, const ActiveSet& S, const LaneVec& v) {
+    constexpr int NV = 3 * MM;
+    const bool gam = D::kGam && S.gam;
+    const int m = Dt.m;
+    // v <- Pi v
+    double uu = 0.0, uv = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < m; ++i) {
+        ContactRows R;
+        ContactProj P;
+        contact_geom(Dt, S, i, R, P);
+        double f[3] = {v[3 * i], v[3 * i + 1], v[3 * i + 2]};
+        proj_apply(P, f);
+        if (gam) {
+            double u[3];
+            sum_row_complement(P, u);
+            uu += dot3(u, u);
+            uv += dot3(u, f);
+        }
+#pragma unroll
+        for (int t = 0; t < 3; ++t) v[3 * i + t] = f[t];
+    }
+    if (gam) {
+        const double su = uv / uu;
+#pragma unroll 1
+        for (int i = 0; i < m; ++i) {
+            ContactRows R;
+            ContactProj P;
+            contact_geom(Dt, S, i, R, P);
+            double u[3];
+            sum_row_complement(P, u);
+#pragma unroll
+            for (int t = 0; t < 3; ++t) v[3 * i + t] -= su * u[t];
+        }
+    }
+    double gv[6];
+    g_times<MM>(Dt, v, false, gv);
+    chol6_solve(S.L, gv);
+    // v <- (v - Pi G^T gv) / (2 eps)
+    const double s2 = 0.5 / Dt.eps;
+    double ut = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < m; ++i) {
+        double t3[3];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) s += Dt.G[k * NV + 3 * i + t] * gv[k];
+            t3[t] = s;
+        }
+        ContactRows R;
+        ContactProj P;
+        contact_geom(Dt, S, i, R, P);
+        proj_apply(P, t3);
+        if (gam) {
+            double u[3];
+            sum_row_complement(P, u);
+            ut += dot3(u, t3);
+        }
+#pragma unroll
+        for (int t = 0; t < 3; ++t) v[3 * i + t] = s2 * (v[3 * i + t] - t3[t]);
+    }
+    if (gam) {
+        const double sc = s2 * ut / uu;
+#pragma unroll 1
+        for (int i = 0; i < m; ++i) {
+            ContactRows R;
+            ContactProj P;
+            contact_geom(Dt, S, i, R, P);
+            double u[3];
+            sum_row_complement(P, u);
+#pragma unroll
+            for (int t = 0; t < 3; ++t) v[3 * i + t] += sc * u[t];
+        }
+    }
+}
+
+// |u|^2 for the current masks (0 when the normal-sum row is dependent on
+// the contacts' rows).
+template <typename D>
+BODEX_FI double sum_row_norm2(const D& Dt, const ActiveSet& S) {
+    double un = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < Dt.m; ++i) {
+        ContactRows R;
+        ContactProj P;
+        contact_geom(Dt, S, i, R, P);
+        double u[3];
+        sum_row_complement(P, u);
+        un += dot3(u, u);
+    }
+    return un;
+}
+
+// Factor eps I6 + G Pi G^T = eps I6 + sum_i (G_i Pi_i)(G_i Pi_i)^T, minus
+// (G u)(G u)^T / |u|^2 with the normal-sum row.
+template <int MM, typename D>
+BODEX_FI bool factor_set(const D& Dt, ActiveSet& S) {
+    const bool gam = D::kGam && S.gam;
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int c = 0; c <= r; ++c) S.L.a[lo_idx(r, c)] = (r == c) ? Dt.eps : 0.0;
+    double gu[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, uu = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < Dt.m; ++i) {
+        ContactRows R;
+        ContactProj P;
+        contact_geom(Dt, S, i, R, P);
+        double b[6][3];
+        contact_block<MM>(Dt, i, b);
+        if (gam) {
+            double u[3];
+            sum_row_complement(P, u);
+            uu += dot3(u, u);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) gu[k] += dot3(b[k], u);
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) proj_apply(P, b[k]);
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int c = 0; c <= r; ++c) S.L.a[lo_idx(r, c)] += dot3(b[r], b[c]);
+    }
+    if (gam) {
+        if (!(uu > 0.0)) return false;
+        const double iu = 1.0 / uu;
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int c = 0; c <= r; ++c) S.L.a[lo_idx(r, c)] -= gu[r] * gu[c] * iu;
+    }
+    return chol6(S.L);
+}
+
+// The pending row p of the one-row steps: contact pi, row pk (pk = 9: the
+// normal-sum row, pk < 0: none) and its coefficients on one contact.
+struct PendingRow {
+    int pi, pk;
+    double c[3];
+    double b;
+};
+
+BODEX_FI bool pending_on(const PendingRow& p, int i) { return p.pk == 9 || (p.pk >= 0 && i == p.pi); }
+
+// Multipliers from stationarity at x with a partial multiplier up on the
+// pending row: -grad(x) - up c_p = sum_i C_i^T lam_i + lg a.
+template <int MM, typename D>
+BODEX_FI void stationary_multipliers(const D& Dt, const ActiveSet& S, const PolishWork& W,
+                                     const PendingRow& p, double up, double* lg) {
+    const bool gam = D::kGam && S.gam;
+    double r6[6];
+    g_times<MM>(Dt, W.x, true, r6);
+    double ug = 0.0;
+    if (gam) {
+        double num = 0.0, den = 0.0;
+#pragma unroll 1
+        for (int i = 0; i < Dt.m; ++i) {
+            ContactRows R;
+            ContactProj P;
+            contact_geom(Dt, S, i, R, P);
+            double h[3], u[3];
+            contact_grad<MM>(Dt, i, r6, W.x, h);
+            const bool on = pending_on(p, i);
+#pragma unroll
+            for (int t = 0; t < 3; ++t) h[t] = -h[t] - (on ? up * p.c[t] : 0.0);
+            sum_row_complement(P, u);
+            num += dot3(u, h);
+            den += dot3(u, u);
+        }
+        ug = num / den;
+    }
+    *lg = ug;
+#pragma unroll 1
+    for (int i = 0; i < Dt.m; ++i) {
+        ContactRows R;
+        contact_rows(contact_mask(S.mask, i), Dt.muc[i], Dt.fmax, R);
+        double h[3], r[3];
+        contact_grad<MM>(Dt, i, r6, W.x, h);
+        const bool on = pending_on(p, i);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) h[t] = -h[t] - (on ? up * p.c[t] : 0.0);
+        h[0] += ug;
+        rows_coeffs(R, h, r);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) W.lam[3 * i + j] = r[j];
+    }
+}
+
+// Start of the equality-constrained solve: x <- a point on the active rows
+// (per contact the least-norm point of its rows, then, with the normal-sum
+// row, a move inside the contacts' null spaces onto that row; z is used as
+// work space).
+template <typename D>
+BODEX_FI void eqp_start(const D& Dt, const ActiveSet& S, const PolishWork& W) {
+    const int m = Dt.m;
+    double un = 0.0, ax = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < m; ++i) {
+        ContactRows R;
+        ContactProj P;
+        contact_geom(Dt, S, i, R, P);
+        double f[3], u[3];
+        rows_point(R, f);
+        sum_row_complement(P, u);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            W.x[3 * i + t] = f[t];
+            W.z[3 * i + t] = u[t];
+        }
+        un += dot3(u, u);
+        ax -= f[0];
+    }
+    if (D::kGam && S.gam) {
+        const double s = (-Dt.gamma - ax) / un;
+#pragma unroll 1
+        for (int c = 0; c < 3 * m; ++c) W.x[c] += s * W.z[c];
+    }
+}
+
+// The most violated inactive row at x (pk < 0: none above the tolerance).
+template <int MM, typename D>
+BODEX_FI PendingRow most_violated(const D& Dt, const ActiveSet& S, const PolishWork& W, bool use_gam,
+                                  double tol) {
+    PendingRow p = {-1, -1, {0.0, 0.0, 0.0}, 0.0};
+    double worst = tol, sum1 = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < Dt.m; ++i) {
+        const double f[3] = {W.x[3 * i], W.x[3 * i + 1], W.x[3 * i + 2]};
+        const unsigned mk = contact_mask(S.mask, i);
+        sum1 += f[0];
+#pragma unroll
+        for (int kk = 0; kk < 9; ++kk) {
+            double c[3], b;
+            row3(kk, Dt.muc[i], Dt.fmax, c, &b);
+            const double s = dot3(c, f) - b;
+            if (!((mk >> kk) & 1u) && s > worst) {
+                worst = s;
+                p.pi = i;
+                p.pk = kk;
+            }
+        }
+    }
+    if (use_gam && !S.gam && Dt.gamma - sum1 > worst) {
+        p.pi = -1;
+        p.pk = 9;
+    }
+    if (p.pk == 9) {
+        p.c[0] = -1.0;
+        p.c[1] = p.c[2] = 0.0;
+        p.b = -Dt.gamma;
+    } else if (p.pk >= 0) {
+        row3(p.pk, Dt.muc[p.pi], Dt.fmax, p.c, &p.b);
+    }
+    return p;
+}
+
+struct PolishOut {
+    int status;  // 0 accepted, 1 rejected by the KKT check, 2 step cap, 3 breakdown
+    int steps;   // factorisations
+};
+
+// The polish of one QP.  y0: ADMM-form duals (rows 9i+kk and the normal-sum
+// row 9 MM); rows with positive dual (negative for the normal-sum row) seed
+// the active set.  On return W.x holds the point, S the active set and
+// W.lam, *lg its multipliers.
+//
+// The method, in order: (1) on the warm set, the minimiser with the active
+// rows as equalities (x <- x0 - H grad(x0), twice); while a multiplier is
+// negative, drop the most negative row and repeat; (2) while a row is
+// violated, take the most violated row p and move along z = H c_p, dropping
+// rows whose multipliers reach zero, until p is satisfied (then it joins the
+// set) -- the dual active-set steps; (3) after any step, the minimiser on
+// the final set once more, exactly, then the KKT acceptance check.  The
+// loop below runs these as one state machine so that each linear-algebra
+// routine has a single call site (small code on the GPU).
+template <int MM, typename YP, typename D>
+BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork& W, ActiveSet& S,
+                             double* lg) {
     PolishOut out;
     out.status = 0;
     out.steps = 0;
-    out.k = 0;
-    int k = 0;
-    RowMask mask;
-    mask.clear();
-    double g0[NV];
-    symv64<NV>(Pinv, q, g0);
+    const double fm = Dt.fmax;
+    const int m = Dt.m;
+    const bool use_gam = D::kGam && Dt.gamma > 0.0 && m > 0;
+    const double tol_add = 1e-12 * (1.0 + fm + Dt.gamma);
 
-    // Warm start: per contact, the rows with positive ADMM dual, largest first,
-    // kept while linearly independent (at most three per contact).
+    // warm start: per contact, rows with positive ADMM dual, largest first,
+    // kept while independent
+    S.mask = 0;
+#pragma unroll 1
+    for (int i = 0; i < m; ++i) {
+        double yv[9];
 #pragma unroll
-    for (int i = 0; i < MM; ++i) {
-        if (i >= X.m) continue;
-        double s0[3] = {0, 0, 0}, s1[3] = {0, 0, 0};
-        int ns = 0;
-        uint32_t used = 0;
-        for (int pass = 0; pass < 9 && ns < 3; ++pass) {
+        for (int kk = 0; kk < 9; ++kk) yv[kk] = double(y0[9 * i + kk]);
+        unsigned mk = 0u, used = 0u;
+#pragma unroll 1
+        for (int pass = 0; pass < 9; ++pass) {
             int best = -1;
             double by = 0.0;
+#pragma unroll
             for (int kk = 0; kk < 9; ++kk) {
-                const double yv = double(y0[9 * i + kk]);
-                if (!((used >> kk) & 1) && yv > by) {
-                    by = yv;
+                if (!((used >> kk) & 1u) && yv[kk] > by) {
+                    by = yv[kk];
                     best = kk;
                 }
             }
             if (best < 0) break;
             used |= 1u << best;
+            ContactRows R;
+            ContactProj P;
+            contact_rows(mk, Dt.muc[i], fm, R);
+            contact_proj(R, P);
+            if (R.n >= 3) break;
             double c[3], b;
-            row3(9 * i + best, X.muc[i], X.fmax, c, &b);
-            const double nc = sqrt(dot3(c, c));
-            bool indep = true;
-            if (ns == 1) {
-                double cr[3];
-                cross3(s0, c, cr);
-                indep = sqrt(dot3(cr, cr)) > 1e-6 * nc * sqrt(dot3(s0, s0));
-            } else if (ns == 2) {
-                double cr[3];
-                cross3(s0, s1, cr);
-                indep = fabs(dot3(cr, c)) > 1e-6 * nc * sqrt(dot3(cr, cr));
-            }
-            if (!indep) continue;
-            if (ns == 0) {
-                s0[0] = c[0]; s0[1] = c[1]; s0[2] = c[2];
-            } else if (ns == 1) {
-                s1[0] = c[0]; s1[1] = c[1]; s1[2] = c[2];
-            }
-            ns++;
-#pragma unroll
-            for (int j = 0; j < NV; ++j)
-                if (j == k) act[j] = 9 * i + best;
-            mask.set(9 * i + best);
-            k++;
+            row3(best, Dt.muc[i], fm, c, &b);
+            const double nc = dot3(c, c);
+            proj_apply(P, c);
+            if (dot3(c, c) > 1e-12 * nc) mk |= 1u << best;
         }
+        S.mask |= uint64_t(mk) << (9 * i);
     }
+    S.gam = false;
+    if (use_gam && double(y0[9 * MM]) < 0.0) S.gam = sum_row_norm2(Dt, S) > 1e-12 * m;
 
-    // Minimiser on the warm set; drop rows with negative multipliers until the
-    // pair is dual feasible (a valid starting point of the dual method).
+    const PendingRow none = {-1, -1, {0.0, 0.0, 0.0}, 0.0};
+    enum { kWarm, kSteps, kFinal };
+    enum { kEqp0, kEqp1, kStep };
+    int phase = kWarm, mode = kEqp0;
+    bool refactor = true;
+    PendingRow p = none;
+    double up = 0.0;
+#pragma unroll 1
     for (;;) {
-        if (k > 0 && !factor_active<MM>(X, Pinv, act, k, L, stride)) {
-            out.status = 3;
-            *kout = k;
-            return out;
-        }
-        eqp_solve<MM>(X, Pinv, L, stride, act, k, g0, x, lam);
-        int worst = -1;
-        double wv = -1e-14;
-#pragma unroll
-        for (int j = 0; j < NV; ++j)
-            if (j < k && lam[j] < wv) {
-                wv = lam[j];
-                worst = j;
-            }
-        if (worst < 0) break;
-        int dropped = -1;
-#pragma unroll
-        for (int j = 0; j < NV; ++j)
-            if (j == worst) dropped = act[j];
-        mask.unset(dropped);
-#pragma unroll
-        for (int j = 0; j < NV - 1; ++j)
-            if (j >= worst) {
-                act[j] = act[j + 1];
-                lam[j] = lam[j + 1];
-            }
-        k--;
-        out.steps++;
-    }
-    double u[NV];
-#pragma unroll
-    for (int j = 0; j < NV; ++j) u[j] = lam[j];
-
-    const double tol_add = 1e-12 * (1.0 + X.fmax);
-    for (;;) {
-        // most violated inactive row
-        int p = -1;
-        double worst = tol_add;
-        for (int i = 0; i < X.m; ++i) {
-            for (int kk = 0; kk < 9; ++kk) {
-                const int r = 9 * i + kk;
-                if (mask.has(r)) continue;
-                double b;
-                const double s = row_dot<MM>(X, r, x, &b) - b;
-                if (s > worst) {
-                    worst = s;
-                    p = r;
-                }
-            }
-        }
-        if (X.gamma > 0.0 && !mask.has(GR)) {
-            double b;
-            const double s = row_dot<MM>(X, GR, x, &b) - b;
-            if (s > worst) {
-                worst = s;
-                p = GR;
-            }
-        }
-        if (p < 0) break;
-        double up = 0.0;
-        for (;;) {
+        if (refactor) {
             if (++out.steps > max_steps) {
                 out.status = 2;
-                *kout = k;
                 return out;
             }
-            if (k > 0 && !factor_active<MM>(X, Pinv, act, k, L, stride)) {
+            if (!factor_set<MM>(Dt, S)) {
                 out.status = 3;
-                *kout = k;
                 return out;
             }
-            double hp[NV];
-            pinv_row<MM>(X, Pinv, p, hp);
-            double r[NV];
-#pragma unroll
-            for (int j = 0; j < NV; ++j) {
-                double b;
-                r[j] = (j < k) ? row_dot<MM>(X, act[j], hp, &b) : 0.0;
-            }
-            chol_solve<NV>(L, stride, k, r);
-            // z = P^{-1} (c_p - C_W^T r)
-            double t[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) t[v] = 0.0;
-            row_axpy<MM>(X, p, 1.0, t);
-#pragma unroll
-            for (int j = 0; j < NV; ++j)
-                if (j < k) row_axpy<MM>(X, act[j], -r[j], t);
-            double z[NV];
-            symv64<NV>(Pinv, t, z);
-            double b;
-            const double cz = row_dot<MM>(X, p, z, &b);
-            const double cpp = row_dot<MM>(X, p, hp, &b);
-            const bool dep = !(cz > 1e-10 * cpp);
-            double t1 = INFINITY;
-            int l = -1;
-#pragma unroll
-            for (int j = 0; j < NV; ++j)
-                if (j < k && r[j] > 0.0 && u[j] / r[j] < t1) {
-                    t1 = u[j] / r[j];
-                    l = j;
-                }
-            if (dep && l < 0) {
-                out.status = 3;
-                *kout = k;
-                return out;
-            }
-            const double sp = row_dot<MM>(X, p, x, &b) - b;
-            const double t2 = dep ? INFINITY : sp / cz;
-            const double st = t2 < t1 ? t2 : t1;
-            if (!dep) {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) x[v] -= st * z[v];
-            }
-#pragma unroll
-            for (int j = 0; j < NV; ++j)
-                if (j < k) u[j] -= st * r[j];
-            up += st;
-            if (t2 <= t1) {
-                if (k >= NV) {
-                    out.status = 3;
-                    *kout = k;
-                    return out;
-                }
-#pragma unroll
-                for (int j = 0; j < NV; ++j)
-                    if (j == k) {
-                        act[j] = p;
-                        u[j] = up;
-                    }
-                mask.set(p);
-                k++;
-                break;
-            }
-            int dropped = -1;
-#pragma unroll
-            for (int j = 0; j < NV; ++j)
-                if (j == l) dropped = act[j];
-            mask.unset(dropped);
-#pragma unroll
-            for (int j = 0; j < NV - 1; ++j)
-                if (j >= l) {
-                    act[j] = act[j + 1];
-                    u[j] = u[j + 1];
-                }
-            k--;
+            refactor = false;
         }
-    }
-    // Exact re-solve on the final active set (removes drift of the updates).
-    if (k > 0 && !factor_active<MM>(X, Pinv, act, k, L, stride)) {
-        out.status = 3;
-        *kout = k;
-        return out;
-    }
-    eqp_solve<MM>(X, Pinv, L, stride, act, k, g0, x, lam);
-    eqp_refine<MM>(X, G, Pinv, L, stride, act, k, q, x, lam);
-    eqp_refine<MM>(X, G, Pinv, L, stride, act, k, q, x, lam);
-    *kout = k;
-    out.k = k;
+        const bool gam = D::kGam && S.gam;
+        // the vector H is applied to: grad(x) (equality solve) or c_p (step)
+        bool dep = false;
+        double sp = -p.b;
+        if (mode == kEqp0) eqp_start(Dt, S, W);
+        if (mode != kStep) {
+            double r6[6];
+            g_times<MM>(Dt, W.x, true, r6);
+#pragma unroll 1
+            for (int i = 0; i < m; ++i) {
+                double g[3];
+                contact_grad<MM>(Dt, i, r6, W.x, g);
+#pragma unroll
+                for (int t = 0; t < 3; ++t) W.z[3 * i + t] = g[t];
+            }
+        } else {
+            // c_p into z; is it in the span of the active rows?
+            double res2 = 0.0, cn2 = 0.0, uv = 0.0, uu = 0.0;
+#pragma unroll 1
+            for (int i = 0; i < m; ++i) {
+                const bool on = pending_on(p, i);
+                double v[3] = {on ? p.c[0] : 0.0, on ? p.c[1] : 0.0, on ? p.c[2] : 0.0};
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    W.z[3 * i + t] = v[t];
+                    sp += v[t] * W.x[3 * i + t];
+                }
+                ContactRows R;
+                ContactProj P;
+                contact_geom(Dt, S, i, R, P);
+                cn2 += dot3(v, v);
+                proj_apply(P, v);
+                res2 += dot3(v, v);
+                if (gam) {
+                    double u[3];
+                    sum_row_complement(P, u);
+                    uv += dot3(u, v);
+                    uu += dot3(u, u);
+                }
+            }
+            if (gam) res2 -= uv * uv / uu;
+            dep = !(res2 > 1e-12 * cn2);
+        }
+        if (dep) {
+#pragma unroll 1
+            for (int c = 0; c < 3 * m; ++c) W.z[c] = 0.0;
+        } else {
+            apply_h<MM>(Dt, S, W.z);
+        }
 
-    // KKT check with P x formed from G (independent of the accuracy of P^{-1}).
-    double gx[6];
-    for (int a = 0; a < 6; ++a) {
-        double s = 0.0;
+        if (mode != kStep) {
+            // equality solve pass: x <- x - H grad(x)
+#pragma unroll 1
+            for (int c = 0; c < 3 * m; ++c) W.x[c] -= W.z[c];
+            if (mode == kEqp0) {
+                mode = kEqp1;
+                continue;
+            }
+            stationary_multipliers<MM>(Dt, S, W, none, 0.0, lg);
+            if (phase == kFinal) break;
+            if (phase == kWarm) {
+                int wbit = -1;
+                double wv = -1e-14;
+                if (D::kGam && S.gam && *lg < wv) {
+                    wv = *lg;
+                    wbit = 9 * MM;
+                }
+#pragma unroll 1
+                for (int i = 0; i < m; ++i) {
+                    ContactRows R;
+                    contact_rows(contact_mask(S.mask, i), Dt.muc[i], fm, R);
 #pragma unroll
-        for (int c = 0; c < NV; ++c) s += G[a * NV + c] * x[c];
-        gx[a] = s;
-    }
-    double st[NV];
-    double sq = 0.0, spx = 0.0;
+                    for (int j = 0; j < 3; ++j) {
+                        const double l = W.lam[3 * i + j];
+                        if (j < R.n && l < wv) {
+                            wv = l;
+                            wbit = 9 * i + R.id[j];
+                        }
+                    }
+                }
+                if (wbit >= 0) {
+                    if (D::kGam && wbit == 9 * MM)
+                        S.gam = false;
+                    else
+                        S.mask &= ~(uint64_t(1) << wbit);
+                    refactor = true;
+                    mode = kEqp0;
+                    continue;
+                }
+                phase = kSteps;
+            }
+        } else {
+            // one-row step: w = c_p - P z over the active rows (r per
+            // contact, rg for the normal-sum row); the largest step keeping
+            // the multipliers nonnegative (t1) against the step that
+            // satisfies p (t2)
+            double cz = 0.0;
+#pragma unroll 1
+            for (int i = 0; i < m; ++i)
+                if (pending_on(p, i)) cz += p.c[0] * W.z[3 * i] + p.c[1] * W.z[3 * i + 1] + p.c[2] * W.z[3 * i + 2];
+            double gz[6];
+            g_times<MM>(Dt, W.z, false, gz);
+            double rg = 0.0;
+            if (gam) {
+                double num = 0.0, den = 0.0;
+#pragma unroll 1
+                for (int i = 0; i < m; ++i) {
+                    ContactRows R;
+                    ContactProj P;
+                    contact_geom(Dt, S, i, R, P);
+                    double w[3], u[3];
+                    contact_grad<MM>(Dt, i, gz, W.z, w);
+                    const bool on = pending_on(p, i);
 #pragma unroll
-    for (int c = 0; c < NV; ++c) {
-        double s = X.eps * x[c];
-        for (int a = 0; a < 6; ++a) s += G[a * NV + c] * gx[a];
-        st[c] = 2.0 * s + q[c];
-        sq = fmax(sq, fabs(q[c]));
-        spx = fmax(spx, fabs(2.0 * s));
-    }
-    double lmax = 0.0;
+                    for (int t = 0; t < 3; ++t) w[t] = (on ? p.c[t] : 0.0) - w[t];
+                    sum_row_complement(P, u);
+                    num += dot3(u, w);
+                    den += dot3(u, u);
+                }
+                rg = num / den;
+            }
+            double t1 = INFINITY;
+            int lbit = -1;
+            if (gam && rg > 0.0) {
+                t1 = *lg / rg;
+                lbit = 9 * MM;
+            }
+#pragma unroll 1
+            for (int i = 0; i < m; ++i) {
+                ContactRows R;
+                contact_rows(contact_mask(S.mask, i), Dt.muc[i], fm, R);
+                double w[3], r[3];
+                contact_grad<MM>(Dt, i, gz, W.z, w);
+                const bool on = pending_on(p, i);
 #pragma unroll
-    for (int j = 0; j < NV; ++j)
-        if (j < k) {
-            row_axpy<MM>(X, act[j], lam[j], st);
-            lmax = fmax(lmax, fabs(lam[j]));
+                for (int t = 0; t < 3; ++t) w[t] = (on ? p.c[t] : 0.0) - w[t];
+                w[0] += rg;
+                rows_coeffs(R, w, r);
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const double l = W.lam[3 * i + j];
+                    if (j < R.n && r[j] > 0.0 && l / r[j] < t1) {
+                        t1 = l / r[j];
+                        lbit = 9 * i + R.id[j];
+                    }
+                }
+            }
+            const double t2 = (dep || !(cz > 0.0)) ? INFINITY : sp / cz;
+            const double st = t2 < t1 ? t2 : t1;
+            if (!(st < INFINITY) || !(st >= 0.0)) {
+                out.status = 3;  // infeasible or broken down
+                return out;
+            }
+#pragma unroll 1
+            for (int c = 0; c < 3 * m; ++c) W.x[c] -= st * W.z[c];
+            up += st;
+            refactor = true;
+            if (t2 <= t1) {
+                // p joins the active set
+                if (p.pk == 9)
+                    S.gam = true;
+                else
+                    S.mask |= uint64_t(1) << (9 * p.pi + p.pk);
+                stationary_multipliers<MM>(Dt, S, W, none, 0.0, lg);
+                phase = kFinal;  // an exact re-solve follows the last step
+            } else {
+                // drop the row whose multiplier reached zero, continue with p
+                if (D::kGam && lbit == 9 * MM)
+                    S.gam = false;
+                else
+                    S.mask &= ~(uint64_t(1) << lbit);
+                stationary_multipliers<MM>(Dt, S, W, p, up, lg);
+                continue;
+            }
         }
-    double stat = 0.0;
+        // next row to satisfy
+        p = most_violated<MM>(Dt, S, W, use_gam, tol_add);
+        if (p.pk < 0) {
+            if (phase == kWarm || phase == kSteps) break;  // x is the minimiser on this set
+            mode = kEqp0;                                  // kFinal: re-solve exactly
+            continue;
+        }
+        phase = kSteps;
+        up = 0.0;
+        mode = kStep;
+    }
+    // acceptance: stationarity, dual and primal feasibility
+    const bool gam = D::kGam && S.gam;
+    double r6[6];
+    g_times<MM>(Dt, W.x, true, r6);
+    double gs = 0.0, stat = 0.0, lneg = 0.0, lmax = 0.0, viol = 0.0, sum1 = 0.0;
+    if (gam) {
+        lneg = fmax(lneg, -*lg);
+        lmax = fmax(lmax, fabs(*lg));
+    }
+#pragma unroll 1
+    for (int i = 0; i < m; ++i) {
+        double g[3];
+        contact_grad<MM>(Dt, i, r6, W.x, g);
+        gs = fmax(gs, fmax(fabs(g[0]), fmax(fabs(g[1]), fabs(g[2]))));
+        double st[3] = {g[0] - (gam ? *lg : 0.0), g[1], g[2]};
+        ContactRows R;
+        contact_rows(contact_mask(S.mask, i), Dt.muc[i], fm, R);
 #pragma unroll
-    for (int c = 0; c < NV; ++c) stat = fmax(stat, fabs(st[c]));
-    double lneg = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            if (j >= R.n) continue;
+            const double l = W.lam[3 * i + j];
 #pragma unroll
-    for (int j = 0; j < NV; ++j)
-        if (j < k) lneg = fmax(lneg, -lam[j]);
-    double viol = 0.0;
-    for (int i = 0; i < X.m; ++i)
+            for (int t = 0; t < 3; ++t) st[t] += l * R.c[j][t];
+            lneg = fmax(lneg, -l);
+            lmax = fmax(lmax, fabs(l));
+        }
+        stat = fmax(stat, fmax(fabs(st[0]), fmax(fabs(st[1]), fabs(st[2]))));
+        const double f[3] = {W.x[3 * i], W.x[3 * i + 1], W.x[3 * i + 2]};
+#pragma unroll
         for (int kk = 0; kk < 9; ++kk) {
-            double b;
-            viol = fmax(viol, row_dot<MM>(X, 9 * i + kk, x, &b) - b);
+            double c[3], b;
+            row3(kk, Dt.muc[i], fm, c, &b);
+            viol = fmax(viol, dot3(c, f) - b);
         }
-    if (X.gamma > 0.0) {
-        double b;
-        viol = fmax(viol, row_dot<MM>(X, GR, x, &b) - b);
+        sum1 += f[0];
     }
-    const bool ok = stat <= 1e-9 * (1.0 + sq + spx) && lneg <= 1e-9 * (1.0 + lmax) &&
-                    viol <= 1e-9 * (1.0 + X.fmax) && isfinite(stat);
+    if (use_gam) viol = fmax(viol, Dt.gamma - sum1);
+    const bool ok = stat <= 1e-9 * (1.0 + gs + lmax) && lneg <= 1e-9 * (1.0 + lmax) &&
+                    viol <= 1e-9 * (1.0 + fm + Dt.gamma) && isfinite(stat) && isfinite(gs);
     out.status = ok ? 0 : 1;
     return out;
 }
 
-// Relative KKT residual (same definition as the ADMM check) of an FP32 state
-// (x, z, y), evaluated in FP64.
-template <int MM, typename GP>
-BODEX_FI double rel_kkt64(GP G, const double* muc, const double* q, int m, double eps,
-                                 const float* x, const float* z, const float* y) {
+// Relative KKT residual (same definition as the ADMM check) of a state
+// (x, z, y), evaluated in FP64.  x(c), z(r), y(r): accessors of the force
+// entries and of the contact rows r = 9i+kk; zg, yg: the normal-sum row;
+// bt = beta t.  Contacts are visited in a loop (no per-lane arrays).
+template <int MM, typename GP, typename XA, typename ZA, typename YA>
+BODEX_FI double rel_kkt64(GP G, const double* muc, const double* bt, int m, double eps, XA x, ZA z, YA y,
+                          double zg, double yg) {
     constexpr int NV = 3 * MM;
-    double rp = 0, nAx = 0, nz = 0, aty[NV];
-    double s1 = 0.0;
+    double gx[6];
 #pragma unroll
-    for (int i = 0; i < MM; ++i) {
-        double a1 = 0, a2 = 0, a3 = 0;
-        if (i < m) {
-            const double x1 = x[3 * i], x2 = x[3 * i + 1], x3 = x[3 * i + 2];
-            for (int k = 0; k < 8; ++k) {
-                const double ck = facet_cos<double>(k), sk = facet_sin<double>(k);
-                const double ax = ck * x2 + sk * x3 - muc[i] * x1;
-                const double zk = z[9 * i + k], yk = y[9 * i + k];
-                rp = fmax(rp, fabs(ax - zk));
-                nAx = fmax(nAx, fabs(ax));
-                nz = fmax(nz, fabs(zk));
-                a1 -= muc[i] * yk;
-                a2 += ck * yk;
-                a3 += sk * yk;
-            }
-            const double zb = z[9 * i + 8];
-            a1 += double(y[9 * i + 8]) + double(y[9 * MM]);
-            rp = fmax(rp, fabs(x1 - zb));
-            nAx = fmax(nAx, fabs(x1));
-            nz = fmax(nz, fabs(zb));
-            s1 += x1;
-        }
-        aty[3 * i] = a1;
-        aty[3 * i + 1] = a2;
-        aty[3 * i + 2] = a3;
+    for (int k = 0; k < 6; ++k) gx[k] = 0.0;
+#pragma unroll 1
+    for (int c = 0; c < 3 * m; ++c) {
+        const double xc = x(c);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) gx[k] += G[k * NV + c] * xc;
     }
-    const double zg = z[9 * MM];
+    double rp = 0, nAx = 0, nz = 0, rd = 0, nPx = 0, nAty = 0, nq = 0, s1 = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < m; ++i) {
+        const double x1 = x(3 * i), x2 = x(3 * i + 1), x3 = x(3 * i + 2);
+        double aty[3] = {yg, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const double ck = facet_cos<double>(k), sk = facet_sin<double>(k);
+            const double ax = ck * x2 + sk * x3 - muc[i] * x1;
+            const double zk = z(9 * i + k), yk = y(9 * i + k);
+            rp = fmax(rp, fabs(ax - zk));
+            nAx = fmax(nAx, fabs(ax));
+            nz = fmax(nz, fabs(zk));
+            aty[0] -= muc[i] * yk;
+            aty[1] += ck * yk;
+            aty[2] += sk * yk;
+        }
+        const double zb = z(9 * i + 8);
+        aty[0] += y(9 * i + 8);
+        rp = fmax(rp, fabs(x1 - zb));
+        nAx = fmax(nAx, fabs(x1));
+        nz = fmax(nz, fabs(zb));
+        s1 += x1;
+        const double xi[3] = {x1, x2, x3};
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            double s = eps * xi[t], qc = 0.0;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                s += G[k * NV + 3 * i + t] * gx[k];
+                qc += G[k * NV + 3 * i + t] * bt[k];
+            }
+            const double px = 2.0 * s;
+            qc *= -2.0;
+            rd = fmax(rd, fabs(px + qc + aty[t]));
+            nPx = fmax(nPx, fabs(px));
+            nAty = fmax(nAty, fabs(aty[t]));
+            nq = fmax(nq, fabs(qc));
+        }
+    }
     rp = fmax(rp, fabs(s1 - zg));
     nAx = fmax(nAx, fabs(s1));
     nz = fmax(nz, fabs(zg));
-    double gx[6];
-    for (int a = 0; a < 6; ++a) {
-        double s = 0.0;
-#pragma unroll
-        for (int c = 0; c < NV; ++c) s += G[a * NV + c] * double(x[c]);
-        gx[a] = s;
-    }
-    double rd = 0, nPx = 0, nAty = 0, nq = 0;
-#pragma unroll
-    for (int c = 0; c < NV; ++c) {
-        double s = eps * double(x[c]);
-        for (int a = 0; a < 6; ++a) s += G[a * NV + c] * gx[a];
-        const double px = 2.0 * s;
-        rd = fmax(rd, fabs(px + q[c] + aty[c]));
-        nPx = fmax(nPx, fabs(px));
-        nAty = fmax(nAty, fabs(aty[c]));
-        nq = fmax(nq, fabs(q[c]));
-    }
     return fmax(rp / (1.0 + fmax(nAx, nz)), rd / (1.0 + fmax(fmax(nPx, nAty), nq)));
 }
 

@@ -31,7 +31,6 @@ struct GraphEntry {
     int* d_desc = nullptr;
     size_t desc_ints = 0;
     int* d_queue = nullptr;
-    double* d_gwork = nullptr;
     uint64_t stamp = 0;
 };
 
@@ -62,9 +61,6 @@ struct bodex_qp {
     // internal state when the caller passes none
     float* d_state = nullptr;
     size_t d_state_cap = 0;
-    // global polish workspace (large m_max)
-    double* d_gwork = nullptr;
-    size_t d_gwork_cap = 0;
     // graphs
     std::vector<GraphEntry> graphs;
     uint64_t graph_clock = 0;
@@ -106,11 +102,7 @@ bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0
 // Contact counts the kernels are compiled for.  A batch with m_max contacts
 // per grasp runs on the smallest compiled size >= m_max (array strides stay
 // m_max; the extra contacts are inert padding).
-#ifndef BODEX_WITH_MM8
 constexpr int kCompiledMM[] = {4, 5};
-#else
-constexpr int kCompiledMM[] = {4, 5, 8};
-#endif
 
 int kernel_mm(int m_max) {
     for (int mm : kCompiledMM)
@@ -122,33 +114,17 @@ size_t admm_lds(int mm, int slots) {
     switch (mm) {
         case 4: return bodex::AdmmLds<4>::bytes(slots);
         case 5: return bodex::AdmmLds<5>::bytes(slots);
-#ifdef BODEX_WITH_MM8
-        case 8: return bodex::AdmmLds<8>::bytes(slots);
-#endif
     }
     return 0;
 }
 
-size_t fin_lds(int mm, int slots) {
+size_t fin_lds(int mm, int slots, bool bwd) {
     switch (mm) {
-        case 4: return bodex::FinLds<4>::bytes(slots);
-        case 5: return bodex::FinLds<5>::bytes(slots);
-#ifdef BODEX_WITH_MM8
-        case 8: return bodex::FinLds<8>::bytes(slots);
-#endif
+        case 4: return bodex::FinLds<4>::bytes(slots, bwd);
+        case 5: return bodex::FinLds<5>::bytes(slots, bwd);
     }
     return 0;
 }
-
-// FP64 polish workspace per resident block of the finalize/backward kernels.
-size_t polish_work_bytes(int mm, int blocks) {
-    const size_t nk = size_t(3 * mm) * (3 * mm + 1) / 2;
-    return size_t(blocks) * 64 * nk * sizeof(double);
-}
-
-// Resident blocks of the finalize/backward kernels (they loop over the tile
-// queue; the count bounds the polish workspace).
-constexpr int kFinBlocksPerCU = 4;
 
 // Build the tile schedule.  Plain: grasps in index order, greedily packed.
 // Batched: grasps sorted by (m, s) so that tiles are uniform in contact count
@@ -420,7 +396,7 @@ void bodex_qp_default_params(bodex_qp_params* p) {
     p->rho_max = 1e4f;
     p->rho_hysteresis = 5.0f;
     p->fp64_cond = 1e4f;
-    p->polish_steps = 64;
+    p->polish_steps = 128;
     p->iters_per_chunk = 20;
     p->flags = BODEX_F_POLISH | BODEX_F_ADAPTIVE_RHO;
     p->admm_waves = 0;
@@ -521,13 +497,11 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
     const bool timing = (h->prm.flags & BODEX_F_TIMING) != 0;
     const bool graph = (h->prm.flags & BODEX_F_GRAPH) != 0 && h->stream != nullptr;
     const size_t lds_a = admm_lds(mm, S.slots);
-    const size_t lds_f = fin_lds(mm, S.slots);
+    const size_t lds_f = fin_lds(mm, S.slots, false);
     int per_cu = std::max(1, std::min(16, int((160 * 1024) / std::max<size_t>(lds_a, 1))));
     const int grid_a = batched ? occupancy_grid(h, per_cu, S.n_tiles) : S.n_tiles;
-    const int grid_f = occupancy_grid(h, kFinBlocksPerCU, S.n_tiles);
-    rc = ensure_device(h, reinterpret_cast<void**>(&h->d_gwork), &h->d_gwork_cap,
-                       polish_work_bytes(mm, grid_f));
-    if (rc) return rc;
+    // finalize: one block per tile (the polish keeps its state in registers)
+    const int grid_f = S.n_tiles;
 
     // Enqueue the launch sequence (reset counters, ADMM, finalize) for the
     // descriptors at d.
@@ -541,8 +515,7 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
         HIP_TRY(h, launch(Kind::Admm, mm, aa, grid_a, lds_a, h->stream, h->prm.admm_waves));
         if (with_events) HIP_TRY(h, hipEventRecord(h->tev[1], h->stream));
         KArgs f = a;
-        f.queue = d_queue + 1;
-        f.gwork = h->d_gwork;
+        f.queue = nullptr;
         if (with_events) HIP_TRY(h, hipEventRecord(h->tev[2], h->stream));
         HIP_TRY(h, launch(Kind::Fin, mm, f, grid_f, lds_f, h->stream));
         if (with_events) HIP_TRY(h, hipEventRecord(h->tev[3], h->stream));
@@ -654,15 +627,9 @@ int bodex_qp_backward(bodex_qp_t* h, const bodex_batch* in, const bodex_state* s
     rc = upload_desc(h, in, S, h->d_desc, &up);
     if (rc) return rc;
     bind_desc(a, h->d_desc, G, S);
-    const size_t lds_b = fin_lds(mm, S.slots);
-    int* d_queue = h->d_desc + (n_ints - 4);
-    a.queue = d_queue + 2;
-    HIP_TRY(h, bodex::launch_reset(d_queue + 2, 1, h->stream));
-    const int grid_b = occupancy_grid(h, kFinBlocksPerCU, S.n_tiles);
-    rc = ensure_device(h, reinterpret_cast<void**>(&h->d_gwork), &h->d_gwork_cap,
-                       polish_work_bytes(mm, grid_b));
-    if (rc) return rc;
-    a.gwork = h->d_gwork;
+    const size_t lds_b = fin_lds(mm, S.slots, true);
+    a.queue = nullptr;
+    const int grid_b = S.n_tiles;
     const bool timing = (h->prm.flags & BODEX_F_TIMING) != 0;
     if (timing && !h->tev[0]) {
         for (auto& e : h->tev) HIP_TRY(h, hipEventCreate(&e));
@@ -683,11 +650,9 @@ int bodex_qp_destroy(bodex_qp_t* h) {
     for (auto& g : h->graphs) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
         if (g.d_desc) (void)hipFree(g.d_desc);
-        if (g.d_gwork) (void)hipFree(g.d_gwork);
     }
     if (h->d_desc) (void)hipFree(h->d_desc);
     if (h->d_state) (void)hipFree(h->d_state);
-    if (h->d_gwork) (void)hipFree(h->d_gwork);
     if (h->h_desc) (void)hipHostFree(h->h_desc);
     if (h->desc_ev) (void)hipEventDestroy(h->desc_ev);
     for (auto& e : h->tev)

@@ -1,16 +1,16 @@
-// Launcher of the finalize kernel for the compiled contact counts.
+// Launcher of the finalize kernel for the compiled contact counts (gamma = 0).
 #include "bodex_kernels.h"
 #include "bodex_launch.h"
 
 namespace bodex {
 
+hipError_t launch_finalize_sum(int mm, const KArgs& a, int grid, size_t lds, hipStream_t st);
+
 hipError_t launch_finalize(int mm, const KArgs& a, int grid, size_t lds, hipStream_t st) {
+    if (a.gamma > 0.f) return launch_finalize_sum(mm, a, grid, lds, st);
     switch (mm) {
-        case 4: hipLaunchKernelGGL(finalize_kernel<4>, dim3(grid), dim3(64), lds, st, a); break;
-        case 5: hipLaunchKernelGGL(finalize_kernel<5>, dim3(grid), dim3(64), lds, st, a); break;
-#ifdef BODEX_WITH_MM8
-        case 8: hipLaunchKernelGGL(finalize_kernel<8>, dim3(grid), dim3(64), lds, st, a); break;
-#endif
+        case 4: hipLaunchKernelGGL((finalize_kernel<4, false>), dim3(grid), dim3(64), lds, st, a); break;
+        case 5: hipLaunchKernelGGL((finalize_kernel<5, false>), dim3(grid), dim3(64), lds, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -1,0 +1,16 @@
+// Launcher of the finalize kernel for the compiled contact counts, with the normal-sum row (gamma > 0).
+#include "bodex_kernels.h"
+#include "bodex_launch.h"
+
+namespace bodex {
+
+hipError_t launch_finalize_sum(int mm, const KArgs& a, int grid, size_t lds, hipStream_t st) {
+    switch (mm) {
+        case 4: hipLaunchKernelGGL((finalize_kernel<4, true>), dim3(grid), dim3(64), lds, st, a); break;
+        case 5: hipLaunchKernelGGL((finalize_kernel<5, true>), dim3(grid), dim3(64), lds, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace bodex
