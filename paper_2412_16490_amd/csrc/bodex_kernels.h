@@ -512,13 +512,16 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) 
 // ---------------------------------------------------------------------------
 template <int MM>
 struct FinLds {
-    static constexpr int NV = 3 * MM, NG = 6 * NV, NW = 3 * NV * kWave;
-    // per slot: G64, muc64 (8); per lane (lane-interleaved): the polish's x,
-    // z and multipliers; finalize: the energy reduction (one per lane);
-    // backward: Gbar per slot, and the gradient reduction 6 + NV per lane,
-    // which reuses the polish space once every lane has finished it.
+    static constexpr int NV = 3 * MM, NG = 6 * NV;
+    // per lane, lane-interleaved: the polish's x, z, multipliers (3 NV) and
+    // projector cache (4 MM)
+    static constexpr int NW = (3 * NV + 4 * MM) * kWave;
+    // per slot: G64, muc64 (8); the polish space; finalize: the energy
+    // reduction (one per lane); backward: Gbar per slot, and the gradient
+    // reduction 6 + NV per lane, which reuses the polish space once every
+    // lane has finished it.
     static __host__ __device__ size_t bytes(int slots, bool bwd) {
-        return size_t(slots) * (NG + 8) * 8 + size_t(NW) * 8 + (bwd ? size_t(slots) * NG * 8 : 64 * 8) +
+        return size_t(slots) * (NG + 8) * 8 + size_t(NW) * 8 + (bwd ? size_t(slots) * NG * 8 : size_t(kWave) * 8) +
                kMaxSlots * 32 + 64;
     }
 };
@@ -532,8 +535,8 @@ struct FinPtrs {
 
 template <int MM>
 __device__ inline FinPtrs<MM> fin_carve(unsigned char* smem, int S, bool bwd) {
-    constexpr int NG = FinLds<MM>::NG, NW = FinLds<MM>::NW;
-    static_assert(kWave * (6 + 3 * MM) <= NW, "reduction buffer must fit in the polish space");
+    constexpr int NV = FinLds<MM>::NV, NG = FinLds<MM>::NG, NW = FinLds<MM>::NW;
+    static_assert(kWave * (6 + NV) <= NW, "reduction buffer must fit in the polish space");
     FinPtrs<MM> P;
     double* d = reinterpret_cast<double*>(smem);
     P.G = d;
@@ -549,22 +552,27 @@ __device__ inline FinPtrs<MM> fin_carve(unsigned char* smem, int S, bool bwd) {
     } else {
         P.Gbar = nullptr;
         P.red = d;
-        d += 64;
+        d += kWave;
     }
     P.info = reinterpret_cast<SlotInfo*>(d);
     P.flag = reinterpret_cast<int*>(P.info + kMaxSlots);
     return P;
 }
 
-// This lane's polish vectors in the shared polish space.
+// This lane's polish vectors and projector cache in the polish space.
 template <int MM>
-__device__ inline PolishWork polish_work(const FinPtrs<MM>& P, int lane) {
+__device__ inline PolishWork<LaneVec> polish_work(const FinPtrs<MM>& P, int lane) {
     constexpr int NV = 3 * MM;
-    PolishWork W;
+    PolishWork<LaneVec> W;
     W.x = LaneVec{P.work + lane, kWave};
     W.z = LaneVec{P.work + NV * kWave + lane, kWave};
     W.lam = LaneVec{P.work + 2 * NV * kWave + lane, kWave};
     return W;
+}
+
+template <int MM>
+__device__ inline LaneVec projector_cache(const FinPtrs<MM>& P, int lane) {
+    return LaneVec{P.work + 3 * 3 * MM * kWave + lane, kWave};
 }
 
 // Returns whether the lane's grasp has finite, valid inputs.
@@ -629,12 +637,12 @@ __device__ inline LdsPolishData<MM, GAM> polish_data(const KArgs& a, const FinPt
 // the polish handles the normal-sum row (gamma > 0).
 // ---------------------------------------------------------------------------
 template <int MM, bool GAM>
-__global__ void __launch_bounds__(64) finalize_kernel(const KArgs a) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) finalize_kernel(const KArgs a) {
     constexpr int NG = 6 * 3 * MM;
     extern __shared__ __align__(16) unsigned char smem[];
     const FinPtrs<MM> P = fin_carve<MM>(smem, a.slots, false);
     const int lane = threadIdx.x;
-    const PolishWork W = polish_work<MM>(P, lane);
+    const PolishWork<LaneVec> W = polish_work<MM>(P, lane);
     __shared__ int sTile;
     for (int t = fetch_tile(a, &sTile, -1); t < a.n_tiles; t = fetch_tile(a, &sTile, t)) {
         int nsl;
@@ -660,7 +668,8 @@ __global__ void __launch_bounds__(64) finalize_kernel(const KArgs a) {
             if (finite_in && a.polish) {
                 const LdsPolishData<MM, GAM> D = polish_data<MM, GAM>(a, P, slot, si, bt);
                 double lg = 0.0;
-                ActiveSet S;
+                ActiveSet<MM> S;
+                S.pc = projector_cache<MM>(P, lane);
                 const StridedY<MM> y0{a.y + w, W_, a.ms};
                 const PolishOut po = polish_qp<MM>(D, y0, a.polish_steps, W, S, &lg);
                 if (po.status == 0) {
@@ -762,12 +771,12 @@ __global__ void __launch_bounds__(64) finalize_kernel(const KArgs a) {
 // Backward kernel.
 // ---------------------------------------------------------------------------
 template <int MM, bool GAM>
-__global__ void __launch_bounds__(64) backward_kernel(const KArgs a) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) backward_kernel(const KArgs a) {
     constexpr int NV = 3 * MM, NG = 6 * NV;
     extern __shared__ __align__(16) unsigned char smem[];
     const FinPtrs<MM> P = fin_carve<MM>(smem, a.slots, true);
     const int lane = threadIdx.x;
-    const PolishWork W = polish_work<MM>(P, lane);
+    const PolishWork<LaneVec> W = polish_work<MM>(P, lane);
     __shared__ int sTile;
     for (int t = fetch_tile(a, &sTile, -1); t < a.n_tiles; t = fetch_tile(a, &sTile, t)) {
         int nsl;
@@ -794,7 +803,8 @@ __global__ void __launch_bounds__(64) backward_kernel(const KArgs a) {
             for (int r = 0; r < 6; ++r) bt[r] = double(a.beta) * tw[r];
             const LdsPolishData<MM, GAM> D = polish_data<MM, GAM>(a, P, slot, si, bt);
             double lg = 0.0;
-            ActiveSet S;
+            ActiveSet<MM> S;
+            S.pc = projector_cache<MM>(P, lane);
             const StridedY<MM> y0{a.y + w, size_t(a.W), a.ms};
             const PolishOut po = polish_qp<MM>(D, y0, a.polish_steps, W, S, &lg);
             if (po.status == 0) {

@@ -394,18 +394,26 @@ BODEX_FI Residual admm_residual(const float* w, const float* x, BQ bq,
 // is not a separate row.
 // ---------------------------------------------------------------------------
 
-// Coefficients of a per-contact row on its contact's 3 variables.
-BODEX_FI void row3(int r, double muc, double fm, double c[3], double* b) {
-    const int k = r % 9;
-    if (k == 8) {
-        c[0] = 1.0; c[1] = 0.0; c[2] = 0.0;
-        *b = fm;
-    } else {
-        c[0] = -muc;
-        c[1] = facet_cos<double>(k);
-        c[2] = facet_sin<double>(k);
-        *b = 0.0;
-    }
+// cos and sin of facet k's angle (2k+1) pi/8 for a run-time k: the
+// magnitudes are cos(pi/8) or sin(pi/8) (cos is the larger for k in
+// {0, 3, 4, 7}); cos is negative for k in 2..5, sin for k in 4..7.
+BODEX_FI void facet_cs(int k, double* ck, double* sk) {
+    const bool cbig = ((k ^ (k >> 1)) & 1) == 0;
+    const double a = cbig ? kC8 : kS8, b = cbig ? kS8 : kC8;
+    *ck = ((k + 2) & 4) ? -a : a;
+    *sk = (k & 4) ? -b : b;
+}
+
+// Coefficients of row kk (0..8) of a contact on its 3 variables: facet kk
+// (b = 0) or the upper normal bound (kk = 8, b = fmax).
+BODEX_FI void row3(int kk, double muc, double fm, double c[3], double* b) {
+    double ck, sk;
+    facet_cs(kk & 7, &ck, &sk);
+    const bool bound = kk == 8;
+    c[0] = bound ? 1.0 : -muc;
+    c[1] = bound ? 0.0 : ck;
+    c[2] = bound ? 0.0 : sk;
+    *b = bound ? fm : 0.0;
 }
 
 // Three-vector helpers.
@@ -458,16 +466,15 @@ BODEX_FI void contact_rows(unsigned mask, double muc, double fm, ContactRows& R)
     }
 }
 
-// Null-space projector of one contact: n = 0 identity, 1 minus the row
-// direction e, 2 the direction e = c0 x c1, 3 zero.
+// Null-space projector of one contact, Pi v = a v + k (e . v) e: with n
+// active rows, n = 0: a = 1, k = 0; n = 1: e the row, a = 1, k = -1/|e|^2;
+// n = 2: e = c0 x c1, a = 0, k = 1/|e|^2; n = 3: a = k = 0.
 struct ContactProj {
-    int n;
     double e[3];
-    double ie;  // 1 / (e . e)
+    double k, a;
 };
 
 BODEX_FI void contact_proj(const ContactRows& R, ContactProj& P) {
-    P.n = R.n;
     if (R.n == 2) {
         cross3(R.c[0], R.c[1], P.e);
     } else {
@@ -475,31 +482,24 @@ BODEX_FI void contact_proj(const ContactRows& R, ContactProj& P) {
         P.e[1] = R.c[0][1];
         P.e[2] = R.c[0][2];
     }
-    P.ie = (R.n == 1 || R.n == 2) ? 1.0 / dot3(P.e, P.e) : 0.0;
+    const double ie = 1.0 / dot3(P.e, P.e);
+    P.k = (R.n == 1) ? -ie : (R.n == 2 ? ie : 0.0);
+    P.a = (R.n <= 1) ? 1.0 : 0.0;
 }
 
 BODEX_FI void proj_apply(const ContactProj& P, double* v) {
-    const double d = dot3(P.e, v) * P.ie;
-    if (P.n == 1) {
-        v[0] -= d * P.e[0];
-        v[1] -= d * P.e[1];
-        v[2] -= d * P.e[2];
-    } else if (P.n == 2) {
-        v[0] = d * P.e[0];
-        v[1] = d * P.e[1];
-        v[2] = d * P.e[2];
-    } else if (P.n >= 3) {
-        v[0] = v[1] = v[2] = 0.0;
-    }
+    const double d = dot3(P.e, v) * P.k;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) v[t] = P.a * v[t] + d * P.e[t];
 }
 
 // u_i = Pi_i a_i with a_i = (-1, 0, 0), the contact's share of the
 // normal-sum row.
 BODEX_FI void sum_row_complement(const ContactProj& P, double* u) {
-    u[0] = -1.0;
-    u[1] = 0.0;
-    u[2] = 0.0;
-    proj_apply(P, u);
+    const double d = -P.e[0] * P.k;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) u[t] = d * P.e[t];
+    u[0] -= P.a;
 }
 
 // Coefficients r with sum_j r_j c_j = w for w in the span of the rows.
@@ -568,24 +568,27 @@ BODEX_FI bool chol6(Sym6& M) {
             for (int l = 0; l < j; ++l) s -= M.a[lo_idx(i, l)] * M.a[lo_idx(j, l)];
             M.a[lo_idx(i, j)] = s * id;
         }
+        // keep the reciprocal of the pivot for the solves
+        M.a[lo_idx(j, j)] = id;
     }
     return true;
 }
 
+// Solve (L L^T) v = rhs in place; the diagonal of L holds reciprocals.
 BODEX_FI void chol6_solve(const Sym6& L, double* v) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         double s = v[i];
 #pragma unroll
         for (int l = 0; l < i; ++l) s -= L.a[lo_idx(i, l)] * v[l];
-        v[i] = s / L.a[lo_idx(i, i)];
+        v[i] = s * L.a[lo_idx(i, i)];
     }
 #pragma unroll
     for (int i = 5; i >= 0; --i) {
         double s = v[i];
 #pragma unroll
         for (int l = i + 1; l < 6; ++l) s -= L.a[lo_idx(l, i)] * v[l];
-        v[i] = s / L.a[lo_idx(i, i)];
+        v[i] = s * L.a[lo_idx(i, i)];
     }
 }
 
@@ -594,6 +597,7 @@ BODEX_FI void chol6_solve(const Sym6& L, double* v) {
 // normal-sum row is compiled in.
 template <int MM, typename GP, bool GAM>
 struct PolishData {
+    static constexpr int kMM = MM;
     static constexpr bool kGam = GAM;
     GP G;
     const double* muc;
@@ -602,63 +606,81 @@ struct PolishData {
     double fmax, gamma, eps;
 };
 
-// One lane's vector in memory: element c at p[c * stride] (lane-interleaved
-// LDS on the GPU, so that loops over contacts need not be unrolled).
+// One lane's vector in memory shared by the lanes: element c at
+// p[c * stride] (lane-interleaved).
 struct LaneVec {
     double* p;
     int stride;
     BODEX_FI double& operator[](int c) const { return p[c * stride]; }
 };
 
+// One lane's vector in its registers (a local array of the caller).  The
+// polish indexes it only with wave-uniform indices (loops over contacts
+// run the same trip count on every lane), which the compiler can serve
+// from registers without unrolling the loops.
+struct RegVec {
+    double* p;
+    BODEX_FI double& operator[](int c) const { return p[c]; }
+};
+
 // The polish's per-lane vectors: x and z (3 m each) and the multipliers of
 // the active rows (3 per contact, ascending row order).
+template <class V>
 struct PolishWork {
-    LaneVec x, z, lam;
+    V x, z, lam;
 };
 
 // Active set: bit 9i+kk of mask is row kk of contact i; gam: the normal-sum
-// row; L: the factor of eps I6 + G Pi G^T.
+// row; L: the factor of eps I6 + G Pi G^T; the contacts' projectors, kept
+// from the last factorisation.
+template <int MM>
 struct ActiveSet {
     uint64_t mask;
     bool gam;
     Sym6 L;
+    LaneVec pc;  // per contact: e (3), k of its projector (a follows from the mask)
 };
 
 BODEX_FI unsigned contact_mask(uint64_t mask, int i) { return unsigned(mask >> (9 * i)) & 0x1FFu; }
 
-template <typename D>
-BODEX_FI void contact_geom(const D& Dt, const ActiveSet& S, int i, ContactRows& R, ContactProj& P) {
+template <typename D, int MM>
+BODEX_FI void contact_geom(const D& Dt, const ActiveSet<MM>& S, int i, ContactRows& R, ContactProj& P) {
     contact_rows(contact_mask(S.mask, i), Dt.muc[i], Dt.fmax, R);
     contact_proj(R, P);
 }
 
-// Contact i's 6x3 block of G.
-template <int MM, typename D>
-BODEX_FI void contact_block(const D& Dt, int i, double b[6][3]) {
-    constexpr int NV = 3 * MM;
-#pragma unroll
-    for (int k = 0; k < 6; ++k)
-#pragma unroll
-        for (int t = 0; t < 3; ++t) b[k][t] = Dt.G[k * NV + 3 * i + t];
+template <int MM>
+BODEX_FI ContactProj cached_proj(const ActiveSet<MM>& S, int i) {
+    ContactProj P;
+    P.e[0] = S.pc[4 * i];
+    P.e[1] = S.pc[4 * i + 1];
+    P.e[2] = S.pc[4 * i + 2];
+    P.k = S.pc[4 * i + 3];
+    P.a = __builtin_popcount(contact_mask(S.mask, i)) <= 1 ? 1.0 : 0.0;
+    return P;
 }
 
 // r6 = G v (minus beta t when with_t).
-template <int MM, typename D>
-BODEX_FI void g_times(const D& Dt, const LaneVec& v, bool with_t, double* r6) {
+template <int MM, typename D, class V>
+BODEX_FI void g_times(const D& Dt, const V& v, bool with_t, double* r6) {
     constexpr int NV = 3 * MM;
 #pragma unroll
     for (int k = 0; k < 6; ++k) r6[k] = with_t ? -Dt.bt[k] : 0.0;
 #pragma unroll 1
-    for (int c = 0; c < 3 * Dt.m; ++c) {
-        const double vc = v[c];
+    for (int i = 0; i < MM; ++i) {
+        if (i >= Dt.m) continue;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) r6[k] += Dt.G[k * NV + c] * vc;
+        for (int t = 0; t < 3; ++t) {
+            const double vc = v[3 * i + t];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) r6[k] += Dt.G[k * NV + 3 * i + t] * vc;
+        }
     }
 }
 
 // Contact i's part of 2 (G^T r6 + eps v).
-template <int MM, typename D>
-BODEX_FI void contact_grad(const D& Dt, int i, const double* r6, const LaneVec& v, double* g) {
+template <int MM, typename D, class V>
+BODEX_FI void contact_grad(const D& Dt, int i, const double* r6, const V& v, double* g) {
     constexpr int NV = 3 * MM;
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
@@ -670,18 +692,17 @@ BODEX_FI void contact_grad(const D& Dt, int i, const double* r6, const LaneVec& 
 }
 
 // In place: v <- H v.
-template <int MM, typename D>
-BODEX_FI void apply_h(const D& Dt, const ActiveSet& S, const LaneVec& v) {
+template <int MM, typename D, class V>
+BODEX_FI void apply_h(const D& Dt, const ActiveSet<MM>& S, const V& v) {
     constexpr int NV = 3 * MM;
     const bool gam = D::kGam && S.gam;
     const int m = Dt.m;
-    // v <- Pi v
+    // v <- Pi v (per contact; the normal-sum direction below)
     double uu = 0.0, uv = 0.0;
 #pragma unroll 1
-    for (int i = 0; i < m; ++i) {
-        ContactRows R;
-        ContactProj P;
-        contact_geom(Dt, S, i, R, P);
+    for (int i = 0; i < MM; ++i) {
+        if (i >= m) continue;
+        const ContactProj P = cached_proj(S, i);
         double f[3] = {v[3 * i], v[3 * i + 1], v[3 * i + 2]};
         proj_apply(P, f);
         if (gam) {
@@ -693,27 +714,35 @@ BODEX_FI void apply_h(const D& Dt, const ActiveSet& S, const LaneVec& v) {
 #pragma unroll
         for (int t = 0; t < 3; ++t) v[3 * i + t] = f[t];
     }
-    if (gam) {
-        const double su = uv / uu;
-#pragma unroll 1
-        for (int i = 0; i < m; ++i) {
-            ContactRows R;
-            ContactProj P;
-            contact_geom(Dt, S, i, R, P);
-            double u[3];
-            sum_row_complement(P, u);
-#pragma unroll
-            for (int t = 0; t < 3; ++t) v[3 * i + t] -= su * u[t];
-        }
-    }
+    const double su = gam ? uv / uu : 0.0;
     double gv[6];
-    g_times<MM>(Dt, v, false, gv);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) gv[k] = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < MM; ++i) {
+        if (i >= m) continue;
+        double f[3] = {v[3 * i], v[3 * i + 1], v[3 * i + 2]};
+        if (gam) {
+            double u[3];
+            sum_row_complement(cached_proj(S, i), u);
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                f[t] -= su * u[t];
+                v[3 * i + t] = f[t];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) gv[k] += Dt.G[k * NV + 3 * i + t] * f[t];
+    }
     chol6_solve(S.L, gv);
     // v <- (v - Pi G^T gv) / (2 eps)
     const double s2 = 0.5 / Dt.eps;
     double ut = 0.0;
 #pragma unroll 1
-    for (int i = 0; i < m; ++i) {
+    for (int i = 0; i < MM; ++i) {
+        if (i >= m) continue;
         double t3[3];
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
@@ -722,9 +751,7 @@ BODEX_FI void apply_h(const D& Dt, const ActiveSet& S, const LaneVec& v) {
             for (int k = 0; k < 6; ++k) s += Dt.G[k * NV + 3 * i + t] * gv[k];
             t3[t] = s;
         }
-        ContactRows R;
-        ContactProj P;
-        contact_geom(Dt, S, i, R, P);
+        const ContactProj P = cached_proj(S, i);
         proj_apply(P, t3);
         if (gam) {
             double u[3];
@@ -737,12 +764,10 @@ BODEX_FI void apply_h(const D& Dt, const ActiveSet& S, const LaneVec& v) {
     if (gam) {
         const double sc = s2 * ut / uu;
 #pragma unroll 1
-        for (int i = 0; i < m; ++i) {
-            ContactRows R;
-            ContactProj P;
-            contact_geom(Dt, S, i, R, P);
+        for (int i = 0; i < MM; ++i) {
+            if (i >= m) continue;
             double u[3];
-            sum_row_complement(P, u);
+            sum_row_complement(cached_proj(S, i), u);
 #pragma unroll
             for (int t = 0; t < 3; ++t) v[3 * i + t] += sc * u[t];
         }
@@ -751,11 +776,12 @@ BODEX_FI void apply_h(const D& Dt, const ActiveSet& S, const LaneVec& v) {
 
 // |u|^2 for the current masks (0 when the normal-sum row is dependent on
 // the contacts' rows).
-template <typename D>
-BODEX_FI double sum_row_norm2(const D& Dt, const ActiveSet& S) {
+template <typename D, int MM>
+BODEX_FI double sum_row_norm2(const D& Dt, const ActiveSet<MM>& S) {
     double un = 0.0;
 #pragma unroll 1
-    for (int i = 0; i < Dt.m; ++i) {
+    for (int i = 0; i < MM; ++i) {
+        if (i >= Dt.m) continue;
         ContactRows R;
         ContactProj P;
         contact_geom(Dt, S, i, R, P);
@@ -766,10 +792,12 @@ BODEX_FI double sum_row_norm2(const D& Dt, const ActiveSet& S) {
     return un;
 }
 
-// Factor eps I6 + G Pi G^T = eps I6 + sum_i (G_i Pi_i)(G_i Pi_i)^T, minus
-// (G u)(G u)^T / |u|^2 with the normal-sum row.
+// Refresh the projectors and factor eps I6 + G Pi G^T = eps I6 +
+// sum_i (G_i Pi_i)(G_i Pi_i)^T, minus (G u)(G u)^T / |u|^2 with the
+// normal-sum row.
 template <int MM, typename D>
-BODEX_FI bool factor_set(const D& Dt, ActiveSet& S) {
+BODEX_FI bool factor_set(const D& Dt, ActiveSet<MM>& S) {
+    constexpr int NV = 3 * MM;
     const bool gam = D::kGam && S.gam;
 #pragma unroll
     for (int r = 0; r < 6; ++r)
@@ -777,12 +805,19 @@ BODEX_FI bool factor_set(const D& Dt, ActiveSet& S) {
         for (int c = 0; c <= r; ++c) S.L.a[lo_idx(r, c)] = (r == c) ? Dt.eps : 0.0;
     double gu[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, uu = 0.0;
 #pragma unroll 1
-    for (int i = 0; i < Dt.m; ++i) {
+    for (int i = 0; i < MM; ++i) {
+        if (i >= Dt.m) continue;
         ContactRows R;
         ContactProj P;
         contact_geom(Dt, S, i, R, P);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) S.pc[4 * i + t] = P.e[t];
+        S.pc[4 * i + 3] = P.k;
         double b[6][3];
-        contact_block<MM>(Dt, i, b);
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+#pragma unroll
+            for (int t = 0; t < 3; ++t) b[k][t] = Dt.G[k * NV + 3 * i + t];
         if (gam) {
             double u[3];
             sum_row_complement(P, u);
@@ -819,9 +854,10 @@ struct PendingRow {
 BODEX_FI bool pending_on(const PendingRow& p, int i) { return p.pk == 9 || (p.pk >= 0 && i == p.pi); }
 
 // Multipliers from stationarity at x with a partial multiplier up on the
-// pending row: -grad(x) - up c_p = sum_i C_i^T lam_i + lg a.
-template <int MM, typename D>
-BODEX_FI void stationary_multipliers(const D& Dt, const ActiveSet& S, const PolishWork& W,
+// pending row: -grad(x) - up c_p = sum_i C_i^T lam_i + lg a.  Uses the
+// projectors of the last factorisation (callers refactor first).
+template <int MM, typename D, class V>
+BODEX_FI void stationary_multipliers(const D& Dt, const ActiveSet<MM>& S, const PolishWork<V>& W,
                                      const PendingRow& p, double up, double* lg) {
     const bool gam = D::kGam && S.gam;
     double r6[6];
@@ -830,16 +866,14 @@ BODEX_FI void stationary_multipliers(const D& Dt, const ActiveSet& S, const Poli
     if (gam) {
         double num = 0.0, den = 0.0;
 #pragma unroll 1
-        for (int i = 0; i < Dt.m; ++i) {
-            ContactRows R;
-            ContactProj P;
-            contact_geom(Dt, S, i, R, P);
+        for (int i = 0; i < MM; ++i) {
+            if (i >= Dt.m) continue;
             double h[3], u[3];
             contact_grad<MM>(Dt, i, r6, W.x, h);
             const bool on = pending_on(p, i);
 #pragma unroll
             for (int t = 0; t < 3; ++t) h[t] = -h[t] - (on ? up * p.c[t] : 0.0);
-            sum_row_complement(P, u);
+            sum_row_complement(cached_proj(S, i), u);
             num += dot3(u, h);
             den += dot3(u, u);
         }
@@ -847,7 +881,8 @@ BODEX_FI void stationary_multipliers(const D& Dt, const ActiveSet& S, const Poli
     }
     *lg = ug;
 #pragma unroll 1
-    for (int i = 0; i < Dt.m; ++i) {
+    for (int i = 0; i < MM; ++i) {
+        if (i >= Dt.m) continue;
         ContactRows R;
         contact_rows(contact_mask(S.mask, i), Dt.muc[i], Dt.fmax, R);
         double h[3], r[3];
@@ -866,18 +901,17 @@ BODEX_FI void stationary_multipliers(const D& Dt, const ActiveSet& S, const Poli
 // (per contact the least-norm point of its rows, then, with the normal-sum
 // row, a move inside the contacts' null spaces onto that row; z is used as
 // work space).
-template <typename D>
-BODEX_FI void eqp_start(const D& Dt, const ActiveSet& S, const PolishWork& W) {
-    const int m = Dt.m;
+template <int MM, typename D, class V>
+BODEX_FI void eqp_start(const D& Dt, const ActiveSet<MM>& S, const PolishWork<V>& W) {
     double un = 0.0, ax = 0.0;
 #pragma unroll 1
-    for (int i = 0; i < m; ++i) {
+    for (int i = 0; i < MM; ++i) {
+        if (i >= Dt.m) continue;
         ContactRows R;
-        ContactProj P;
-        contact_geom(Dt, S, i, R, P);
+        contact_rows(contact_mask(S.mask, i), Dt.muc[i], Dt.fmax, R);
         double f[3], u[3];
         rows_point(R, f);
-        sum_row_complement(P, u);
+        sum_row_complement(cached_proj(S, i), u);
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
             W.x[3 * i + t] = f[t];
@@ -889,25 +923,31 @@ BODEX_FI void eqp_start(const D& Dt, const ActiveSet& S, const PolishWork& W) {
     if (D::kGam && S.gam) {
         const double s = (-Dt.gamma - ax) / un;
 #pragma unroll 1
-        for (int c = 0; c < 3 * m; ++c) W.x[c] += s * W.z[c];
+        for (int i = 0; i < MM; ++i) {
+            if (i >= Dt.m) continue;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) W.x[3 * i + t] += s * W.z[3 * i + t];
+        }
     }
 }
 
 // The most violated inactive row at x (pk < 0: none above the tolerance).
-template <int MM, typename D>
-BODEX_FI PendingRow most_violated(const D& Dt, const ActiveSet& S, const PolishWork& W, bool use_gam,
+template <int MM, typename D, class V>
+BODEX_FI PendingRow most_violated(const D& Dt, const ActiveSet<MM>& S, const PolishWork<V>& W, bool use_gam,
                                   double tol) {
     PendingRow p = {-1, -1, {0.0, 0.0, 0.0}, 0.0};
     double worst = tol, sum1 = 0.0;
 #pragma unroll 1
-    for (int i = 0; i < Dt.m; ++i) {
+    for (int i = 0; i < MM; ++i) {
+        if (i >= Dt.m) continue;
         const double f[3] = {W.x[3 * i], W.x[3 * i + 1], W.x[3 * i + 2]};
         const unsigned mk = contact_mask(S.mask, i);
+        const double mu = Dt.muc[i];
         sum1 += f[0];
 #pragma unroll
         for (int kk = 0; kk < 9; ++kk) {
             double c[3], b;
-            row3(kk, Dt.muc[i], Dt.fmax, c, &b);
+            row3(kk, mu, Dt.fmax, c, &b);
             const double s = dot3(c, f) - b;
             if (!((mk >> kk) & 1u) && s > worst) {
                 worst = s;
@@ -949,8 +989,8 @@ struct PolishOut {
 // the final set once more, exactly, then the KKT acceptance check.  The
 // loop below runs these as one state machine so that each linear-algebra
 // routine has a single call site (small code on the GPU).
-template <int MM, typename YP, typename D>
-BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork& W, ActiveSet& S,
+template <int MM, typename YP, typename D, class V>
+BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork<V>& W, ActiveSet<MM>& S,
                              double* lg) {
     PolishOut out;
     out.status = 0;
@@ -964,34 +1004,37 @@ BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork
     // kept while independent
     S.mask = 0;
 #pragma unroll 1
-    for (int i = 0; i < m; ++i) {
+    for (int i = 0; i < MM; ++i) {
+        if (i >= m) continue;
         double yv[9];
 #pragma unroll
         for (int kk = 0; kk < 9; ++kk) yv[kk] = double(y0[9 * i + kk]);
         unsigned mk = 0u, used = 0u;
 #pragma unroll 1
-        for (int pass = 0; pass < 9; ++pass) {
+        for (int pass = 0; pass < 3; ++pass) {
+            // the largest remaining positive dual that is independent of the
+            // rows taken so far
+            ContactRows R;
+            ContactProj P;
+            contact_rows(mk, Dt.muc[i], fm, R);
+            contact_proj(R, P);
             int best = -1;
             double by = 0.0;
 #pragma unroll
             for (int kk = 0; kk < 9; ++kk) {
-                if (!((used >> kk) & 1u) && yv[kk] > by) {
+                double c[3], b;
+                row3(kk, Dt.muc[i], fm, c, &b);
+                const double nc = dot3(c, c);
+                proj_apply(P, c);
+                const bool indep = dot3(c, c) > 1e-12 * nc;
+                if (!((used >> kk) & 1u) && indep && yv[kk] > by) {
                     by = yv[kk];
                     best = kk;
                 }
             }
             if (best < 0) break;
             used |= 1u << best;
-            ContactRows R;
-            ContactProj P;
-            contact_rows(mk, Dt.muc[i], fm, R);
-            contact_proj(R, P);
-            if (R.n >= 3) break;
-            double c[3], b;
-            row3(best, Dt.muc[i], fm, c, &b);
-            const double nc = dot3(c, c);
-            proj_apply(P, c);
-            if (dot3(c, c) > 1e-12 * nc) mk |= 1u << best;
+            mk |= 1u << best;
         }
         S.mask |= uint64_t(mk) << (9 * i);
     }
@@ -1000,11 +1043,11 @@ BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork
 
     const PendingRow none = {-1, -1, {0.0, 0.0, 0.0}, 0.0};
     enum { kWarm, kSteps, kFinal };
-    enum { kEqp0, kEqp1, kStep };
+    enum { kEqp0, kEqp1, kStep, kCheck, kPick };
     int phase = kWarm, mode = kEqp0;
-    bool refactor = true;
-    PendingRow p = none;
-    double up = 0.0;
+    bool refactor = true, need_mult = false;
+    PendingRow p = none, mp = none;
+    double up = 0.0, mup = 0.0;
 #pragma unroll 1
     for (;;) {
         if (refactor) {
@@ -1018,16 +1061,74 @@ BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork
             }
             refactor = false;
         }
+        if (need_mult) {
+            stationary_multipliers<MM>(Dt, S, W, mp, mup, lg);
+            need_mult = false;
+        }
+        if (mode == kCheck) {
+            // after an equality solve: done (final re-solve), or in the warm
+            // phase drop the most negative multiplier
+            if (phase == kFinal) break;
+            if (phase == kWarm) {
+                int wbit = -1;
+                double wv = -1e-14;
+                if (D::kGam && S.gam && *lg < wv) {
+                    wv = *lg;
+                    wbit = 9 * MM;
+                }
+#pragma unroll 1
+                for (int i = 0; i < MM; ++i) {
+                    if (i >= m) continue;
+                    const unsigned mk = contact_mask(S.mask, i);
+                    const int n = __builtin_popcount(mk);
+                    unsigned rest = mk;
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {
+                        const int id = rest ? __builtin_ctz(rest) : 8;
+                        rest &= rest - 1u;
+                        const double l = W.lam[3 * i + j];
+                        if (j < n && l < wv) {
+                            wv = l;
+                            wbit = 9 * i + id;
+                        }
+                    }
+                }
+                if (wbit >= 0) {
+                    if (D::kGam && wbit == 9 * MM)
+                        S.gam = false;
+                    else
+                        S.mask &= ~(uint64_t(1) << wbit);
+                    refactor = true;
+                    mode = kEqp0;
+                    continue;
+                }
+                phase = kSteps;
+            }
+            mode = kPick;
+        }
+        if (mode == kPick) {
+            // next row to satisfy
+            p = most_violated<MM>(Dt, S, W, use_gam, tol_add);
+            if (p.pk < 0) {
+                if (phase != kFinal) break;  // x is the minimiser on this set
+                mode = kEqp0;                // after steps: re-solve exactly
+            } else {
+                phase = kSteps;
+                up = 0.0;
+                mode = kStep;
+            }
+        }
         const bool gam = D::kGam && S.gam;
         // the vector H is applied to: grad(x) (equality solve) or c_p (step)
         bool dep = false;
         double sp = -p.b;
-        if (mode == kEqp0) eqp_start(Dt, S, W);
+        if (mode == kEqp0) eqp_start<MM>(Dt, S, W);
         if (mode != kStep) {
             double r6[6];
             g_times<MM>(Dt, W.x, true, r6);
 #pragma unroll 1
-            for (int i = 0; i < m; ++i) {
+            for (int i = 0; i < MM; ++i) {
+                if (i >= m) continue;
                 double g[3];
                 contact_grad<MM>(Dt, i, r6, W.x, g);
 #pragma unroll
@@ -1037,7 +1138,8 @@ BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork
             // c_p into z; is it in the span of the active rows?
             double res2 = 0.0, cn2 = 0.0, uv = 0.0, uu = 0.0;
 #pragma unroll 1
-            for (int i = 0; i < m; ++i) {
+            for (int i = 0; i < MM; ++i) {
+                if (i >= m) continue;
                 const bool on = pending_on(p, i);
                 double v[3] = {on ? p.c[0] : 0.0, on ? p.c[1] : 0.0, on ? p.c[2] : 0.0};
 #pragma unroll
@@ -1045,9 +1147,7 @@ BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork
                     W.z[3 * i + t] = v[t];
                     sp += v[t] * W.x[3 * i + t];
                 }
-                ContactRows R;
-                ContactProj P;
-                contact_geom(Dt, S, i, R, P);
+                const ContactProj P = cached_proj(S, i);
                 cn2 += dot3(v, v);
                 proj_apply(P, v);
                 res2 += dot3(v, v);
@@ -1063,7 +1163,11 @@ BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork
         }
         if (dep) {
 #pragma unroll 1
-            for (int c = 0; c < 3 * m; ++c) W.z[c] = 0.0;
+            for (int i = 0; i < MM; ++i) {
+                if (i >= m) continue;
+#pragma unroll
+                for (int t = 0; t < 3; ++t) W.z[3 * i + t] = 0.0;
+            }
         } else {
             apply_h<MM>(Dt, S, W.z);
         }
@@ -1071,138 +1175,107 @@ BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork
         if (mode != kStep) {
             // equality solve pass: x <- x - H grad(x)
 #pragma unroll 1
-            for (int c = 0; c < 3 * m; ++c) W.x[c] -= W.z[c];
+            for (int i = 0; i < MM; ++i) {
+                if (i >= m) continue;
+#pragma unroll
+                for (int t = 0; t < 3; ++t) W.x[3 * i + t] -= W.z[3 * i + t];
+            }
             if (mode == kEqp0) {
                 mode = kEqp1;
-                continue;
+            } else {
+                mp = none;
+                mup = 0.0;
+                need_mult = true;
+                mode = kCheck;
             }
-            stationary_multipliers<MM>(Dt, S, W, none, 0.0, lg);
-            if (phase == kFinal) break;
-            if (phase == kWarm) {
-                int wbit = -1;
-                double wv = -1e-14;
-                if (D::kGam && S.gam && *lg < wv) {
-                    wv = *lg;
-                    wbit = 9 * MM;
-                }
+            continue;
+        }
+        // one-row step: w = c_p - P z over the active rows (r per contact,
+        // rg for the normal-sum row); the largest step keeping the
+        // multipliers nonnegative (t1) against the step that satisfies p (t2)
+        double cz = 0.0;
+        double gz[6];
+        g_times<MM>(Dt, W.z, false, gz);
+        double rg = 0.0;
+        if (gam) {
+            double num = 0.0, den = 0.0;
 #pragma unroll 1
-                for (int i = 0; i < m; ++i) {
-                    ContactRows R;
-                    contact_rows(contact_mask(S.mask, i), Dt.muc[i], fm, R);
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        const double l = W.lam[3 * i + j];
-                        if (j < R.n && l < wv) {
-                            wv = l;
-                            wbit = 9 * i + R.id[j];
-                        }
-                    }
-                }
-                if (wbit >= 0) {
-                    if (D::kGam && wbit == 9 * MM)
-                        S.gam = false;
-                    else
-                        S.mask &= ~(uint64_t(1) << wbit);
-                    refactor = true;
-                    mode = kEqp0;
-                    continue;
-                }
-                phase = kSteps;
-            }
-        } else {
-            // one-row step: w = c_p - P z over the active rows (r per
-            // contact, rg for the normal-sum row); the largest step keeping
-            // the multipliers nonnegative (t1) against the step that
-            // satisfies p (t2)
-            double cz = 0.0;
-#pragma unroll 1
-            for (int i = 0; i < m; ++i)
-                if (pending_on(p, i)) cz += p.c[0] * W.z[3 * i] + p.c[1] * W.z[3 * i + 1] + p.c[2] * W.z[3 * i + 2];
-            double gz[6];
-            g_times<MM>(Dt, W.z, false, gz);
-            double rg = 0.0;
-            if (gam) {
-                double num = 0.0, den = 0.0;
-#pragma unroll 1
-                for (int i = 0; i < m; ++i) {
-                    ContactRows R;
-                    ContactProj P;
-                    contact_geom(Dt, S, i, R, P);
-                    double w[3], u[3];
-                    contact_grad<MM>(Dt, i, gz, W.z, w);
-                    const bool on = pending_on(p, i);
-#pragma unroll
-                    for (int t = 0; t < 3; ++t) w[t] = (on ? p.c[t] : 0.0) - w[t];
-                    sum_row_complement(P, u);
-                    num += dot3(u, w);
-                    den += dot3(u, u);
-                }
-                rg = num / den;
-            }
-            double t1 = INFINITY;
-            int lbit = -1;
-            if (gam && rg > 0.0) {
-                t1 = *lg / rg;
-                lbit = 9 * MM;
-            }
-#pragma unroll 1
-            for (int i = 0; i < m; ++i) {
-                ContactRows R;
-                contact_rows(contact_mask(S.mask, i), Dt.muc[i], fm, R);
-                double w[3], r[3];
+            for (int i = 0; i < MM; ++i) {
+                if (i >= m) continue;
+                double w[3], u[3];
                 contact_grad<MM>(Dt, i, gz, W.z, w);
                 const bool on = pending_on(p, i);
 #pragma unroll
                 for (int t = 0; t < 3; ++t) w[t] = (on ? p.c[t] : 0.0) - w[t];
-                w[0] += rg;
-                rows_coeffs(R, w, r);
+                sum_row_complement(cached_proj(S, i), u);
+                num += dot3(u, w);
+                den += dot3(u, u);
+            }
+            rg = num / den;
+        }
+        double t1 = INFINITY;
+        int lbit = -1;
+        if (gam && rg > 0.0) {
+            t1 = *lg / rg;
+            lbit = 9 * MM;
+        }
+#pragma unroll 1
+        for (int i = 0; i < MM; ++i) {
+            if (i >= m) continue;
+            const bool on = pending_on(p, i);
+            if (on) cz += p.c[0] * W.z[3 * i] + p.c[1] * W.z[3 * i + 1] + p.c[2] * W.z[3 * i + 2];
+            ContactRows R;
+            contact_rows(contact_mask(S.mask, i), Dt.muc[i], fm, R);
+            double w[3], r[3];
+            contact_grad<MM>(Dt, i, gz, W.z, w);
 #pragma unroll
-                for (int j = 0; j < 3; ++j) {
-                    const double l = W.lam[3 * i + j];
-                    if (j < R.n && r[j] > 0.0 && l / r[j] < t1) {
-                        t1 = l / r[j];
-                        lbit = 9 * i + R.id[j];
-                    }
+            for (int t = 0; t < 3; ++t) w[t] = (on ? p.c[t] : 0.0) - w[t];
+            w[0] += rg;
+            rows_coeffs(R, w, r);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const double l = W.lam[3 * i + j];
+                if (j < R.n && r[j] > 0.0 && l / r[j] < t1) {
+                    t1 = l / r[j];
+                    lbit = 9 * i + R.id[j];
                 }
             }
-            const double t2 = (dep || !(cz > 0.0)) ? INFINITY : sp / cz;
-            const double st = t2 < t1 ? t2 : t1;
-            if (!(st < INFINITY) || !(st >= 0.0)) {
-                out.status = 3;  // infeasible or broken down
-                return out;
-            }
+        }
+        const double t2 = (dep || !(cz > 0.0)) ? INFINITY : sp / cz;
+        const double st = t2 < t1 ? t2 : t1;
+        if (!(st < INFINITY) || !(st >= 0.0)) {
+            out.status = 3;  // infeasible or broken down
+            return out;
+        }
 #pragma unroll 1
-            for (int c = 0; c < 3 * m; ++c) W.x[c] -= st * W.z[c];
-            up += st;
-            refactor = true;
-            if (t2 <= t1) {
-                // p joins the active set
-                if (p.pk == 9)
-                    S.gam = true;
-                else
-                    S.mask |= uint64_t(1) << (9 * p.pi + p.pk);
-                stationary_multipliers<MM>(Dt, S, W, none, 0.0, lg);
-                phase = kFinal;  // an exact re-solve follows the last step
-            } else {
-                // drop the row whose multiplier reached zero, continue with p
-                if (D::kGam && lbit == 9 * MM)
-                    S.gam = false;
-                else
-                    S.mask &= ~(uint64_t(1) << lbit);
-                stationary_multipliers<MM>(Dt, S, W, p, up, lg);
-                continue;
-            }
+        for (int i = 0; i < MM; ++i) {
+            if (i >= m) continue;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) W.x[3 * i + t] -= st * W.z[3 * i + t];
         }
-        // next row to satisfy
-        p = most_violated<MM>(Dt, S, W, use_gam, tol_add);
-        if (p.pk < 0) {
-            if (phase == kWarm || phase == kSteps) break;  // x is the minimiser on this set
-            mode = kEqp0;                                  // kFinal: re-solve exactly
-            continue;
+        up += st;
+        refactor = true;
+        need_mult = true;
+        if (t2 <= t1) {
+            // p joins the active set; an exact re-solve follows the last step
+            if (p.pk == 9)
+                S.gam = true;
+            else
+                S.mask |= uint64_t(1) << (9 * p.pi + p.pk);
+            phase = kFinal;
+            mp = none;
+            mup = 0.0;
+            mode = kPick;
+        } else {
+            // drop the row whose multiplier reached zero, continue with p
+            if (D::kGam && lbit == 9 * MM)
+                S.gam = false;
+            else
+                S.mask &= ~(uint64_t(1) << lbit);
+            mp = p;
+            mup = up;
+            mode = kStep;
         }
-        phase = kSteps;
-        up = 0.0;
-        mode = kStep;
     }
     // acceptance: stationarity, dual and primal feasibility
     const bool gam = D::kGam && S.gam;
@@ -1214,7 +1287,8 @@ BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork
         lmax = fmax(lmax, fabs(*lg));
     }
 #pragma unroll 1
-    for (int i = 0; i < m; ++i) {
+    for (int i = 0; i < MM; ++i) {
+        if (i >= m) continue;
         double g[3];
         contact_grad<MM>(Dt, i, r6, W.x, g);
         gs = fmax(gs, fmax(fabs(g[0]), fmax(fabs(g[1]), fabs(g[2]))));
