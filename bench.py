@@ -7,7 +7,9 @@ per-grasp factorisation, fused ADMM with residual checks and rho adaptation,
 FP64 polish, objectives, energies and state.
 
 Prints one JSON line.  Besides the contract fields it carries:
-  roofline      the ADMM kernel (dominant) against the FP32 vector ALU peak
+  roofline      the kernel with the larger share of the step (ADMM: FP32 vector
+                ALU peak; finalize/polish: FP64 vector ALU peak), with the
+                other kernel in roofline_other_kernel
   cpu_baseline  the FP64 oracle on the host cores over the same QPs
   forms         the uneven batch (50,000 grasps) in one persistent graph launch
                 vs per-(m, s) plain launches, and forward+backward on the
@@ -26,10 +28,47 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMDs x 16 FP32 lanes x 2.4 GHz = 39.3e12 VALU lane-ops/s;
-# an FMA counts 2 flops -> 78.6 TFLOP/s without packed FP32 (which this build
-# does not use; the 157.3 TFLOP/s vendor figure assumes packed FMA).
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 VALU lane-ops/s;
+# an FMA counts 2 flops -> 78.6 TFLOP/s for FP32 without packed FMA (which this
+# build does not use; the 157.3 TFLOP/s vendor figure assumes packed FMA) and
+# 78.6 TFLOP/s for FP64 (full-rate FMA).
 PEAK_FP32_TFLOPS = 78.6
+PEAK_FP64_TFLOPS = 78.6
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = os.path.join(ROOT, "paper_2412_16490_amd", "csrc")
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources; a traffic figure measured on other sources is
+    not reported."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(KERNEL_SOURCES)):
+        if f.endswith((".h", ".hip")):
+            with open(os.path.join(KERNEL_SOURCES, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/traffic_<kernel>.txt: 'source_hash', 'bytes_per_launch'), or
+    None when it is missing or was taken on other sources."""
+    path = os.path.join(PROFILES, "traffic_%s.txt" % kernel)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def admm_flops(m: int, iters: np.ndarray, check_every: int) -> float:
@@ -95,7 +134,7 @@ def main():
     stream = torch.cuda.current_stream()
     solver = api.Solver(p, stream=stream.cuda_stream)
     st = api.new_state(db.n_grasps, db.n_qps, db.m_max)
-    res = api.new_result(db.n_grasps, db.n_qps, db.m_max)
+    res = api.new_result(db.n_grasps, db.n_qps, db.m_max, polish_flops=True)
 
     for _ in range(args.warmup):
         solver.solve(db, state=st, result=res)
@@ -120,12 +159,27 @@ def main():
     value = converged / (ms_step / 1e3)
 
     admm_avg = float(np.mean(admm_ms))
-    flops = admm_flops(5, iters, p.check_every)
-    achieved = flops / (admm_avg / 1e3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                "kernel": "admm_kernel<5>", "kernel_ms": round(admm_avg, 4),
-                "algorithmic_flops": flops}
+    fin_avg = float(np.mean(fin_ms))
+    flops_a = admm_flops(5, iters, p.check_every)
+    flops_f = float(np.sum(res["polish_flops"].double().cpu().numpy()))
+    kernels = {
+        "admm": {"bound": "alu", "kernel": "admm_kernel<5>", "dtype": "f32", "peak": PEAK_FP32_TFLOPS,
+                 "ms": admm_avg, "flops": flops_a},
+        "finalize": {"bound": "alu", "kernel": "finalize_kernel<5>", "dtype": "f64",
+                     "peak": PEAK_FP64_TFLOPS, "ms": fin_avg, "flops": flops_f},
+    }
+
+    def roof(name):
+        k = kernels[name]
+        achieved = k["flops"] / (k["ms"] / 1e3) / 1e12
+        tr = measured_traffic(name)
+        return {"bound": k["bound"], "achieved": round(achieved, 3), "peak": k["peak"], "unit": "TFLOP/s",
+                "frac": round(achieved / k["peak"], 4), "traffic": tr, "kernel": k["kernel"],
+                "kernel_dtype": k["dtype"], "kernel_ms": round(k["ms"], 4), "algorithmic_flops": k["flops"]}
+
+    dominant = max(kernels, key=lambda n: kernels[n]["ms"])
+    roofline = roof(dominant)
+    other = roof("finalize" if dominant == "admm" else "admm")
 
     out = {
         "metric": "contact-force QPs/sec at rel. KKT resid <=1e-5 (plain vs batched/served); p50/p99",
@@ -147,6 +201,7 @@ def main():
                    "iters_mean": float(np.mean(iters)), "iters_p99": float(np.percentile(iters, 99)),
                    "finalize_ms": round(float(np.mean(fin_ms)), 4)},
         "roofline": roofline,
+        "roofline_other_kernel": other,
     }
     solver.close()
 

@@ -135,6 +135,9 @@ typedef struct {
     unsigned char *status;  /* device [W]   BODEX_ST_* bits                   */
     bodex_state state;      /* optional in/out state; all-NULL pointers make  */
                             /* the library use its own workspace              */
+    float *polish_flops;    /* optional device [W]: algorithmic FP64 flops    */
+                            /* the polish spent on each QP (0 without polish; */
+                            /* NULL = not written), for roofline accounting   */
 } bodex_result;
 
 typedef struct bodex_qp bodex_qp_t;

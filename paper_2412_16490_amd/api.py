@@ -66,7 +66,7 @@ class Result(ctypes.Structure):
         ("forces", ctypes.c_void_p), ("qp_obj", ctypes.c_void_p),
         ("energy", ctypes.c_void_p), ("kkt_rel", ctypes.c_void_p),
         ("iters", ctypes.c_void_p), ("status", ctypes.c_void_p),
-        ("state", State),
+        ("state", State), ("polish_flops", ctypes.c_void_p),
     ]
 
 
@@ -202,9 +202,9 @@ def new_state(n_grasps, n_qps, m_max, device="cuda"):
     }
 
 
-def new_result(n_grasps, n_qps, m_max, device="cuda"):
+def new_result(n_grasps, n_qps, m_max, device="cuda", polish_flops=False):
     import torch
-    return {
+    out = {
         "forces": torch.empty((n_qps, 3 * m_max), dtype=torch.float32, device=device),
         "qp_obj": torch.empty((n_qps,), dtype=torch.float32, device=device),
         "energy": torch.empty((n_grasps,), dtype=torch.float32, device=device),
@@ -212,6 +212,9 @@ def new_result(n_grasps, n_qps, m_max, device="cuda"):
         "iters": torch.empty((n_qps,), dtype=torch.int32, device=device),
         "status": torch.empty((n_qps,), dtype=torch.uint8, device=device),
     }
+    if polish_flops:
+        out["polish_flops"] = torch.zeros((n_qps,), dtype=torch.float32, device=device)
+    return out
 
 
 def _c_state(st) -> State:
@@ -230,6 +233,7 @@ def bodex_qp_solve(h, batch: DeviceBatch, result: dict, state: dict | None = Non
     r.iters = _ptr(result["iters"])
     r.status = _ptr(result["status"])
     r.state = _c_state(state)
+    r.polish_flops = _ptr(result["polish_flops"]) if result.get("polish_flops") is not None else None
     b = batch.c_batch()
     _check(lib().bodex_qp_solve(h, ctypes.byref(b), ctypes.byref(r)), h)
 

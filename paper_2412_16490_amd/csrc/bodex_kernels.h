@@ -62,6 +62,7 @@ struct KArgs {
     float* kkt;
     int* iters;
     unsigned char* status;
+    float* pflops;  // optional: polish flops per QP
     // backward
     const float* dLdE;
     const float* dLdQ;
@@ -672,6 +673,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) fi
                 S.pc = projector_cache<MM>(P, lane);
                 const StridedY<MM> y0{a.y + w, W_, a.ms};
                 const PolishOut po = polish_qp<MM>(D, y0, a.polish_steps, W, S, &lg);
+                if (a.pflops) a.pflops[w] = float(polish_flops(si.m, po));
                 if (po.status == 0) {
                     polished = true;
                     st |= kStPolished;

@@ -973,7 +973,30 @@ BODEX_FI PendingRow most_violated(const D& Dt, const ActiveSet<MM>& S, const Pol
 struct PolishOut {
     int status;  // 0 accepted, 1 rejected by the KKT check, 2 step cap, 3 breakdown
     int steps;   // factorisations
+    int eqps;    // equality-constrained solves (two passes and the multipliers each)
+    int moves;   // one-row steps (ratio test and move; the refactor and the
+                 // multipliers that follow are counted in steps and moves)
+    int picks;   // searches for the most violated row
 };
+
+// Algorithmic FP64 flops of one polish (FMA = 2, add/mul/div/sqrt = 1,
+// selects and compares 0), from the arithmetic of each routine at m contacts
+// and the counts it reports; normal-sum row terms (gamma > 0) are left out:
+//   warm start            249 m per pass, 3 passes  (projector 15 + 9 rows x
+//                         (projection 15, two dots 10, scale 1))
+//   factorisation         231 m + 100  (6 projected G rows, 21 dots, 6x6 Cholesky 97)
+//   reduced solve H v     108 m + 72   (two projections, G v, G^T w, 6x6 solves 72)
+//   equality solve        530 m + 144  (start point 36 m, two passes of gradient 78 m
+//                         + H v + update 3 m, multipliers 116 m)
+//   one-row step          380 m + 77   (direction 31 m + H v, G z 36 m, ratio test
+//                         83 m, update 6 m, multipliers 116 m)
+//   violated-row search   54 m
+//   acceptance            150 m
+BODEX_FI double polish_flops(int m, const PolishOut& o) {
+    const double dm = m;
+    return 3.0 * 249.0 * dm + 150.0 * dm + o.steps * (231.0 * dm + 100.0) + o.eqps * (530.0 * dm + 144.0) +
+           o.moves * (380.0 * dm + 77.0) + o.picks * 54.0 * dm;
+}
 
 // The polish of one QP.  y0: ADMM-form duals (rows 9i+kk and the normal-sum
 // row 9 MM); rows with positive dual (negative for the normal-sum row) seed
@@ -995,6 +1018,9 @@ BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork
     PolishOut out;
     out.status = 0;
     out.steps = 0;
+    out.eqps = 0;
+    out.moves = 0;
+    out.picks = 0;
     const double fm = Dt.fmax;
     const int m = Dt.m;
     const bool use_gam = D::kGam && Dt.gamma > 0.0 && m > 0;
@@ -1109,6 +1135,7 @@ BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork
         if (mode == kPick) {
             // next row to satisfy
             p = most_violated<MM>(Dt, S, W, use_gam, tol_add);
+            ++out.picks;
             if (p.pk < 0) {
                 if (phase != kFinal) break;  // x is the minimiser on this set
                 mode = kEqp0;                // after steps: re-solve exactly
@@ -1122,7 +1149,10 @@ BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork
         // the vector H is applied to: grad(x) (equality solve) or c_p (step)
         bool dep = false;
         double sp = -p.b;
-        if (mode == kEqp0) eqp_start<MM>(Dt, S, W);
+        if (mode == kEqp0) {
+            eqp_start<MM>(Dt, S, W);
+            ++out.eqps;
+        }
         if (mode != kStep) {
             double r6[6];
             g_times<MM>(Dt, W.x, true, r6);
@@ -1193,6 +1223,7 @@ BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork
         // one-row step: w = c_p - P z over the active rows (r per contact,
         // rg for the normal-sum row); the largest step keeping the
         // multipliers nonnegative (t1) against the step that satisfies p (t2)
+        ++out.moves;
         double cz = 0.0;
         double gz[6];
         g_times<MM>(Dt, W.z, false, gz);

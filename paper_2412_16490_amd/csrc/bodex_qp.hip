@@ -492,6 +492,7 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
     a.kkt = out->kkt_rel;
     a.iters = out->iters;
     a.status = out->status;
+    a.pflops = out->polish_flops;
 
     const size_t n_ints = size_t(G) * 3 + 1 + S.n_tiles + 1 + 4;
     const bool timing = (h->prm.flags & BODEX_F_TIMING) != 0;
