@@ -668,11 +668,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) fi
             const bool finite_in = good && !(st & kStNonfinite);
             if (finite_in && a.polish) {
                 const LdsPolishData<MM, GAM> D = polish_data<MM, GAM>(a, P, slot, si, bt);
-                double lg = 0.0;
-                ActiveSet<MM> S;
-                S.pc = projector_cache<MM>(P, lane);
+                PolishState<MM> PS;
+                PS.S.pc = projector_cache<MM>(P, lane);
                 const StridedY<MM> y0{a.y + w, W_, a.ms};
-                const PolishOut po = polish_qp<MM>(D, y0, a.polish_steps, W, S, &lg);
+                const PolishOut po = polish_qp<MM>(D, y0, a.polish_steps, W, PS);
+                const ActiveSet<MM>& S = PS.S;
+                const double lg = PS.lg;
                 if (a.pflops) a.pflops[w] = float(polish_flops(si.m, po));
                 if (po.status == 0) {
                     polished = true;
@@ -804,11 +805,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) ba
 #pragma unroll
             for (int r = 0; r < 6; ++r) bt[r] = double(a.beta) * tw[r];
             const LdsPolishData<MM, GAM> D = polish_data<MM, GAM>(a, P, slot, si, bt);
-            double lg = 0.0;
-            ActiveSet<MM> S;
-            S.pc = projector_cache<MM>(P, lane);
+            PolishState<MM> PS;
+            PS.S.pc = projector_cache<MM>(P, lane);
             const StridedY<MM> y0{a.y + w, size_t(a.W), a.ms};
-            const PolishOut po = polish_qp<MM>(D, y0, a.polish_steps, W, S, &lg);
+            const PolishOut po = polish_qp<MM>(D, y0, a.polish_steps, W, PS);
             if (po.status == 0) {
 #pragma unroll
                 for (int c = 0; c < NV; ++c) f[c] = (c < 3 * si.m) ? W.x[c] : 0.0;

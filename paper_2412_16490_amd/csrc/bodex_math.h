@@ -998,10 +998,13 @@ BODEX_FI double polish_flops(int m, const PolishOut& o) {
            o.moves * (380.0 * dm + 77.0) + o.picks * 54.0 * dm;
 }
 
-// The polish of one QP.  y0: ADMM-form duals (rows 9i+kk and the normal-sum
-// row 9 MM); rows with positive dual (negative for the normal-sum row) seed
-// the active set.  On return W.x holds the point, S the active set and
-// W.lam, *lg its multipliers.
+// The polish of one QP, as a resumable state machine: polish_begin sets the
+// warm active set, each polish_advance takes one step of the method and
+// returns true once the QP is finished (PS.out.status set: accepted or not).
+// On finish W.x holds the point, PS.S the active set and W.lam, PS.lg its
+// multipliers.  y0: ADMM-form duals (rows 9i+kk and the normal-sum row
+// 9 MM); rows with positive dual (negative for the normal-sum row) seed the
+// active set.
 //
 // The method, in order: (1) on the warm set, the minimiser with the active
 // rows as equalities (x <- x0 - H grad(x0), twice); while a multiplier is
@@ -1009,22 +1012,35 @@ BODEX_FI double polish_flops(int m, const PolishOut& o) {
 // violated, take the most violated row p and move along z = H c_p, dropping
 // rows whose multipliers reach zero, until p is satisfied (then it joins the
 // set) -- the dual active-set steps; (3) after any step, the minimiser on
-// the final set once more, exactly, then the KKT acceptance check.  The
-// loop below runs these as one state machine so that each linear-algebra
-// routine has a single call site (small code on the GPU).
-template <int MM, typename YP, typename D, class V>
-BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork<V>& W, ActiveSet<MM>& S,
-                             double* lg) {
+// the final set once more, exactly, then the KKT acceptance check.  Each
+// linear-algebra routine has a single call site in polish_advance (small
+// code on the GPU), and a lane can start the next QP as soon as its current
+// one finishes.
+enum PolishPhase { kWarm, kSteps, kFinal };
+enum PolishMode { kEqp0, kEqp1, kStep, kCheck, kPick, kAccept };
+
+template <int MM>
+struct PolishState {
+    ActiveSet<MM> S;
+    PendingRow p, mp;  // pending row; row of the multipliers still to compute
+    double up, mup, lg;
+    int phase, mode;
+    bool refactor, need_mult;
     PolishOut out;
+};
+
+template <int MM, typename YP, typename D>
+BODEX_FI void polish_begin(const D& Dt, YP y0, PolishState<MM>& PS) {
+    PolishOut& out = PS.out;
     out.status = 0;
     out.steps = 0;
     out.eqps = 0;
     out.moves = 0;
     out.picks = 0;
+    ActiveSet<MM>& S = PS.S;
     const double fm = Dt.fmax;
     const int m = Dt.m;
     const bool use_gam = D::kGam && Dt.gamma > 0.0 && m > 0;
-    const double tol_add = 1e-12 * (1.0 + fm + Dt.gamma);
 
     // warm start: per contact, rows with positive ADMM dual, largest first,
     // kept while independent
@@ -1068,247 +1084,27 @@ BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork
     if (use_gam && double(y0[9 * MM]) < 0.0) S.gam = sum_row_norm2(Dt, S) > 1e-12 * m;
 
     const PendingRow none = {-1, -1, {0.0, 0.0, 0.0}, 0.0};
-    enum { kWarm, kSteps, kFinal };
-    enum { kEqp0, kEqp1, kStep, kCheck, kPick };
-    int phase = kWarm, mode = kEqp0;
-    bool refactor = true, need_mult = false;
-    PendingRow p = none, mp = none;
-    double up = 0.0, mup = 0.0;
-#pragma unroll 1
-    for (;;) {
-        if (refactor) {
-            if (++out.steps > max_steps) {
-                out.status = 2;
-                return out;
-            }
-            if (!factor_set<MM>(Dt, S)) {
-                out.status = 3;
-                return out;
-            }
-            refactor = false;
-        }
-        if (need_mult) {
-            stationary_multipliers<MM>(Dt, S, W, mp, mup, lg);
-            need_mult = false;
-        }
-        if (mode == kCheck) {
-            // after an equality solve: done (final re-solve), or in the warm
-            // phase drop the most negative multiplier
-            if (phase == kFinal) break;
-            if (phase == kWarm) {
-                int wbit = -1;
-                double wv = -1e-14;
-                if (D::kGam && S.gam && *lg < wv) {
-                    wv = *lg;
-                    wbit = 9 * MM;
-                }
-#pragma unroll 1
-                for (int i = 0; i < MM; ++i) {
-                    if (i >= m) continue;
-                    const unsigned mk = contact_mask(S.mask, i);
-                    const int n = __builtin_popcount(mk);
-                    unsigned rest = mk;
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) {
-                        const int id = rest ? __builtin_ctz(rest) : 8;
-                        rest &= rest - 1u;
-                        const double l = W.lam[3 * i + j];
-                        if (j < n && l < wv) {
-                            wv = l;
-                            wbit = 9 * i + id;
-                        }
-                    }
-                }
-                if (wbit >= 0) {
-                    if (D::kGam && wbit == 9 * MM)
-                        S.gam = false;
-                    else
-                        S.mask &= ~(uint64_t(1) << wbit);
-                    refactor = true;
-                    mode = kEqp0;
-                    continue;
-                }
-                phase = kSteps;
-            }
-            mode = kPick;
-        }
-        if (mode == kPick) {
-            // next row to satisfy
-            p = most_violated<MM>(Dt, S, W, use_gam, tol_add);
-            ++out.picks;
-            if (p.pk < 0) {
-                if (phase != kFinal) break;  // x is the minimiser on this set
-                mode = kEqp0;                // after steps: re-solve exactly
-            } else {
-                phase = kSteps;
-                up = 0.0;
-                mode = kStep;
-            }
-        }
-        const bool gam = D::kGam && S.gam;
-        // the vector H is applied to: grad(x) (equality solve) or c_p (step)
-        bool dep = false;
-        double sp = -p.b;
-        if (mode == kEqp0) {
-            eqp_start<MM>(Dt, S, W);
-            ++out.eqps;
-        }
-        if (mode != kStep) {
-            double r6[6];
-            g_times<MM>(Dt, W.x, true, r6);
-#pragma unroll 1
-            for (int i = 0; i < MM; ++i) {
-                if (i >= m) continue;
-                double g[3];
-                contact_grad<MM>(Dt, i, r6, W.x, g);
-#pragma unroll
-                for (int t = 0; t < 3; ++t) W.z[3 * i + t] = g[t];
-            }
-        } else {
-            // c_p into z; is it in the span of the active rows?
-            double res2 = 0.0, cn2 = 0.0, uv = 0.0, uu = 0.0;
-#pragma unroll 1
-            for (int i = 0; i < MM; ++i) {
-                if (i >= m) continue;
-                const bool on = pending_on(p, i);
-                double v[3] = {on ? p.c[0] : 0.0, on ? p.c[1] : 0.0, on ? p.c[2] : 0.0};
-#pragma unroll
-                for (int t = 0; t < 3; ++t) {
-                    W.z[3 * i + t] = v[t];
-                    sp += v[t] * W.x[3 * i + t];
-                }
-                const ContactProj P = cached_proj(S, i);
-                cn2 += dot3(v, v);
-                proj_apply(P, v);
-                res2 += dot3(v, v);
-                if (gam) {
-                    double u[3];
-                    sum_row_complement(P, u);
-                    uv += dot3(u, v);
-                    uu += dot3(u, u);
-                }
-            }
-            if (gam) res2 -= uv * uv / uu;
-            dep = !(res2 > 1e-12 * cn2);
-        }
-        if (dep) {
-#pragma unroll 1
-            for (int i = 0; i < MM; ++i) {
-                if (i >= m) continue;
-#pragma unroll
-                for (int t = 0; t < 3; ++t) W.z[3 * i + t] = 0.0;
-            }
-        } else {
-            apply_h<MM>(Dt, S, W.z);
-        }
+    PS.p = none;
+    PS.mp = none;
+    PS.up = 0.0;
+    PS.mup = 0.0;
+    PS.lg = 0.0;
+    PS.phase = kWarm;
+    PS.mode = kEqp0;
+    PS.refactor = true;
+    PS.need_mult = false;
+}
 
-        if (mode != kStep) {
-            // equality solve pass: x <- x - H grad(x)
-#pragma unroll 1
-            for (int i = 0; i < MM; ++i) {
-                if (i >= m) continue;
-#pragma unroll
-                for (int t = 0; t < 3; ++t) W.x[3 * i + t] -= W.z[3 * i + t];
-            }
-            if (mode == kEqp0) {
-                mode = kEqp1;
-            } else {
-                mp = none;
-                mup = 0.0;
-                need_mult = true;
-                mode = kCheck;
-            }
-            continue;
-        }
-        // one-row step: w = c_p - P z over the active rows (r per contact,
-        // rg for the normal-sum row); the largest step keeping the
-        // multipliers nonnegative (t1) against the step that satisfies p (t2)
-        ++out.moves;
-        double cz = 0.0;
-        double gz[6];
-        g_times<MM>(Dt, W.z, false, gz);
-        double rg = 0.0;
-        if (gam) {
-            double num = 0.0, den = 0.0;
-#pragma unroll 1
-            for (int i = 0; i < MM; ++i) {
-                if (i >= m) continue;
-                double w[3], u[3];
-                contact_grad<MM>(Dt, i, gz, W.z, w);
-                const bool on = pending_on(p, i);
-#pragma unroll
-                for (int t = 0; t < 3; ++t) w[t] = (on ? p.c[t] : 0.0) - w[t];
-                sum_row_complement(cached_proj(S, i), u);
-                num += dot3(u, w);
-                den += dot3(u, u);
-            }
-            rg = num / den;
-        }
-        double t1 = INFINITY;
-        int lbit = -1;
-        if (gam && rg > 0.0) {
-            t1 = *lg / rg;
-            lbit = 9 * MM;
-        }
-#pragma unroll 1
-        for (int i = 0; i < MM; ++i) {
-            if (i >= m) continue;
-            const bool on = pending_on(p, i);
-            if (on) cz += p.c[0] * W.z[3 * i] + p.c[1] * W.z[3 * i + 1] + p.c[2] * W.z[3 * i + 2];
-            ContactRows R;
-            contact_rows(contact_mask(S.mask, i), Dt.muc[i], fm, R);
-            double w[3], r[3];
-            contact_grad<MM>(Dt, i, gz, W.z, w);
-#pragma unroll
-            for (int t = 0; t < 3; ++t) w[t] = (on ? p.c[t] : 0.0) - w[t];
-            w[0] += rg;
-            rows_coeffs(R, w, r);
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const double l = W.lam[3 * i + j];
-                if (j < R.n && r[j] > 0.0 && l / r[j] < t1) {
-                    t1 = l / r[j];
-                    lbit = 9 * i + R.id[j];
-                }
-            }
-        }
-        const double t2 = (dep || !(cz > 0.0)) ? INFINITY : sp / cz;
-        const double st = t2 < t1 ? t2 : t1;
-        if (!(st < INFINITY) || !(st >= 0.0)) {
-            out.status = 3;  // infeasible or broken down
-            return out;
-        }
-#pragma unroll 1
-        for (int i = 0; i < MM; ++i) {
-            if (i >= m) continue;
-#pragma unroll
-            for (int t = 0; t < 3; ++t) W.x[3 * i + t] -= st * W.z[3 * i + t];
-        }
-        up += st;
-        refactor = true;
-        need_mult = true;
-        if (t2 <= t1) {
-            // p joins the active set; an exact re-solve follows the last step
-            if (p.pk == 9)
-                S.gam = true;
-            else
-                S.mask |= uint64_t(1) << (9 * p.pi + p.pk);
-            phase = kFinal;
-            mp = none;
-            mup = 0.0;
-            mode = kPick;
-        } else {
-            // drop the row whose multiplier reached zero, continue with p
-            if (D::kGam && lbit == 9 * MM)
-                S.gam = false;
-            else
-                S.mask &= ~(uint64_t(1) << lbit);
-            mp = p;
-            mup = up;
-            mode = kStep;
-        }
-    }
-    // acceptance: stationarity, dual and primal feasibility
+// Acceptance: stationarity, dual and primal feasibility.  Sets the status
+// and returns true (the QP is finished).
+template <int MM, typename D, class V>
+BODEX_FI bool polish_accept(const D& Dt, const PolishWork<V>& W, PolishState<MM>& PS) {
+    const ActiveSet<MM>& S = PS.S;
+    PolishOut& out = PS.out;
+    const double* lg = &PS.lg;
+    const double fm = Dt.fmax;
+    const int m = Dt.m;
+    const bool use_gam = D::kGam && Dt.gamma > 0.0 && m > 0;
     const bool gam = D::kGam && S.gam;
     double r6[6];
     g_times<MM>(Dt, W.x, true, r6);
@@ -1349,7 +1145,277 @@ BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork
     const bool ok = stat <= 1e-9 * (1.0 + gs + lmax) && lneg <= 1e-9 * (1.0 + lmax) &&
                     viol <= 1e-9 * (1.0 + fm + Dt.gamma) && isfinite(stat) && isfinite(gs);
     out.status = ok ? 0 : 1;
-    return out;
+    return true;
+}
+
+
+template <int MM, typename D, class V>
+BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W, PolishState<MM>& PS) {
+    ActiveSet<MM>& S = PS.S;
+    PolishOut& out = PS.out;
+    double* lg = &PS.lg;
+    PendingRow& p = PS.p;
+    PendingRow& mp = PS.mp;
+    double& up = PS.up;
+    double& mup = PS.mup;
+    int& phase = PS.phase;
+    int& mode = PS.mode;
+    bool& refactor = PS.refactor;
+    bool& need_mult = PS.need_mult;
+    const double fm = Dt.fmax;
+    const int m = Dt.m;
+    const bool use_gam = D::kGam && Dt.gamma > 0.0 && m > 0;
+    const double tol_add = 1e-12 * (1.0 + fm + Dt.gamma);
+    const PendingRow none = {-1, -1, {0.0, 0.0, 0.0}, 0.0};
+    if (mode == kAccept) return polish_accept<MM>(Dt, W, PS);
+    if (refactor) {
+        if (++out.steps > max_steps) {
+            out.status = 2;
+            return true;
+        }
+        if (!factor_set<MM>(Dt, S)) {
+            out.status = 3;
+            return true;
+        }
+        refactor = false;
+    }
+    if (need_mult) {
+        stationary_multipliers<MM>(Dt, S, W, mp, mup, lg);
+        need_mult = false;
+    }
+    if (mode == kCheck) {
+        // after an equality solve: done (final re-solve), or in the warm
+        // phase drop the most negative multiplier
+        if (phase == kFinal) {
+            mode = kAccept;
+            return false;
+        }
+        if (phase == kWarm) {
+            int wbit = -1;
+            double wv = -1e-14;
+            if (D::kGam && S.gam && *lg < wv) {
+                wv = *lg;
+                wbit = 9 * MM;
+            }
+#pragma unroll 1
+            for (int i = 0; i < MM; ++i) {
+                if (i >= m) continue;
+                const unsigned mk = contact_mask(S.mask, i);
+                const int n = __builtin_popcount(mk);
+                unsigned rest = mk;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const int id = rest ? __builtin_ctz(rest) : 8;
+                    rest &= rest - 1u;
+                    const double l = W.lam[3 * i + j];
+                    if (j < n && l < wv) {
+                        wv = l;
+                        wbit = 9 * i + id;
+                    }
+                }
+            }
+            if (wbit >= 0) {
+                if (D::kGam && wbit == 9 * MM)
+                    S.gam = false;
+                else
+                    S.mask &= ~(uint64_t(1) << wbit);
+                refactor = true;
+                mode = kEqp0;
+                return false;
+            }
+            phase = kSteps;
+        }
+        mode = kPick;
+    }
+    if (mode == kPick) {
+        // next row to satisfy
+        p = most_violated<MM>(Dt, S, W, use_gam, tol_add);
+        ++out.picks;
+        if (p.pk < 0) {
+            if (phase != kFinal) {  // x is the minimiser on this set
+                mode = kAccept;
+                return false;
+            }
+            mode = kEqp0;                // after steps: re-solve exactly
+        } else {
+            phase = kSteps;
+            up = 0.0;
+            mode = kStep;
+        }
+    }
+    const bool gam = D::kGam && S.gam;
+    // the vector H is applied to: grad(x) (equality solve) or c_p (step)
+    bool dep = false;
+    double sp = -p.b;
+    if (mode == kEqp0) {
+        eqp_start<MM>(Dt, S, W);
+        ++out.eqps;
+    }
+    if (mode != kStep) {
+        double r6[6];
+        g_times<MM>(Dt, W.x, true, r6);
+#pragma unroll 1
+        for (int i = 0; i < MM; ++i) {
+            if (i >= m) continue;
+            double g[3];
+            contact_grad<MM>(Dt, i, r6, W.x, g);
+#pragma unroll
+            for (int t = 0; t < 3; ++t) W.z[3 * i + t] = g[t];
+        }
+    } else {
+        // c_p into z; is it in the span of the active rows?
+        double res2 = 0.0, cn2 = 0.0, uv = 0.0, uu = 0.0;
+#pragma unroll 1
+        for (int i = 0; i < MM; ++i) {
+            if (i >= m) continue;
+            const bool on = pending_on(p, i);
+            double v[3] = {on ? p.c[0] : 0.0, on ? p.c[1] : 0.0, on ? p.c[2] : 0.0};
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                W.z[3 * i + t] = v[t];
+                sp += v[t] * W.x[3 * i + t];
+            }
+            const ContactProj P = cached_proj(S, i);
+            cn2 += dot3(v, v);
+            proj_apply(P, v);
+            res2 += dot3(v, v);
+            if (gam) {
+                double u[3];
+                sum_row_complement(P, u);
+                uv += dot3(u, v);
+                uu += dot3(u, u);
+            }
+        }
+        if (gam) res2 -= uv * uv / uu;
+        dep = !(res2 > 1e-12 * cn2);
+    }
+    if (dep) {
+#pragma unroll 1
+        for (int i = 0; i < MM; ++i) {
+            if (i >= m) continue;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) W.z[3 * i + t] = 0.0;
+        }
+    } else {
+        apply_h<MM>(Dt, S, W.z);
+    }
+
+    if (mode != kStep) {
+        // equality solve pass: x <- x - H grad(x)
+#pragma unroll 1
+        for (int i = 0; i < MM; ++i) {
+            if (i >= m) continue;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) W.x[3 * i + t] -= W.z[3 * i + t];
+        }
+        if (mode == kEqp0) {
+            mode = kEqp1;
+        } else {
+            mp = none;
+            mup = 0.0;
+            need_mult = true;
+            mode = kCheck;
+        }
+        return false;
+    }
+    // one-row step: w = c_p - P z over the active rows (r per contact,
+    // rg for the normal-sum row); the largest step keeping the
+    // multipliers nonnegative (t1) against the step that satisfies p (t2)
+    ++out.moves;
+    double cz = 0.0;
+    double gz[6];
+    g_times<MM>(Dt, W.z, false, gz);
+    double rg = 0.0;
+    if (gam) {
+        double num = 0.0, den = 0.0;
+#pragma unroll 1
+        for (int i = 0; i < MM; ++i) {
+            if (i >= m) continue;
+            double w[3], u[3];
+            contact_grad<MM>(Dt, i, gz, W.z, w);
+            const bool on = pending_on(p, i);
+#pragma unroll
+            for (int t = 0; t < 3; ++t) w[t] = (on ? p.c[t] : 0.0) - w[t];
+            sum_row_complement(cached_proj(S, i), u);
+            num += dot3(u, w);
+            den += dot3(u, u);
+        }
+        rg = num / den;
+    }
+    double t1 = INFINITY;
+    int lbit = -1;
+    if (gam && rg > 0.0) {
+        t1 = *lg / rg;
+        lbit = 9 * MM;
+    }
+#pragma unroll 1
+    for (int i = 0; i < MM; ++i) {
+        if (i >= m) continue;
+        const bool on = pending_on(p, i);
+        if (on) cz += p.c[0] * W.z[3 * i] + p.c[1] * W.z[3 * i + 1] + p.c[2] * W.z[3 * i + 2];
+        ContactRows R;
+        contact_rows(contact_mask(S.mask, i), Dt.muc[i], fm, R);
+        double w[3], r[3];
+        contact_grad<MM>(Dt, i, gz, W.z, w);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) w[t] = (on ? p.c[t] : 0.0) - w[t];
+        w[0] += rg;
+        rows_coeffs(R, w, r);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const double l = W.lam[3 * i + j];
+            if (j < R.n && r[j] > 0.0 && l / r[j] < t1) {
+                t1 = l / r[j];
+                lbit = 9 * i + R.id[j];
+            }
+        }
+    }
+    const double t2 = (dep || !(cz > 0.0)) ? INFINITY : sp / cz;
+    const double st = t2 < t1 ? t2 : t1;
+    if (!(st < INFINITY) || !(st >= 0.0)) {
+        out.status = 3;  // infeasible or broken down
+        return true;
+    }
+#pragma unroll 1
+    for (int i = 0; i < MM; ++i) {
+        if (i >= m) continue;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) W.x[3 * i + t] -= st * W.z[3 * i + t];
+    }
+    up += st;
+    refactor = true;
+    need_mult = true;
+    if (t2 <= t1) {
+        // p joins the active set; an exact re-solve follows the last step
+        if (p.pk == 9)
+            S.gam = true;
+        else
+            S.mask |= uint64_t(1) << (9 * p.pi + p.pk);
+        phase = kFinal;
+        mp = none;
+        mup = 0.0;
+        mode = kPick;
+    } else {
+        // drop the row whose multiplier reached zero, continue with p
+        if (D::kGam && lbit == 9 * MM)
+            S.gam = false;
+        else
+            S.mask &= ~(uint64_t(1) << lbit);
+        mp = p;
+        mup = up;
+        mode = kStep;
+    }
+    return false;
+}
+
+// The whole polish of one QP (see polish_begin / polish_advance).
+template <int MM, typename YP, typename D, class V>
+BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork<V>& W, PolishState<MM>& PS) {
+    polish_begin<MM>(Dt, y0, PS);
+#pragma unroll 1
+    while (!polish_advance<MM>(Dt, max_steps, W, PS)) {
+    }
+    return PS.out;
 }
 
 // Relative KKT residual (same definition as the ADMM check) of a state
