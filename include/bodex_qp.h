@@ -143,10 +143,11 @@ typedef struct {
 typedef struct bodex_qp bodex_qp_t;
 
 /* Fill *p with the defaults: m_max 5, s_max 32, fmax 1, gamma 0, beta 1,
- * eps 1e-6, torque_scale 20, tol 1e-5, 500 iterations, rho0 0.1, alpha 1.6,
+ * eps 1e-6, torque_scale 20, tol 1e-5, 500 iterations, rho0 0.3, alpha 1.6,
  * check every 10, rho in [1e-4, 1e4], hysteresis 5, fp64_cond 1e4, 128 polish
  * steps, 20 iterations per chunk, flags POLISH | ADAPTIVE_RHO, admm_waves 0,
- * admm_tol 0 (ADMM runs to tol_rel). */
+ * admm_tol 1e-2 (with the polish on, ADMM only has to find the active set
+ * roughly; the polish then solves each QP exactly). */
 void bodex_qp_default_params(bodex_qp_params *p);
 
 /* Create a handle on `device` that enqueues on `hip_stream` (a hipStream_t;

@@ -389,7 +389,7 @@ void bodex_qp_default_params(bodex_qp_params* p) {
     p->torque_scale = 20.0f;
     p->tol_rel = 1e-5f;
     p->max_iters = 500;
-    p->rho0 = 0.1f;
+    p->rho0 = 0.3f;
     p->alpha = 1.6f;
     p->check_every = 10;
     p->rho_min = 1e-4f;
@@ -400,7 +400,7 @@ void bodex_qp_default_params(bodex_qp_params* p) {
     p->iters_per_chunk = 20;
     p->flags = BODEX_F_POLISH | BODEX_F_ADAPTIVE_RHO;
     p->admm_waves = 0;
-    p->admm_tol = 0.0f;
+    p->admm_tol = 1e-2f;
 }
 
 int bodex_qp_create(const bodex_qp_params* p, int device, void* hip_stream, size_t hbm_budget_bytes,

@@ -40,6 +40,37 @@ def test_ellipsoid_m5_s16_subsets(ng):
     check_state_kkt(b, gpu, 1e-5, range(0, b.n_qps, max(1, b.n_qps // 200)))
 
 
+@pytest.mark.parametrize("admm_tol", [0.0, 1e-3, 1e30])
+def test_admm_tolerance_does_not_change_the_result(admm_tol):
+    # ADMM run to tol_rel (0), to 1e-3, or stopped at its first check (1e30):
+    # the polish reaches the same minimiser
+    b = wl.config(1, 96)
+    gpu = run_gpu(b, admm_tol=admm_tol)
+    ref = _ref(b)
+    print("admm_tol %g:" % admm_tol, check_forward(b, gpu, ref), "iters mean", gpu["iters"].mean())
+    check_energy(b, gpu, ref)
+
+
+def test_polish_flop_count_is_reported():
+    import torch
+    b = wl.config(1, 32)
+    p = api.default_params(m_max=5, s_max=16)
+    s = api.Solver(p)
+    db = api.DeviceBatch(b)
+    r = api.new_result(db.n_grasps, db.n_qps, 5, polish_flops=True)
+    s.solve(db, result=r)
+    torch.cuda.synchronize()
+    fl = r["polish_flops"].cpu().numpy()
+    # at least the warm start, one factorisation, one equality solve and the
+    # acceptance check of a 5-contact QP
+    assert np.all(fl >= 3 * 249 * 5 + 150 * 5 + 231 * 5 + 100 + 530 * 5 + 144)
+    r2 = api.new_result(db.n_grasps, db.n_qps, 5)          # no flop output: still fine
+    s.solve(db, result=r2)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(r2["forces"].cpu().numpy(), r["forces"].cpu().numpy())
+    s.close()
+
+
 def test_mixed_m45_uneven_s():
     b = wl.config(3, 300)
     gpu = run_gpu(b)
