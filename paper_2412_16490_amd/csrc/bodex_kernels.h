@@ -514,9 +514,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) 
 template <int MM>
 struct FinLds {
     static constexpr int NV = 3 * MM, NG = 6 * NV;
-    // per lane, lane-interleaved: the polish's x, z, multipliers (3 NV) and
-    // projector cache (4 MM)
-    static constexpr int NW = (3 * NV + 4 * MM) * kWave;
+    // per lane, lane-interleaved: the polish's x, z (2 NV) and projector
+    // cache (3 MM)
+    static constexpr int NW = (2 * NV + 3 * MM) * kWave;
     // per slot: G64, muc64 (8); the polish space; finalize: the energy
     // reduction (one per lane); backward: Gbar per slot, and the gradient
     // reduction 6 + NV per lane, which reuses the polish space once every
@@ -567,13 +567,12 @@ __device__ inline PolishWork<LaneVec> polish_work(const FinPtrs<MM>& P, int lane
     PolishWork<LaneVec> W;
     W.x = LaneVec{P.work + lane, kWave};
     W.z = LaneVec{P.work + NV * kWave + lane, kWave};
-    W.lam = LaneVec{P.work + 2 * NV * kWave + lane, kWave};
     return W;
 }
 
 template <int MM>
 __device__ inline LaneVec projector_cache(const FinPtrs<MM>& P, int lane) {
-    return LaneVec{P.work + 3 * 3 * MM * kWave + lane, kWave};
+    return LaneVec{P.work + 2 * 3 * MM * kWave + lane, kWave};
 }
 
 // Returns whether the lane's grasp has finite, valid inputs.
@@ -682,13 +681,21 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) fi
                     // ADMM-form state of the polished point: z = A x projected
                     // on [l, u] (the bound itself on active rows), y = the
                     // multipliers of the active rows
-                    double s1 = 0.0;
+                    double s1 = 0.0, r6[6];
+                    g_times<MM>(D, W.x, true, r6);
+                    const PendingRow none = {-1, -1, {0.0, 0.0, 0.0}, 0.0};
 #pragma unroll 1
                     for (int i = 0; i < a.ms; ++i) {
                         const bool live = i < si.m;
                         const double f[3] = {live ? W.x[3 * i] : 0.0, live ? W.x[3 * i + 1] : 0.0,
                                              live ? W.x[3 * i + 2] : 0.0};
                         const unsigned mk = live ? contact_mask(S.mask, i) : 0u;
+                        double lam[3] = {0.0, 0.0, 0.0};
+                        if (live) {
+                            ContactRows R;
+                            contact_rows(mk, muc[i], D.fmax, R);
+                            contact_multipliers<MM>(D, R, W.x, r6, i, none, 0.0, lg, lam);
+                        }
 #pragma unroll
                         for (int c = 0; c < 3; ++c) a.x[size_t(3 * i + c) * W_ + w] = float(f[c]);
 #pragma unroll
@@ -700,7 +707,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) fi
                             const int jr = __builtin_popcount(mk & ((1u << kk) - 1u));
                             const float zv = on ? (kk == 8 ? a.fmax : 0.f)
                                                 : row_proj(9 * i + kk, MM, float(zz), a.fmax, a.gamma);
-                            const float yv = on ? float(W.lam[3 * i + jr]) : 0.f;
+                            const float yv = on ? float(jr == 0 ? lam[0] : (jr == 1 ? lam[1] : lam[2])) : 0.f;
                             a.z[size_t(9 * i + kk) * W_ + w] = zv;
                             a.y[size_t(9 * i + kk) * W_ + w] = yv;
                         }

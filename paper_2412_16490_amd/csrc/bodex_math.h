@@ -466,25 +466,32 @@ BODEX_FI void contact_rows(unsigned mask, double muc, double fm, ContactRows& R)
     }
 }
 
-// Null-space projector of one contact, Pi v = a v + k (e . v) e: with n
-// active rows, n = 0: a = 1, k = 0; n = 1: e the row, a = 1, k = -1/|e|^2;
-// n = 2: e = c0 x c1, a = 0, k = 1/|e|^2; n = 3: a = k = 0.
+// Null-space projector of one contact, Pi v = a v + k (e . v) e with e a
+// unit vector: with n active rows, n = 0: a = 1, k = 0; n = 1: e along the
+// row, a = 1, k = -1; n = 2: e along c0 x c1, a = 0, k = 1; n = 3: a = k = 0.
 struct ContactProj {
     double e[3];
     double k, a;
 };
 
+BODEX_FI void proj_coeffs(int n, ContactProj& P) {
+    P.k = (n == 1) ? -1.0 : (n == 2 ? 1.0 : 0.0);
+    P.a = (n <= 1) ? 1.0 : 0.0;
+}
+
 BODEX_FI void contact_proj(const ContactRows& R, ContactProj& P) {
+    double e[3];
     if (R.n == 2) {
-        cross3(R.c[0], R.c[1], P.e);
+        cross3(R.c[0], R.c[1], e);
     } else {
-        P.e[0] = R.c[0][0];
-        P.e[1] = R.c[0][1];
-        P.e[2] = R.c[0][2];
+        e[0] = R.c[0][0];
+        e[1] = R.c[0][1];
+        e[2] = R.c[0][2];
     }
-    const double ie = 1.0 / dot3(P.e, P.e);
-    P.k = (R.n == 1) ? -ie : (R.n == 2 ? ie : 0.0);
-    P.a = (R.n <= 1) ? 1.0 : 0.0;
+    const double s = (R.n == 1 || R.n == 2) ? 1.0 / sqrt(dot3(e, e)) : 0.0;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) P.e[t] = s * e[t];
+    proj_coeffs(R.n, P);
 }
 
 BODEX_FI void proj_apply(const ContactProj& P, double* v) {
@@ -623,11 +630,10 @@ struct RegVec {
     BODEX_FI double& operator[](int c) const { return p[c]; }
 };
 
-// The polish's per-lane vectors: x and z (3 m each) and the multipliers of
-// the active rows (3 per contact, ascending row order).
+// The polish's per-lane vectors: the point x and the step z (3 m each).
 template <class V>
 struct PolishWork {
-    V x, z, lam;
+    V x, z;
 };
 
 // Active set: bit 9i+kk of mask is row kk of contact i; gam: the normal-sum
@@ -638,7 +644,7 @@ struct ActiveSet {
     uint64_t mask;
     bool gam;
     Sym6 L;
-    LaneVec pc;  // per contact: e (3), k of its projector (a follows from the mask)
+    LaneVec pc;  // per contact: the unit e of its projector (a, k follow from the mask)
 };
 
 BODEX_FI unsigned contact_mask(uint64_t mask, int i) { return unsigned(mask >> (9 * i)) & 0x1FFu; }
@@ -652,11 +658,10 @@ BODEX_FI void contact_geom(const D& Dt, const ActiveSet<MM>& S, int i, ContactRo
 template <int MM>
 BODEX_FI ContactProj cached_proj(const ActiveSet<MM>& S, int i) {
     ContactProj P;
-    P.e[0] = S.pc[4 * i];
-    P.e[1] = S.pc[4 * i + 1];
-    P.e[2] = S.pc[4 * i + 2];
-    P.k = S.pc[4 * i + 3];
-    P.a = __builtin_popcount(contact_mask(S.mask, i)) <= 1 ? 1.0 : 0.0;
+    P.e[0] = S.pc[3 * i];
+    P.e[1] = S.pc[3 * i + 1];
+    P.e[2] = S.pc[3 * i + 2];
+    proj_coeffs(__builtin_popcount(contact_mask(S.mask, i)), P);
     return P;
 }
 
@@ -811,8 +816,7 @@ BODEX_FI bool factor_set(const D& Dt, ActiveSet<MM>& S) {
         ContactProj P;
         contact_geom(Dt, S, i, R, P);
 #pragma unroll
-        for (int t = 0; t < 3; ++t) S.pc[4 * i + t] = P.e[t];
-        S.pc[4 * i + 3] = P.k;
+        for (int t = 0; t < 3; ++t) S.pc[3 * i + t] = P.e[t];
         double b[6][3];
 #pragma unroll
         for (int k = 0; k < 6; ++k)
@@ -854,47 +858,41 @@ struct PendingRow {
 BODEX_FI bool pending_on(const PendingRow& p, int i) { return p.pk == 9 || (p.pk >= 0 && i == p.pi); }
 
 // Multipliers from stationarity at x with a partial multiplier up on the
-// pending row: -grad(x) - up c_p = sum_i C_i^T lam_i + lg a.  Uses the
-// projectors of the last factorisation (callers refactor first).
+// pending row: -grad(x) - up c_p = sum_i C_i^T lam_i + lg a.  They are not
+// stored: sum_row_multiplier gives lg (a least-squares fit over the
+// contacts' null spaces, using the projectors of the last factorisation),
+// contact_multipliers contact i's lam_i (ascending row order) when needed.
+// r6 = G x - beta t.
 template <int MM, typename D, class V>
-BODEX_FI void stationary_multipliers(const D& Dt, const ActiveSet<MM>& S, const PolishWork<V>& W,
-                                     const PendingRow& p, double up, double* lg) {
-    const bool gam = D::kGam && S.gam;
-    double r6[6];
-    g_times<MM>(Dt, W.x, true, r6);
-    double ug = 0.0;
-    if (gam) {
-        double num = 0.0, den = 0.0;
-#pragma unroll 1
-        for (int i = 0; i < MM; ++i) {
-            if (i >= Dt.m) continue;
-            double h[3], u[3];
-            contact_grad<MM>(Dt, i, r6, W.x, h);
-            const bool on = pending_on(p, i);
-#pragma unroll
-            for (int t = 0; t < 3; ++t) h[t] = -h[t] - (on ? up * p.c[t] : 0.0);
-            sum_row_complement(cached_proj(S, i), u);
-            num += dot3(u, h);
-            den += dot3(u, u);
-        }
-        ug = num / den;
-    }
-    *lg = ug;
+BODEX_FI double sum_row_multiplier(const D& Dt, const ActiveSet<MM>& S, const V& x, const double* r6,
+                                   const PendingRow& p, double up) {
+    if (!(D::kGam && S.gam)) return 0.0;
+    double num = 0.0, den = 0.0;
 #pragma unroll 1
     for (int i = 0; i < MM; ++i) {
         if (i >= Dt.m) continue;
-        ContactRows R;
-        contact_rows(contact_mask(S.mask, i), Dt.muc[i], Dt.fmax, R);
-        double h[3], r[3];
-        contact_grad<MM>(Dt, i, r6, W.x, h);
+        double h[3], u[3];
+        contact_grad<MM>(Dt, i, r6, x, h);
         const bool on = pending_on(p, i);
 #pragma unroll
         for (int t = 0; t < 3; ++t) h[t] = -h[t] - (on ? up * p.c[t] : 0.0);
-        h[0] += ug;
-        rows_coeffs(R, h, r);
-#pragma unroll
-        for (int j = 0; j < 3; ++j) W.lam[3 * i + j] = r[j];
+        sum_row_complement(cached_proj(S, i), u);
+        num += dot3(u, h);
+        den += dot3(u, u);
     }
+    return num / den;
+}
+
+template <int MM, typename D, class V>
+BODEX_FI void contact_multipliers(const D& Dt, const ContactRows& R, const V& x, const double* r6, int i,
+                                  const PendingRow& p, double up, double lg, double* lam) {
+    double h[3];
+    contact_grad<MM>(Dt, i, r6, x, h);
+    const bool on = pending_on(p, i);
+#pragma unroll
+    for (int t = 0; t < 3; ++t) h[t] = -h[t] - (on ? up * p.c[t] : 0.0);
+    h[0] += lg;
+    rows_coeffs(R, h, lam);
 }
 
 // Start of the equality-constrained solve: x <- a point on the active rows
@@ -986,25 +984,25 @@ struct PolishOut {
 //                         (projection 15, two dots 10, scale 1))
 //   factorisation         231 m + 100  (6 projected G rows, 21 dots, 6x6 Cholesky 97)
 //   reduced solve H v     108 m + 72   (two projections, G v, G^T w, 6x6 solves 72)
-//   equality solve        530 m + 144  (start point 36 m, two passes of gradient 78 m
-//                         + H v + update 3 m, multipliers 116 m)
-//   one-row step          380 m + 77   (direction 31 m + H v, G z 36 m, ratio test
-//                         83 m, update 6 m, multipliers 116 m)
+//   equality solve        527 m + 144  (start point 36 m, two passes of gradient 78 m
+//                         + H v + update 3 m, multiplier check 113 m)
+//   one-row step          377 m + 77   (direction 31 m + H v, G z 36 m, ratio test
+//                         83 m and the multipliers at x 113 m, update 6 m)
 //   violated-row search   54 m
-//   acceptance            150 m
+//   acceptance            227 m
 BODEX_FI double polish_flops(int m, const PolishOut& o) {
     const double dm = m;
-    return 3.0 * 249.0 * dm + 150.0 * dm + o.steps * (231.0 * dm + 100.0) + o.eqps * (530.0 * dm + 144.0) +
-           o.moves * (380.0 * dm + 77.0) + o.picks * 54.0 * dm;
+    return 3.0 * 249.0 * dm + 227.0 * dm + o.steps * (231.0 * dm + 100.0) + o.eqps * (527.0 * dm + 144.0) +
+           o.moves * (377.0 * dm + 77.0) + o.picks * 54.0 * dm;
 }
 
 // The polish of one QP, as a resumable state machine: polish_begin sets the
 // warm active set, each polish_advance takes one step of the method and
 // returns true once the QP is finished (PS.out.status set: accepted or not).
-// On finish W.x holds the point, PS.S the active set and W.lam, PS.lg its
-// multipliers.  y0: ADMM-form duals (rows 9i+kk and the normal-sum row
-// 9 MM); rows with positive dual (negative for the normal-sum row) seed the
-// active set.
+// On finish W.x holds the point, PS.S the active set and PS.lg the
+// normal-sum multiplier (contact_multipliers gives the others).  y0:
+// ADMM-form duals (rows 9i+kk and the normal-sum row 9 MM); rows with
+// positive dual (negative for the normal-sum row) seed the active set.
 //
 // The method, in order: (1) on the warm set, the minimiser with the active
 // rows as equalities (x <- x0 - H grad(x0), twice); while a multiplier is
@@ -1122,10 +1120,12 @@ BODEX_FI bool polish_accept(const D& Dt, const PolishWork<V>& W, PolishState<MM>
         double st[3] = {g[0] - (gam ? *lg : 0.0), g[1], g[2]};
         ContactRows R;
         contact_rows(contact_mask(S.mask, i), Dt.muc[i], fm, R);
+        double lam[3];
+        contact_multipliers<MM>(Dt, R, W.x, r6, i, PendingRow{-1, -1, {0.0, 0.0, 0.0}, 0.0}, 0.0, *lg, lam);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             if (j >= R.n) continue;
-            const double l = W.lam[3 * i + j];
+            const double l = lam[j];
 #pragma unroll
             for (int t = 0; t < 3; ++t) st[t] += l * R.c[j][t];
             lneg = fmax(lneg, -l);
@@ -1180,7 +1180,14 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
         refactor = false;
     }
     if (need_mult) {
-        stationary_multipliers<MM>(Dt, S, W, mp, mup, lg);
+        // the normal-sum multiplier of the new point / set (the per-contact
+        // multipliers are computed where they are used)
+        *lg = 0.0;
+        if (D::kGam && S.gam) {
+            double r6[6];
+            g_times<MM>(Dt, W.x, true, r6);
+            *lg = sum_row_multiplier<MM>(Dt, S, W.x, r6, mp, mup);
+        }
         need_mult = false;
     }
     if (mode == kCheck) {
@@ -1197,20 +1204,20 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
                 wv = *lg;
                 wbit = 9 * MM;
             }
+            double r6[6];
+            g_times<MM>(Dt, W.x, true, r6);
 #pragma unroll 1
             for (int i = 0; i < MM; ++i) {
                 if (i >= m) continue;
-                const unsigned mk = contact_mask(S.mask, i);
-                const int n = __builtin_popcount(mk);
-                unsigned rest = mk;
+                ContactRows R;
+                contact_rows(contact_mask(S.mask, i), Dt.muc[i], fm, R);
+                double lam[3];
+                contact_multipliers<MM>(Dt, R, W.x, r6, i, mp, mup, *lg, lam);
 #pragma unroll
                 for (int j = 0; j < 3; ++j) {
-                    const int id = rest ? __builtin_ctz(rest) : 8;
-                    rest &= rest - 1u;
-                    const double l = W.lam[3 * i + j];
-                    if (j < n && l < wv) {
-                        wv = l;
-                        wbit = 9 * i + id;
+                    if (j < R.n && lam[j] < wv) {
+                        wv = lam[j];
+                        wbit = 9 * i + R.id[j];
                     }
                 }
             }
@@ -1348,6 +1355,8 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
         t1 = *lg / rg;
         lbit = 9 * MM;
     }
+    double r6x[6];
+    g_times<MM>(Dt, W.x, true, r6x);
 #pragma unroll 1
     for (int i = 0; i < MM; ++i) {
         if (i >= m) continue;
@@ -1355,17 +1364,17 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
         if (on) cz += p.c[0] * W.z[3 * i] + p.c[1] * W.z[3 * i + 1] + p.c[2] * W.z[3 * i + 2];
         ContactRows R;
         contact_rows(contact_mask(S.mask, i), Dt.muc[i], fm, R);
-        double w[3], r[3];
+        double w[3], r[3], lam[3];
         contact_grad<MM>(Dt, i, gz, W.z, w);
 #pragma unroll
         for (int t = 0; t < 3; ++t) w[t] = (on ? p.c[t] : 0.0) - w[t];
         w[0] += rg;
         rows_coeffs(R, w, r);
+        contact_multipliers<MM>(Dt, R, W.x, r6x, i, mp, mup, *lg, lam);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            const double l = W.lam[3 * i + j];
-            if (j < R.n && r[j] > 0.0 && l / r[j] < t1) {
-                t1 = l / r[j];
+            if (j < R.n && r[j] > 0.0 && lam[j] / r[j] < t1) {
+                t1 = lam[j] / r[j];
                 lbit = 9 * i + R.id[j];
             }
         }

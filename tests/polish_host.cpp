@@ -21,8 +21,8 @@ int solve_one(const double* G, const double* muc, const double* bt, int m, doubl
     D.fmax = fmax;
     D.gamma = gamma;
     D.eps = eps;
-    double xb[NV] = {}, zb[NV] = {}, lb[NV] = {}, pcb[4 * MM] = {};
-    PolishWork<LaneVec> W{{xb, 1}, {zb, 1}, {lb, 1}};
+    double xb[NV] = {}, zb[NV] = {}, pcb[3 * MM] = {};
+    PolishWork<LaneVec> W{{xb, 1}, {zb, 1}};
     PolishState<MM> PS;
     PS.S.pc = LaneVec{pcb, 1};
     const PolishOut po = polish_qp<MM>(D, y0, max_steps, W, PS);
