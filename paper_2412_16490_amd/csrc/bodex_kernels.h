@@ -24,6 +24,10 @@
 
 namespace bodex {
 
+// Keep each contact's projector in LDS between factorisations (else it is
+// recomputed from the active rows where needed, which leaves more LDS for
+// resident waves).
+constexpr bool kProjectorCache = false;
 constexpr int kMaxSlots = 12;  // keeps every kernel under 64 KB of LDS
 constexpr int kWave = 64;
 
@@ -514,9 +518,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) 
 template <int MM>
 struct FinLds {
     static constexpr int NV = 3 * MM, NG = 6 * NV;
-    // per lane, lane-interleaved: the polish's x, z (2 NV) and projector
-    // cache (3 MM)
-    static constexpr int NW = (2 * NV + 3 * MM) * kWave;
+    // per lane, lane-interleaved: the polish's x, z (2 NV) and, when
+    // kProjectorCache, the projector cache (3 MM)
+    static constexpr int NW = (2 * NV + (kProjectorCache ? 3 * MM : 0)) * kWave;
     // per slot: G64, muc64 (8); the polish space; finalize: the energy
     // reduction (one per lane); backward: Gbar per slot, and the gradient
     // reduction 6 + NV per lane, which reuses the polish space once every
@@ -572,6 +576,7 @@ __device__ inline PolishWork<LaneVec> polish_work(const FinPtrs<MM>& P, int lane
 
 template <int MM>
 __device__ inline LaneVec projector_cache(const FinPtrs<MM>& P, int lane) {
+    if (!kProjectorCache) return LaneVec{nullptr, 0};
     return LaneVec{P.work + 2 * 3 * MM * kWave + lane, kWave};
 }
 

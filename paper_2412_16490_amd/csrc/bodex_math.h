@@ -655,9 +655,17 @@ BODEX_FI void contact_geom(const D& Dt, const ActiveSet<MM>& S, int i, ContactRo
     contact_proj(R, P);
 }
 
-template <int MM>
-BODEX_FI ContactProj cached_proj(const ActiveSet<MM>& S, int i) {
+// Contact i's projector: from the cache the last factorisation filled, or,
+// when no cache is attached (pc.p null), recomputed from the active rows.
+template <typename D, int MM>
+BODEX_FI ContactProj cached_proj(const D& Dt, const ActiveSet<MM>& S, int i) {
     ContactProj P;
+    if (S.pc.p == nullptr) {
+        ContactRows R;
+        contact_rows(contact_mask(S.mask, i), Dt.muc[i], Dt.fmax, R);
+        contact_proj(R, P);
+        return P;
+    }
     P.e[0] = S.pc[3 * i];
     P.e[1] = S.pc[3 * i + 1];
     P.e[2] = S.pc[3 * i + 2];
@@ -707,7 +715,7 @@ BODEX_FI void apply_h(const D& Dt, const ActiveSet<MM>& S, const V& v) {
 #pragma unroll 1
     for (int i = 0; i < MM; ++i) {
         if (i >= m) continue;
-        const ContactProj P = cached_proj(S, i);
+        const ContactProj P = cached_proj(Dt, S, i);
         double f[3] = {v[3 * i], v[3 * i + 1], v[3 * i + 2]};
         proj_apply(P, f);
         if (gam) {
@@ -729,7 +737,7 @@ BODEX_FI void apply_h(const D& Dt, const ActiveSet<MM>& S, const V& v) {
         double f[3] = {v[3 * i], v[3 * i + 1], v[3 * i + 2]};
         if (gam) {
             double u[3];
-            sum_row_complement(cached_proj(S, i), u);
+            sum_row_complement(cached_proj(Dt, S, i), u);
 #pragma unroll
             for (int t = 0; t < 3; ++t) {
                 f[t] -= su * u[t];
@@ -756,7 +764,7 @@ BODEX_FI void apply_h(const D& Dt, const ActiveSet<MM>& S, const V& v) {
             for (int k = 0; k < 6; ++k) s += Dt.G[k * NV + 3 * i + t] * gv[k];
             t3[t] = s;
         }
-        const ContactProj P = cached_proj(S, i);
+        const ContactProj P = cached_proj(Dt, S, i);
         proj_apply(P, t3);
         if (gam) {
             double u[3];
@@ -772,7 +780,7 @@ BODEX_FI void apply_h(const D& Dt, const ActiveSet<MM>& S, const V& v) {
         for (int i = 0; i < MM; ++i) {
             if (i >= m) continue;
             double u[3];
-            sum_row_complement(cached_proj(S, i), u);
+            sum_row_complement(cached_proj(Dt, S, i), u);
 #pragma unroll
             for (int t = 0; t < 3; ++t) v[3 * i + t] += sc * u[t];
         }
@@ -815,8 +823,10 @@ BODEX_FI bool factor_set(const D& Dt, ActiveSet<MM>& S) {
         ContactRows R;
         ContactProj P;
         contact_geom(Dt, S, i, R, P);
+        if (S.pc.p != nullptr) {
 #pragma unroll
-        for (int t = 0; t < 3; ++t) S.pc[3 * i + t] = P.e[t];
+            for (int t = 0; t < 3; ++t) S.pc[3 * i + t] = P.e[t];
+        }
         double b[6][3];
 #pragma unroll
         for (int k = 0; k < 6; ++k)
@@ -876,7 +886,7 @@ BODEX_FI double sum_row_multiplier(const D& Dt, const ActiveSet<MM>& S, const V&
         const bool on = pending_on(p, i);
 #pragma unroll
         for (int t = 0; t < 3; ++t) h[t] = -h[t] - (on ? up * p.c[t] : 0.0);
-        sum_row_complement(cached_proj(S, i), u);
+        sum_row_complement(cached_proj(Dt, S, i), u);
         num += dot3(u, h);
         den += dot3(u, u);
     }
@@ -909,7 +919,7 @@ BODEX_FI void eqp_start(const D& Dt, const ActiveSet<MM>& S, const PolishWork<V>
         contact_rows(contact_mask(S.mask, i), Dt.muc[i], Dt.fmax, R);
         double f[3], u[3];
         rows_point(R, f);
-        sum_row_complement(cached_proj(S, i), u);
+        sum_row_complement(cached_proj(Dt, S, i), u);
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
             W.x[3 * i + t] = f[t];
@@ -1282,7 +1292,7 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
                 W.z[3 * i + t] = v[t];
                 sp += v[t] * W.x[3 * i + t];
             }
-            const ContactProj P = cached_proj(S, i);
+            const ContactProj P = cached_proj(Dt, S, i);
             cn2 += dot3(v, v);
             proj_apply(P, v);
             res2 += dot3(v, v);
@@ -1343,7 +1353,7 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
             const bool on = pending_on(p, i);
 #pragma unroll
             for (int t = 0; t < 3; ++t) w[t] = (on ? p.c[t] : 0.0) - w[t];
-            sum_row_complement(cached_proj(S, i), u);
+            sum_row_complement(cached_proj(Dt, S, i), u);
             num += dot3(u, w);
             den += dot3(u, u);
         }
