@@ -270,6 +270,29 @@ def forms(torch, api, wl):
                                  "qps_per_s": round(convp / tp, 1), "converged": convp}
         for sv, _, _, _ in outs:
             sv.close()
+    # the paper's force-closure energy on the headline grasps: six force-axis
+    # wrenches per grasp with the normal-sum row (gamma = 0.5), and the beta = 0
+    # QP baseline (gamma = 1)
+    bfa = wl.force_axis_batch(wl.config(1))
+    dfa = api.DeviceBatch(bfa)
+    for name, gamma, beta in (("force_axis_gamma0.5", 0.5, 1.0), ("qp_baseline_beta0_gamma1", 1.0, 0.0)):
+        pf = api.default_params(m_max=5, s_max=6)
+        pf.gamma = gamma
+        pf.beta = beta
+        sf = api.Solver(pf)
+        stf = api.new_state(dfa.n_grasps, dfa.n_qps, 5)
+        rf = api.new_result(dfa.n_grasps, dfa.n_qps, 5)
+        sf.solve(dfa, state=stf, result=rf)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            sf.solve(dfa, state=stf, result=rf)
+        torch.cuda.synchronize()
+        tf = (time.perf_counter() - t0) / 5
+        convf = int(np.sum((rf["status"].cpu().numpy() & api.ST_CONVERGED) != 0))
+        res[name] = {"workload": "ellipsoid-m5, 8192 grasps x 6 force-axis wrenches (%d QPs)" % dfa.n_qps,
+                     "ms": round(tf * 1e3, 3), "qps_per_s": round(convf / tf, 1), "converged": convf}
+        sf.close()
     # forward + backward (differentiation workload, same shape as the headline)
     b2 = wl.config(2)
     db2 = api.DeviceBatch(b2)

@@ -75,6 +75,22 @@ def wrench_dirs(rng: np.random.Generator, w: int) -> np.ndarray:
     return (v / np.linalg.norm(v, axis=-1, keepdims=True)).astype(np.float32)
 
 
+FORCE_AXIS_WRENCHES = np.array([[1, 0, 0, 0, 0, 0], [-1, 0, 0, 0, 0, 0],
+                                [0, 1, 0, 0, 0, 0], [0, -1, 0, 0, 0, 0],
+                                [0, 0, 1, 0, 0, 0], [0, 0, -1, 0, 0, 0]], dtype=np.float32)
+
+
+def force_axis_batch(batch: "Batch") -> "Batch":
+    """The same grasps with the six desired wrenches the paper uses for
+    force closure (Sec. IV-A): unit forces along +-x, +-y, +-z with zero
+    torque, for every grasp."""
+    g = batch.n_grasps
+    woff = (6 * np.arange(g + 1)).astype(np.int32)
+    wrench = np.tile(FORCE_AXIS_WRENCHES, (g, 1))
+    return Batch(batch.points.copy(), batch.normals.copy(), batch.mu.copy(), wrench,
+                 batch.counts.copy(), woff, batch.name + "[force-axis wrenches]")
+
+
 def sphere_contacts(rng, n_grasps, m, radius=0.05):
     u = unit_sphere(rng, (n_grasps, m))
     return (radius * u).astype(np.float32), (-u).astype(np.float32)

@@ -71,6 +71,18 @@ def test_polish_flop_count_is_reported():
     s.close()
 
 
+@pytest.mark.parametrize("gamma,beta", [(0.0, 1.0), (0.5, 1.0), (1.0, 0.0)])
+def test_force_axis_wrenches(gamma, beta):
+    # the paper's force-closure energy: the six unit force-axis wrenches per
+    # grasp (Sec. IV-A), with the normal-sum row of Eq. 9; beta = 0 is the
+    # QP baseline of the comparison in Sec. V
+    b = wl.force_axis_batch(wl.config(1, 128))
+    gpu = run_gpu(b, gamma=gamma, beta=beta)
+    ref = _ref(b, oracle_params(gamma=gamma, beta=beta))
+    print("force axes gamma %g beta %g:" % (gamma, beta), check_forward(b, gpu, ref, beta=beta))
+    check_energy(b, gpu, ref, beta=beta)
+
+
 def test_mixed_m45_uneven_s():
     b = wl.config(3, 300)
     gpu = run_gpu(b)
