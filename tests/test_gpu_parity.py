@@ -141,6 +141,39 @@ def test_small_contact_counts_in_m5_layout():
     check_energy(b, gpu, ref)
 
 
+def test_extreme_sizes():
+    # 64 wrenches per grasp (the largest s), single-contact grasps, and a
+    # 4-contact layout (m_max = 4 kernels) in one test
+    b64 = wl.uniform_batch(777, 9, 5, 64, name="s64")
+    gpu = run_gpu(b64)
+    ref = _ref(b64)
+    print("s=64:", check_forward(b64, gpu, ref))
+    check_energy(b64, gpu, ref)
+    b1 = wl.uniform_batch(778, 40, 1, 7, name="m1")
+    gpu = run_gpu(b1)
+    ref = _ref(b1)
+    print("m=1:", check_forward(b1, gpu, ref))
+    check_energy(b1, gpu, ref)
+    b4 = wl.uniform_batch(779, 70, 4, 13, name="m4")
+    gpu = run_gpu(b4)
+    ref = _ref(b4)
+    print("m=4 layout:", check_forward(b4, gpu, ref))
+    check_energy(b4, gpu, ref)
+
+
+def test_empty_batch_is_a_no_op():
+    import torch
+    b = wl.uniform_batch(780, 4, 5, 3)
+    e = b.subset([])
+    p = api.default_params(m_max=5, s_max=8)
+    s = api.Solver(p)
+    db = api.DeviceBatch(e)
+    r = s.solve(db)
+    torch.cuda.synchronize()
+    assert r["forces"].shape[0] == 0 and s.stats()["launches"] == 0
+    s.close()
+
+
 def test_graph_replay_matches_direct_launch():
     # capture on a side stream, replay several times with eager work between,
     # and compare every replay with a direct launch
