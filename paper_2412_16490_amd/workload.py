@@ -211,3 +211,83 @@ def request_stream(seed=CONFIG_SEEDS[4], rate=200.0, duration=60.0,
             walk[:, g, b.counts[g]:] = 0.0
         yield Request(rid, t, b, steps, walk)
         rid += 1
+
+
+@dataclasses.dataclass
+class FineContacts:
+    """Inputs of the fine-stage surrogate energies (Sec. IV-C, Eq. 10-11).
+
+    link_rot   [G, m_max, 3, 3]  R_i of the link carrying fingertip i (row-major)
+    link_trans [G, m_max, 3]     T_i
+    hand_fine  [G, m_max, 3]     c^f_{i,w}: nearest point on fingertip i (world)
+    obj_fine   [G, m_max, 3]     p^f_i: nearest point on the object
+    obj_coarse [G, m_max, 3]     p^c_i: object point from the end of the coarse stage
+    counts     [G] int32         fingertips per grasp
+    w_q, w_e   [G]               loss weights of Q' and of E^f_d
+    Padding contacts hold R = I and zero points.
+    """
+    link_rot: np.ndarray
+    link_trans: np.ndarray
+    hand_fine: np.ndarray
+    obj_fine: np.ndarray
+    obj_coarse: np.ndarray
+    counts: np.ndarray
+    w_q: np.ndarray
+    w_e: np.ndarray
+
+    @property
+    def n_grasps(self) -> int:
+        return int(self.counts.shape[0])
+
+    @property
+    def m_max(self) -> int:
+        return int(self.link_trans.shape[1])
+
+
+def random_rotations(rng, shape) -> np.ndarray:
+    """Uniform rotations from normalised Gaussian quaternions."""
+    q = rng.standard_normal(tuple(shape) + (4,))
+    q /= np.linalg.norm(q, axis=-1, keepdims=True)
+    w, x, y, z = q[..., 0], q[..., 1], q[..., 2], q[..., 3]
+    R = np.empty(tuple(shape) + (3, 3))
+    R[..., 0, 0] = 1 - 2 * (y * y + z * z)
+    R[..., 0, 1] = 2 * (x * y - w * z)
+    R[..., 0, 2] = 2 * (x * z + w * y)
+    R[..., 1, 0] = 2 * (x * y + w * z)
+    R[..., 1, 1] = 1 - 2 * (x * x + z * z)
+    R[..., 1, 2] = 2 * (y * z - w * x)
+    R[..., 2, 0] = 2 * (x * z - w * y)
+    R[..., 2, 1] = 2 * (y * z + w * x)
+    R[..., 2, 2] = 1 - 2 * (x * x + y * y)
+    return R
+
+
+def fine_contacts(seed, n_grasps, m=5, m_choices=None, tip=0.02, gap=2e-3, drift=1e-3):
+    """Fingertips on ellipsoid objects at the end of the coarse stage: p^c on
+    the surface, the fine nearest points within a few mm of it (gap: fingertip
+    offset, drift: coarse-to-fine shift of the object point), each link's
+    origin `tip` metres behind its fingertip point along a random direction
+    of the link frame."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if m_choices is None:
+        counts = np.full(n_grasps, m, np.int32)
+        m_max = m
+    else:
+        counts = rng.choice(np.asarray(m_choices, np.int32), size=n_grasps)
+        m_max = int(max(m_choices))
+    pc, _ = ellipsoid_contacts(rng, n_grasps, m_max)
+    pc = pc.astype(np.float64)
+    pf = pc + drift * rng.standard_normal(pc.shape)
+    cw = pf + gap * rng.standard_normal(pc.shape)
+    R = random_rotations(rng, (n_grasps, m_max))
+    c_l = tip * unit_sphere(rng, (n_grasps, m_max))
+    T = cw - np.einsum("gmij,gmj->gmi", R, c_l)
+    wq = rng.uniform(0.5, 2.0, n_grasps)
+    we = rng.uniform(0.5, 2.0, n_grasps)
+    pad = np.arange(m_max)[None, :] >= counts[:, None]
+    R[pad] = np.eye(3)
+    for a in (T, cw, pf, pc):
+        a[pad] = 0.0
+    f32 = lambda a: np.ascontiguousarray(a, np.float32)
+    return FineContacts(f32(R), f32(T), f32(cw), f32(pf), f32(pc), counts.astype(np.int32),
+                        f32(wq), f32(we))
