@@ -35,19 +35,6 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_TFLOPS = 78.6
 PEAK_FP64_TFLOPS = 78.6
 PROFILES = os.path.join(ROOT, "profiles")
-KERNEL_SOURCES = os.path.join(ROOT, "paper_2412_16490_amd", "csrc")
-
-
-def kernel_source_hash() -> str:
-    """Hash of the HIP sources; a traffic figure measured on other sources is
-    not reported."""
-    import hashlib
-    h = hashlib.sha256()
-    for f in sorted(os.listdir(KERNEL_SOURCES)):
-        if f.endswith((".h", ".hip")):
-            with open(os.path.join(KERNEL_SOURCES, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
-    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str):
@@ -63,7 +50,8 @@ def measured_traffic(kernel: str):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("source_hash") != kernel_source_hash():
+    from paper_2412_16490_amd.profile_summary import kernel_source_hash
+    if vals.get("source_hash") != kernel_source_hash(kernel):
         return None
     try:
         return float(vals["bytes_per_launch"])
@@ -96,6 +84,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=0.5,
                     help="length of the Poisson arrival window of the served form")
     ap.add_argument("--admm-waves", type=int, default=0, help="ADMM register budget (0 = default)")
+    ap.add_argument("--detach-only", action="store_true",
+                    help="only run the fine-stage surrogate (Detach) form at 2^20 grasps and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run device copies of MIB MiB (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -125,6 +115,9 @@ def main():
     if not os.path.exists(hip_build.LIB):
         hip_build.build()
     assert torch.cuda.is_available(), "no GPU"
+    if args.detach_only:
+        print(json.dumps({"detach_surrogate": detach_form(torch, api, wl, large_only=True)}), flush=True)
+        return
 
     batch = wl.config(1)
     db = api.DeviceBatch(batch)
@@ -293,6 +286,7 @@ def forms(torch, api, wl):
         res[name] = {"workload": "ellipsoid-m5, 8192 grasps x 6 force-axis wrenches (%d QPs)" % dfa.n_qps,
                      "ms": round(tf * 1e3, 3), "qps_per_s": round(convf / tf, 1), "converged": convf}
         sf.close()
+    res["detach_surrogate"] = detach_form(torch, api, wl)
     # forward + backward (differentiation workload, same shape as the headline)
     b2 = wl.config(2)
     db2 = api.DeviceBatch(b2)
@@ -321,6 +315,50 @@ def forms(torch, api, wl):
                       "grasps_per_s": round(db2.n_grasps / tfb, 1)}
     s2.close()
     return res
+
+
+# HBM bytes the fine-stage surrogate kernel must move: per contact R (36),
+# T, c^f_w, p^f, p^c (12 each) read and dL/dR (36), dL/dT (12) written; per
+# grasp the contact count and two weights read, Q' and E^f_d written.
+DETACH_BYTES_PER_CONTACT = 84 + 48
+DETACH_BYTES_PER_GRASP = 12 + 8
+PEAK_HBM_GBS = 8000.0
+
+
+def detach_form(torch, api, wl, large_only=False):
+    """Fine-stage surrogate energies with Detach (Eq. 10-11) and their
+    gradient: 2^20 grasps x 5 fingertips in one launch (HBM-bound), timed with
+    events on the stream it runs on; plus the headline's 8192 grasps."""
+    out = {}
+    stream = torch.cuda.current_stream()
+    sv = api.Solver(api.default_params(), stream=stream.cuda_stream)
+    sizes = ((1 << 20, "large"),) if large_only else ((1 << 20, "large"), (8192, "headline_grasps"))
+    for G, label in sizes:
+        fc = api.DeviceFineContacts(wl.fine_contacts(16496, G, m=5))
+        o = sv.detach_energy(fc)
+        for _ in range(3):
+            sv.detach_energy(fc, out=o)
+        n = 20
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            sv.detach_energy(fc, out=o)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / n
+        nbytes = G * 5 * DETACH_BYTES_PER_CONTACT + G * DETACH_BYTES_PER_GRASP
+        gbs = nbytes / (ms / 1e3) / 1e9
+        entry = {"workload": "%d grasps x 5 fingertips (seed 16496)" % G, "kernel_ms": round(ms, 5),
+                 "grasps_per_s": round(G / (ms / 1e3), 1)}
+        if label == "large":
+            entry["roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                 "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": measured_traffic("detach"),
+                                 "kernel": "detach_kernel", "algorithmic_bytes": nbytes}
+        out[label] = entry
+        del fc, o
+    sv.close()
+    return out
 
 
 def tuning(torch, api, db):

@@ -205,6 +205,43 @@ int bodex_qp_last_stats(bodex_qp_t *h, int *launches, int *graph_replays,
 int bodex_qp_kernel_times(bodex_qp_t *h, float *admm_ms, float *finalize_ms,
                           float *backward_ms);
 
+/* Inputs of the fine-stage surrogate energies (Sec. IV-C, Eq. 10-11): one
+ * entry per fingertip contact, arrays [G][m][...] contiguous in that order.
+ * Unlike bodex_batch, the contact counts are a device array. */
+typedef struct {
+    int n_grasps;             /* G >= 0                                       */
+    int m;                    /* contacts per grasp in the layout, 1..8       */
+    const int *contact_count; /* device [G] contacts used (<= m); NULL = m    */
+    const float *link_rot;    /* device [G][m][3][3] R_i of the fingertip's   */
+                              /* link, row-major, invertible                  */
+    const float *link_trans;  /* device [G][m][3] T_i                         */
+    const float *hand_fine;   /* device [G][m][3] c^f_{i,w}: nearest point on */
+                              /* the fingertip (fine stage, world frame)      */
+    const float *obj_fine;    /* device [G][m][3] p^f_i: nearest object point */
+    const float *obj_coarse;  /* device [G][m][3] p^c_i: object point from the*/
+                              /* end of the coarse stage                      */
+} bodex_fine_contacts;
+
+/* Fine-stage energies with the Detach trick (Sec. IV-C, Eq. 10-11).  Per
+ * contact, c_l = R^{-1} (c^f_w - T) is the fingertip point in its link frame,
+ * held constant, and c' = R c_l + T; then
+ *     q_surr[g] = Q'    = sum_i |c'_i - p^c_i|^2,
+ *     e_dist[g] = E^f_d = sum_i |c'_i - p^f_i|^2
+ * (device [G], required).  With dL_dR (device [G][m][3][3]) and dL_dT
+ * (device [G][m][3]) -- both or neither -- also the gradient of
+ * L = sum_g w_q[g] Q'_g + w_e[g] E^f_{d,g} with respect to the link
+ * transforms, dL/dR_i = g_i c_l^T and dL/dT_i = g_i with
+ * g_i = 2 w_q (c'_i - p^c_i) + 2 w_e (c'_i - p^f_i); w_q, w_e are device [G],
+ * NULL = weight 0.  Gradients are overwritten, or added to when `accumulate`
+ * is non-zero; contacts at or beyond contact_count[g] add nothing and get a
+ * zero gradient.  Uses no workspace.  Errors: EINVAL (m outside 1..8,
+ * G < 0, a required pointer NULL, only one gradient output, misaligned),
+ * EHIP. */
+int bodex_qp_detach_energy(bodex_qp_t *h, const bodex_fine_contacts *in,
+                           const float *w_q, const float *w_e, float *q_surr,
+                           float *e_dist, float *dL_dR, float *dL_dT,
+                           int accumulate);
+
 #ifdef __cplusplus
 }
 #endif

@@ -56,6 +56,15 @@ class Batch(ctypes.Structure):
     ]
 
 
+class FineContacts(ctypes.Structure):
+    _fields_ = [
+        ("n_grasps", ctypes.c_int), ("m", ctypes.c_int),
+        ("contact_count", ctypes.c_void_p), ("link_rot", ctypes.c_void_p),
+        ("link_trans", ctypes.c_void_p), ("hand_fine", ctypes.c_void_p),
+        ("obj_fine", ctypes.c_void_p), ("obj_coarse", ctypes.c_void_p),
+    ]
+
+
 class State(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("z", ctypes.c_void_p),
                 ("y", ctypes.c_void_p), ("rho", ctypes.c_void_p)]
@@ -108,6 +117,9 @@ def lib():
         L.bodex_qp_kernel_times.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
                                             ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
         L.bodex_qp_kernel_times.restype = ctypes.c_int
+        L.bodex_qp_detach_energy.argtypes = [ctypes.c_void_p, ctypes.POINTER(FineContacts)] + [ctypes.c_void_p] * 6 + [
+            ctypes.c_int]
+        L.bodex_qp_detach_energy.restype = ctypes.c_int
         _lib = L
         return L
 
@@ -115,7 +127,7 @@ def lib():
 EXPORTED = ("bodex_qp_default_params", "bodex_qp_create", "bodex_qp_set_stream",
             "bodex_qp_solve", "bodex_qp_backward", "bodex_qp_destroy",
             "bodex_qp_last_error", "bodex_qp_state_bytes", "bodex_qp_last_stats",
-            "bodex_qp_kernel_times")
+            "bodex_qp_kernel_times", "bodex_qp_detach_energy")
 
 
 def default_params(**overrides) -> Params:
@@ -258,6 +270,43 @@ def bodex_qp_kernel_times(h):
     return {"admm_ms": a.value, "finalize_ms": b.value, "backward_ms": c.value}
 
 
+class DeviceFineContacts:
+    """Device copies of a workload.FineContacts (all arrays on the GPU)."""
+
+    def __init__(self, fc, device="cuda"):
+        import torch
+        t = lambda a, dt=np.float32: torch.as_tensor(np.ascontiguousarray(a, dt), device=device)
+        self.counts = t(fc.counts, np.int32)
+        self.link_rot = t(fc.link_rot)
+        self.link_trans = t(fc.link_trans)
+        self.hand_fine = t(fc.hand_fine)
+        self.obj_fine = t(fc.obj_fine)
+        self.obj_coarse = t(fc.obj_coarse)
+        self.w_q = t(fc.w_q)
+        self.w_e = t(fc.w_e)
+        self.n_grasps = int(self.link_trans.shape[0])
+        self.m = int(self.link_trans.shape[1])
+
+    def c_struct(self, counts=True) -> FineContacts:
+        f = FineContacts()
+        f.n_grasps = self.n_grasps
+        f.m = self.m
+        f.contact_count = _ptr(self.counts) if counts else None
+        f.link_rot = _ptr(self.link_rot)
+        f.link_trans = _ptr(self.link_trans)
+        f.hand_fine = _ptr(self.hand_fine)
+        f.obj_fine = _ptr(self.obj_fine)
+        f.obj_coarse = _ptr(self.obj_coarse)
+        return f
+
+
+def bodex_qp_detach_energy(h, fc: DeviceFineContacts, q_surr, e_dist, w_q=None, w_e=None,
+                           dL_dR=None, dL_dT=None, accumulate: bool = False, counts: bool = True) -> None:
+    f = fc.c_struct(counts)
+    _check(lib().bodex_qp_detach_energy(h, ctypes.byref(f), _ptr(w_q), _ptr(w_e), _ptr(q_surr), _ptr(e_dist),
+                                        _ptr(dL_dR), _ptr(dL_dT), 1 if accumulate else 0), h)
+
+
 class Solver:
     """A handle on one device and stream (torch's current stream by default)."""
 
@@ -286,6 +335,22 @@ class Solver:
         if out is None:
             out = (torch.zeros_like(batch.points), torch.zeros_like(batch.normals))
         bodex_qp_backward(self.h, batch, state, dL_dE, dL_dQ, out[0], out[1], accumulate)
+        return out
+
+    def detach_energy(self, fc: DeviceFineContacts, grads=True, out=None, accumulate=False):
+        """Q', E^f_d [G] and, with grads, dL/dR [G][m][3][3], dL/dT [G][m][3]
+        for the weights fc.w_q, fc.w_e."""
+        import torch
+        G, m = fc.n_grasps, fc.m
+        dev = fc.link_trans.device
+        if out is None:
+            out = {"q_surr": torch.empty(G, dtype=torch.float32, device=dev),
+                   "e_dist": torch.empty(G, dtype=torch.float32, device=dev)}
+            if grads:
+                out["dL_dR"] = torch.zeros((G, m, 3, 3), dtype=torch.float32, device=dev)
+                out["dL_dT"] = torch.zeros((G, m, 3), dtype=torch.float32, device=dev)
+        bodex_qp_detach_energy(self.h, fc, out["q_surr"], out["e_dist"], fc.w_q, fc.w_e,
+                               out.get("dL_dR"), out.get("dL_dT"), accumulate)
         return out
 
     def stats(self):

@@ -696,4 +696,43 @@ int bodex_qp_last_stats(bodex_qp_t* h, int* launches, int* graph_replays, int* t
     return 0;
 }
 
+int bodex_qp_detach_energy(bodex_qp_t* h, const bodex_fine_contacts* in, const float* w_q, const float* w_e,
+                           float* q_surr, float* e_dist, float* dL_dR, float* dL_dT, int accumulate) {
+    if (!h) return BODEX_EINVAL;
+    if (!in) return fail(h, BODEX_EINVAL, "fine contacts are NULL");
+    const int G = in->n_grasps, M = in->m;
+    if (G < 0) return fail(h, BODEX_EINVAL, "n_grasps %d < 0", G);
+    if (M < 1 || M > BODEX_MAX_CONTACTS) return fail(h, BODEX_EINVAL, "m %d outside 1..%d", M, BODEX_MAX_CONTACTS);
+    if ((dL_dR == nullptr) != (dL_dT == nullptr))
+        return fail(h, BODEX_EINVAL, "dL_dR and dL_dT must both be set or both be NULL");
+    if (G == 0) return 0;
+    const void* req[] = {in->link_rot, in->link_trans, in->hand_fine, in->obj_fine, in->obj_coarse, q_surr, e_dist};
+    for (const void* p : req)
+        if (!p) return fail(h, BODEX_EINVAL, "a required array is NULL");
+    const void* all[] = {in->contact_count, in->link_rot, in->link_trans, in->hand_fine, in->obj_fine,
+                         in->obj_coarse, w_q, w_e, q_surr, e_dist, dL_dR, dL_dT};
+    for (const void* p : all)
+        if (!aligned4(p)) return fail(h, BODEX_EINVAL, "arrays must be 4-byte aligned");
+    HIP_TRY(h, hipSetDevice(h->device));
+    bodex::DetachArgs a;
+    a.G = G;
+    a.M = M;
+    a.counts = in->contact_count;
+    a.R = in->link_rot;
+    a.T = in->link_trans;
+    a.cw = in->hand_fine;
+    a.pf = in->obj_fine;
+    a.pc = in->obj_coarse;
+    a.wq = w_q;
+    a.we = w_e;
+    a.Qp = q_surr;
+    a.Ed = e_dist;
+    a.dR = dL_dR;
+    a.dT = dL_dT;
+    a.accumulate = accumulate ? 1 : 0;
+    HIP_TRY(h, bodex::launch_detach(a, h->stream));
+    h->last_launches = 1;
+    return 0;
+}
+
 }  // extern "C"

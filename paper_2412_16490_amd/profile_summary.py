@@ -25,12 +25,20 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 
 
-def kernel_source_hash() -> str:
+# The sources each measured kernel is built and launched from: a traffic
+# figure is reported only while these files are unchanged.
+KERNEL_FILES = {
+    "admm": ("bodex_math.h", "bodex_kernels.h", "k_admm.hip", "bodex_qp.hip"),
+    "finalize": ("bodex_math.h", "bodex_kernels.h", "k_finalize.hip", "k_finalize_sum.hip", "bodex_qp.hip"),
+    "detach": ("bodex_launch.h", "k_detach.hip"),
+}
+
+
+def kernel_source_hash(kernel: str) -> str:
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
-        if f.endswith((".h", ".hip")):
-            with open(os.path.join(CSRC, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
+    for f in sorted(KERNEL_FILES[kernel]):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -92,7 +100,7 @@ def traffic(a):
     print("fetch_bytes_per_launch: %.0f" % fetch_b)
     print("write_bytes_per_launch: %.0f" % write_b)
     print("bytes_per_launch: %.0f" % (fetch_b + write_b))
-    print("source_hash: %s" % kernel_source_hash())
+    print("source_hash: %s" % kernel_source_hash(a.name))
 
 
 def main():
@@ -102,7 +110,7 @@ def main():
     k.add_argument("db")
     k.add_argument("--command", required=True)
     t = sub.add_parser("traffic")
-    t.add_argument("--name", required=True)
+    t.add_argument("--name", required=True, choices=sorted(KERNEL_FILES))
     t.add_argument("--kernel", required=True)
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
