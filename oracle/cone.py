@@ -19,7 +19,10 @@ a backtracking line search that keeps f strictly feasible, for t_b growing
 geometrically until the duality-gap bound nu / t_b is below `gap` (nu = 2
 per cone + 1 per bound + 1 for the sum row); each centering stops when half
 the squared Newton decrement is below `newton_tol` or below the rounding
-level of the merit value t_b Q + phi (the line search cannot resolve less).  The barrier is
+level of the merit value t_b Q + phi (the line search cannot resolve less).
+The Newton system is solved after symmetric diagonal scaling; should it still
+be singular to working precision, the iteration stops at the current point
+(t_barrier reports how far it got).  The barrier is
     phi(f) = - sum_i log(mu_i^2 f_i1^2 - f_i2^2 - f_i3^2) - sum_i log(fmax - f_i1)
              - log(sum_i f_i1 - gamma).
 At the end the barrier also gives a dual point (per-contact cone multipliers
@@ -87,13 +90,21 @@ def solve(G, mu, t, beta=1.0, eps=1e-6, fmax=1.0, gamma=0.0, gap=1e-13, t0=1.0, 
     nu = 3 * m + (1 if use_gam else 0)
     tb = t0
     steps = 0
+    floor = False
     while True:
         # centering: Newton on tb Q + phi
         for _ in range(max_newton):
             phi, gb, Hb = _barrier(f, mu, fmax, gamma, use_gam)
             grad = tb * (P @ f + q) + gb
             hess = tb * P + Hb
-            d = -np.linalg.solve(hess, grad)
+            # symmetric diagonal scaling before the solve (the barrier's
+            # diagonal spans many orders of magnitude at large tb)
+            sc = 1.0 / np.sqrt(np.diag(hess))
+            try:
+                d = -sc * np.linalg.solve(hess * np.outer(sc, sc), grad * sc)
+            except np.linalg.LinAlgError:
+                floor = True  # rounding floor: stop at the current point
+                break
             dec2 = -grad @ d
             steps += 1
             val = tb * Q(f) + phi
@@ -112,7 +123,7 @@ def solve(G, mu, t, beta=1.0, eps=1e-6, fmax=1.0, gamma=0.0, gap=1e-13, t0=1.0, 
             if a < 1e-20:
                 break
             f = f + a * d
-        if nu / tb < gap:
+        if floor or nu / tb < gap:
             break
         tb *= growth
     # dual point from the barrier: s_i = -(1/tb) grad of the cone term (in the
