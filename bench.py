@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=0.5,
                     help="length of the Poisson arrival window of the served form")
     ap.add_argument("--admm-waves", type=int, default=0, help="ADMM register budget (0 = default)")
+    ap.add_argument("--cone-only", action="store_true",
+                    help="only run the circular-cone form and print its JSON")
     ap.add_argument("--detach-only", action="store_true",
                     help="only run the fine-stage surrogate (Detach) form at 2^20 grasps and print its JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -115,6 +117,9 @@ def main():
     if not os.path.exists(hip_build.LIB):
         hip_build.build()
     assert torch.cuda.is_available(), "no GPU"
+    if args.cone_only:
+        print(json.dumps({"circular_cone": cone_form(torch, api, wl)}), flush=True)
+        return
     if args.detach_only:
         print(json.dumps({"detach_surrogate": detach_form(torch, api, wl, large_only=True)}), flush=True)
         return
@@ -287,6 +292,7 @@ def forms(torch, api, wl):
                      "ms": round(tf * 1e3, 3), "qps_per_s": round(convf / tf, 1), "converged": convf}
         sf.close()
     res["detach_surrogate"] = detach_form(torch, api, wl)
+    res["circular_cone"] = cone_form(torch, api, wl)
     # forward + backward (differentiation workload, same shape as the headline)
     b2 = wl.config(2)
     db2 = api.DeviceBatch(b2)
@@ -315,6 +321,59 @@ def forms(torch, api, wl):
                       "grasps_per_s": round(db2.n_grasps / tfb, 1)}
     s2.close()
     return res
+
+
+def cone_form(torch, api, wl):
+    """The exact circular friction cone of Eq. 1 on the headline grasps
+    (8192 x 16 wrenches): ADMM with the truncated-cone projection and the FP64
+    barrier polish; the finalize kernel's FP64 roofline; and the energy gap of
+    the 8-facet pyramid the paper uses (its E is an upper bound of the cone's)."""
+    b = wl.config(1)
+    db = api.DeviceBatch(b)
+    out = {}
+    energies = {}
+    for model in (api.CONE_CIRCULAR, api.CONE_PYRAMID8):
+        p = api.default_params(m_max=5, s_max=16)
+        p.friction_cone = model
+        p.flags |= api.F_TIMING
+        s = api.Solver(p)
+        st = api.new_state(db.n_grasps, db.n_qps, 5, cone=model == api.CONE_CIRCULAR)
+        r = api.new_result(db.n_grasps, db.n_qps, 5, polish_flops=True)
+        s.solve(db, state=st, result=r)
+        torch.cuda.synchronize()
+        n = 5
+        fin, adm = [], []
+        t0 = time.perf_counter()
+        for _ in range(n):
+            s.solve(db, state=st, result=r)
+            kt = s.kernel_times()
+            fin.append(kt["finalize_ms"])
+            adm.append(kt["admm_ms"])
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / n
+        energies[model] = r["energy"].double().cpu().numpy()
+        if model == api.CONE_CIRCULAR:
+            conv = int(np.sum((r["status"].cpu().numpy() & api.ST_CONVERGED) != 0))
+            pol = int(np.sum((r["status"].cpu().numpy() & api.ST_POLISHED) != 0))
+            fin_ms = float(np.mean(fin))
+            flops = float(np.sum(r["polish_flops"].double().cpu().numpy()))
+            ach = flops / (fin_ms / 1e3) / 1e12
+            out.update({"workload": "ellipsoid-m5-s16 (8192 grasps x 16 wrenches, seed 16491), exact cone",
+                        "ms": round(ms, 3), "qps_per_s": round(conv / (ms / 1e3), 1), "converged": conv,
+                        "polished": pol, "admm_ms": round(float(np.mean(adm)), 4), "finalize_ms": round(fin_ms, 4),
+                        "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP64_TFLOPS,
+                                     "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4),
+                                     "traffic": measured_traffic("cone_finalize"),
+                                     "kernel": "cone_finalize_kernel<5>", "kernel_dtype": "f64",
+                                     "algorithmic_flops": flops}})
+        s.close()
+    ec, ep = energies[api.CONE_CIRCULAR], energies[api.CONE_PYRAMID8]
+    gap = (ep - ec) / np.maximum(ec, 1e-12)
+    out["pyramid_energy_gap"] = {"mean_rel": round(float(np.mean(gap)), 5),
+                                 "median_rel": round(float(np.median(gap)), 5),
+                                 "max_rel": round(float(np.max(gap)), 5),
+                                 "grasps_pyramid_below_cone": int(np.sum(ep < ec * (1 - 1e-5)))}
+    return out
 
 
 # HBM bytes the fine-stage surrogate kernel must move: per contact R (36),

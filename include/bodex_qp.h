@@ -77,6 +77,20 @@ extern "C" {
                                   /* it while the batch shape is unchanged     */
 #define BODEX_F_TIMING 0x20       /* record HIP events around each kernel      */
 
+/* Friction model (bodex_qp_params.friction_cone).
+ * PYRAMID8: the 8-facet pyramid inscribed in the cone of Eq. 1, the
+ *   linearisation of Sec. IV-A (facets at (2k+1) pi/8 with coefficient
+ *   mu cos(pi/8)).
+ * CIRCULAR: the exact cone |(f_2, f_3)| <= mu f_1 of Eq. 1 (the quadratically
+ *   constrained form the paper linearises).  ADMM projects each contact's
+ *   force onto the cone truncated at fmax (closed form); the FP64 polish is a
+ *   barrier (interior-point) method warm-started from the ADMM point.  The
+ *   ADMM state has 3 m_max + 1 rows of z and y (rows 3i..3i+2 contact i's
+ *   force, row 3 m_max the normal-sum row).  bodex_qp_backward uses the
+ *   polished forces the solve left in state.x. */
+#define BODEX_CONE_PYRAMID8 0
+#define BODEX_CONE_CIRCULAR 1
+
 typedef struct {
     int m_max;            /* contacts per grasp, 1..5 (array padding)        */
     int s_max;            /* wrenches per grasp, 1..64                        */
@@ -101,6 +115,8 @@ typedef struct {
                           /* per SIMD: 1, 2, 3 or 4 (0 = library default)     */
     float admm_tol;       /* ADMM stops a QP at this relative KKT residual;   */
                           /* the polish then lifts it to tol_rel (0 = tol_rel) */
+    int friction_cone;    /* BODEX_CONE_PYRAMID8 (default) or                 */
+                          /* BODEX_CONE_CIRCULAR                              */
 } bodex_qp_params;
 
 /* One batch of grasps (CSR over wrenches). */
@@ -118,7 +134,8 @@ typedef struct {
 /* ADMM state, structure-of-arrays so that consecutive QPs are consecutive in
  * memory.  Rows of z, y per contact i: 8 pyramid facets (9i .. 9i+7), then
  * the normal bound (9i+8); row 9*m_max is the gamma row.  Unused rows of
- * grasps with fewer contacts hold zeros. */
+ * grasps with fewer contacts hold zeros.  With BODEX_CONE_CIRCULAR z and y
+ * have 3 m_max + 1 rows instead (see there). */
 typedef struct {
     float *x;   /* device [3 m_max][W]      forces in (normal, d, e) order    */
     float *z;   /* device [9 m_max + 1][W]                                    */
@@ -188,7 +205,8 @@ int bodex_qp_destroy(bodex_qp_t *h);
  * h is NULL).  Valid until the next call on the handle. */
 const char *bodex_qp_last_error(const bodex_qp_t *h);
 
-/* Device bytes of a caller-held state for a batch (x, z, y, rho). */
+/* Device bytes of a caller-held state for a batch (x, z, y, rho); the
+ * pyramid layout, an upper bound for the circular cone's. */
 size_t bodex_qp_state_bytes(int n_grasps, int n_qps, int m_max);
 
 /* Statistics of the last solve (host copies, filled after the stream is

@@ -22,6 +22,7 @@ OK, EINVAL, EHIP, EBUDGET, EINFEAS, EUNSUP, ENODEV = 0, -1, -2, -3, -4, -5, -6
 ST_CONVERGED, ST_MAX_ITER, ST_NONFINITE, ST_FP64_CHOL, ST_POLISH_REJ, ST_POLISHED = (
     0x01, 0x02, 0x04, 0x08, 0x10, 0x20)
 F_WARM_START, F_POLISH, F_ADAPTIVE_RHO, F_BATCHED, F_GRAPH, F_TIMING = 0x01, 0x02, 0x04, 0x08, 0x10, 0x20
+CONE_PYRAMID8, CONE_CIRCULAR = 0, 1
 
 
 class BodexError(RuntimeError):
@@ -42,7 +43,7 @@ class Params(ctypes.Structure):
         ("rho_hysteresis", ctypes.c_float), ("fp64_cond", ctypes.c_float),
         ("polish_steps", ctypes.c_int), ("iters_per_chunk", ctypes.c_int),
         ("flags", ctypes.c_uint), ("admm_waves", ctypes.c_int),
-        ("admm_tol", ctypes.c_float),
+        ("admm_tol", ctypes.c_float), ("friction_cone", ctypes.c_int),
     ]
 
 
@@ -204,12 +205,15 @@ class DeviceBatch:
         return b
 
 
-def new_state(n_grasps, n_qps, m_max, device="cuda"):
+def new_state(n_grasps, n_qps, m_max, device="cuda", cone=False):
+    """Caller-held ADMM state; cone: the circular-cone layout (3 m_max + 1
+    rows of z and y instead of 9 m_max + 1)."""
     import torch
+    nr = (3 if cone else 9) * m_max + 1
     return {
         "x": torch.zeros((3 * m_max, n_qps), dtype=torch.float32, device=device),
-        "z": torch.zeros((9 * m_max + 1, n_qps), dtype=torch.float32, device=device),
-        "y": torch.zeros((9 * m_max + 1, n_qps), dtype=torch.float32, device=device),
+        "z": torch.zeros((nr, n_qps), dtype=torch.float32, device=device),
+        "y": torch.zeros((nr, n_qps), dtype=torch.float32, device=device),
         "rho": torch.zeros((n_grasps,), dtype=torch.float32, device=device),
     }
 

@@ -20,6 +20,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "bodex_cone.h"
 #include "bodex_math.h"
 
 namespace bodex {
@@ -76,6 +77,7 @@ struct KArgs {
     // parameters
     float kappa, beta, eps, fmax, gamma, tol, admm_tol, rho0, alpha, rho_min, rho_max, hyst, fp64_cond;
     int max_iters, check_every, warm, adaptive, polish, polish_steps;
+    int cone;  // 1: exact circular cone (state rows 3 m + 1), 0: 8-facet pyramid
 };
 
 struct SlotInfo {
@@ -89,6 +91,13 @@ template <int MM>
 __device__ inline int state_row(int r, int ms) {
     if (r == 9 * MM) return 9 * ms;
     return r < 9 * ms ? r : -1;
+}
+
+// The same for the cone form (3 rows per contact, the sum row at 3 MM).
+template <int MM>
+__device__ inline int cone_state_row(int r, int ms) {
+    if (r == 3 * MM) return 3 * ms;
+    return r < 3 * ms ? r : -1;
 }
 
 // Slot of each lane: lanes of one grasp are contiguous, in slot order.
@@ -222,18 +231,35 @@ __device__ __forceinline__ void write_admm_x(const KArgs& a, unsigned w, const f
         if (c < 3 * a.ms) (a.x + size_t(c) * a.W)[w] = xv[c];
 }
 
-template <int MM>
-__device__ __forceinline__ void write_admm_zy(const KArgs& a, unsigned w, const float* wv, float rho) {
-    constexpr int NR = 9 * MM + 1;
+template <int MM, bool CONE>
+__device__ __forceinline__ void write_admm_zy(const KArgs& a, unsigned w, const float* wv, const float* muc,
+                                              float rho) {
     asm volatile("" : "+v"(w));
+    if constexpr (CONE) {
+        constexpr int NR = 3 * MM + 1;
+        float muv[MM], zv[NR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        if (r % 9 == 0) BODEX_SPLIT();
-        const int sr = state_row<MM>(r, a.ms);
-        const float zr = row_proj(r, MM, wv[r], a.fmax, a.gamma);
-        if (sr >= 0) {
-            (a.z + size_t(sr) * a.W)[w] = zr;
-            (a.y + size_t(sr) * a.W)[w] = rho * (wv[r] - zr);
+        for (int i = 0; i < MM; ++i) muv[i] = muc[i];
+        cone_proj_all<MM>(wv, muv, a.fmax, a.gamma, zv);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int sr = cone_state_row<MM>(r, a.ms);
+            if (sr >= 0) {
+                (a.z + size_t(sr) * a.W)[w] = zv[r];
+                (a.y + size_t(sr) * a.W)[w] = rho * (wv[r] - zv[r]);
+            }
+        }
+    } else {
+        constexpr int NR = 9 * MM + 1;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            if (r % 9 == 0) BODEX_SPLIT();
+            const int sr = state_row<MM>(r, a.ms);
+            const float zr = row_proj(r, MM, wv[r], a.fmax, a.gamma);
+            if (sr >= 0) {
+                (a.z + size_t(sr) * a.W)[w] = zr;
+                (a.y + size_t(sr) * a.W)[w] = rho * (wv[r] - zr);
+            }
         }
     }
 }
@@ -243,7 +269,7 @@ __device__ __forceinline__ void write_admm_zy(const KArgs& a, unsigned w, const 
 // whose conditioning bound exceeds fp64_cond.  Called by every lane of the
 // wave (barriers inside).  Returns bit 1 if this lane's slot used FP64, bit 2
 // if its factorisation failed.
-template <int MM>
+template <int MM, bool CONE>
 __device__ __forceinline__ int refactor_slots(const KArgs& a, bool mine, int slot, int j, int s, int m,
                                               float rho, const float* sG, const float* sMuc, double* sLw,
                                               float* sKi, double* sYv, int* sMisc) {
@@ -254,7 +280,8 @@ __device__ __forceinline__ int refactor_slots(const KArgs& a, bool mine, int slo
     __syncthreads();
     bool want64 = false;
     if (mine) {
-        const float cb = kkt_cond_bound<float, NV>(Gs, mucs, m, rho, a.eps);
+        const float cb = CONE ? cone_kkt_cond_bound<float, NV>(Gs, m, rho, a.eps)
+                              : kkt_cond_bound<float, NV>(Gs, mucs, m, rho, a.eps);
         want64 = !(cb <= a.fp64_cond);
         if (want64) atomicOr(&sMisc[1], 1);
     }
@@ -271,10 +298,14 @@ __device__ __forceinline__ int refactor_slots(const KArgs& a, bool mine, int slo
             double sacc = 0.0;
             for (int r = 0; r < 6; ++r) sacc += double(Gs[r * NV + i]) * double(Gs[r * NV + c]);
             double v = 2.0 * sacc + ((i == c) ? 2.0 * eps : 0.0);
-            if (i % 3 == 0 && c % 3 == 0)
+            if (CONE) {
+                if (i == c) v += rr;
+                if (i % 3 == 0 && c % 3 == 0) v += rr;
+            } else if (i % 3 == 0 && c % 3 == 0) {
                 v += (ci == cj) ? rr * (8.0 * double(mucs[ci]) * double(mucs[ci]) + 2.0) : rr;
-            else if (i == c)
+            } else if (i == c) {
                 v += 4.0 * rr;
+            }
             return v;
         });
     }
@@ -282,7 +313,8 @@ __device__ __forceinline__ int refactor_slots(const KArgs& a, bool mine, int slo
     const float eps32 = a.eps;
     float* yf = reinterpret_cast<float*>(sYv) + threadIdx.x;
     const bool ok32 = coop_inverse<float, NV>(mine && !want64, j, s, Lf, Ki, yf, [&](int i, int c) {
-        return kkt_entry<float, NV>(Gs, mucs, m, rho, eps32, i, c);
+        return CONE ? cone_kkt_entry<float, NV>(Gs, m, rho, eps32, i, c)
+                    : kkt_entry<float, NV>(Gs, mucs, m, rho, eps32, i, c);
     });
     int r = 0;
     if (mine && want64) r |= 1;
@@ -294,9 +326,11 @@ __device__ __forceinline__ int refactor_slots(const KArgs& a, bool mine, int slo
 // ADMM kernel.
 // ---------------------------------------------------------------------------
 // OCC: register budget expressed as resident waves per SIMD (1 = unlimited).
-template <int MM, int OCC>
+// CONE: the exact circular cone (3 MM + 1 state rows), else the 8-facet
+// pyramid (9 MM + 1 rows).
+template <int MM, int OCC, bool CONE>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) admm_kernel(const KArgs a) {
-    constexpr int NV = 3 * MM, NR = 9 * MM + 1, NK = NV * (NV + 1) / 2;
+    constexpr int NV = 3 * MM, NR = CONE ? 3 * MM + 1 : 9 * MM + 1, NK = NV * (NV + 1) / 2;
     constexpr int NKP = Dims<MM>::NKP, NG = 6 * NV;
     extern __shared__ __align__(16) unsigned char smem[];
     const int S = a.slots;
@@ -338,7 +372,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) 
                 const float n[3] = {a.normals[base], a.normals[base + 1], a.normals[base + 2]};
                 const float mu = a.mu[size_t(si.g) * a.ms + c];
                 const bool ok = grasp_columns<float, NV>(p, n, a.kappa, c, sG + size_t(slot) * NG);
-                sMuc[slot * 8 + c] = mu * float(kC8);
+                sMuc[slot * 8 + c] = CONE ? mu : mu * float(kC8);
                 if (!ok || !(mu > 0.f) || !isfinite(mu)) atomicOr(&sFlag[slot], 4);
             }
             if (j == 0) {
@@ -380,7 +414,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) 
         for (int r = 0; r < NR; ++r) {
             if (r % 9 == 0) BODEX_SPLIT();
             float v = 0.f;
-            const int sr = state_row<MM>(r, a.ms);
+            const int sr = CONE ? cone_state_row<MM>(r, a.ms) : state_row<MM>(r, a.ms);
             if (act && a.warm && sr >= 0) {
                 const float zr = (a.z + size_t(sr) * a.W)[wl], yr = (a.y + size_t(sr) * a.W)[wl];
                 v = zr + yr / rho;
@@ -391,8 +425,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) 
         // --- factorisation ------------------------------------------------------
         unsigned char stbits = 0;
         {
-            const int fr = refactor_slots<MM>(a, act && !bad, act ? slot : 0, j, si.s, m, rho, sG, sMuc, sLw,
-                                              sKi, sYv, sMisc);
+            const int fr = refactor_slots<MM, CONE>(a, act && !bad, act ? slot : 0, j, si.s, m, rho, sG, sMuc,
+                                                    sLw, sKi, sYv, sMisc);
             if (fr & 1) stbits |= kStFp64;
             if (fr & 2) bad = true;
         }
@@ -413,14 +447,22 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) 
             BODEX_SPLIT();
             if (!done) {
                 float rhs[NV];
-                admm_rhs<MM>(wv, bq, muc, rho, a.fmax, a.gamma, m, rhs);
-                symv_packed<NV>(Ki, rhs, xv);
-                admm_update<MM>(wv, xv, muc, a.alpha, a.fmax, a.gamma, m);
+                if constexpr (CONE) {
+                    float pv[NR];
+                    cone_rhs<MM>(wv, bq, muc, rho, a.fmax, a.gamma, m, pv, rhs);
+                    symv_packed<NV>(Ki, rhs, xv);
+                    cone_update<MM>(wv, xv, pv, a.alpha, m);
+                } else {
+                    admm_rhs<MM>(wv, bq, muc, rho, a.fmax, a.gamma, m, rhs);
+                    symv_packed<NV>(Ki, rhs, xv);
+                    admm_update<MM>(wv, xv, muc, a.alpha, a.fmax, a.gamma, m);
+                }
             }
             if (it % a.check_every != 0 && it != a.max_iters) continue;
             float rpn = -1.f, rdn = -1.f;
             if (!done) {
-                const Residual R = admm_residual<MM>(wv, xv, bq, muc, Gs, rho, a.eps, a.fmax, a.gamma, m);
+                const Residual R = CONE ? cone_residual<MM>(wv, xv, bq, muc, Gs, rho, a.eps, a.fmax, a.gamma, m)
+                                        : admm_residual<MM>(wv, xv, bq, muc, Gs, rho, a.eps, a.fmax, a.gamma, m);
                 rel_last = R.rel;
                 if (!isfinite(R.rel)) {
                     done = true;
@@ -468,17 +510,26 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) 
                 const float rn = sRho[slot];
                 if (!done) {
                     // keep (z, y): w' = z + y / rho'
+                    if constexpr (CONE) {
+                        float muv[MM], zv[NR];
 #pragma unroll
-                    for (int r = 0; r < NR; ++r) {
-                        const float zr = row_proj(r, MM, wv[r], a.fmax, a.gamma);
-                        wv[r] = zr + (rho / rn) * (wv[r] - zr);
+                        for (int i = 0; i < MM; ++i) muv[i] = muc[i];
+                        cone_proj_all<MM>(wv, muv, a.fmax, a.gamma, zv);
+#pragma unroll
+                        for (int r = 0; r < NR; ++r) wv[r] = zv[r] + (rho / rn) * (wv[r] - zv[r]);
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < NR; ++r) {
+                            const float zr = row_proj(r, MM, wv[r], a.fmax, a.gamma);
+                            wv[r] = zr + (rho / rn) * (wv[r] - zr);
+                        }
                     }
                 }
                 rho = rn;
             }
             {
-                const int fr = refactor_slots<MM>(a, mine, act ? slot : 0, j, si.s, m, rho, sG, sMuc, sLw,
-                                                  sKi, sYv, sMisc);
+                const int fr = refactor_slots<MM, CONE>(a, mine, act ? slot : 0, j, si.s, m, rho, sG, sMuc, sLw,
+                                                        sKi, sYv, sMisc);
                 if (fr & 1) stbits |= kStFp64;
                 if ((fr & 2) && mine && !done) {
                     done = true;
@@ -501,7 +552,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) 
             rel_last = NAN;
             write_admm_x<MM>(a, wl, xv);
         }
-        if (act) write_admm_zy<MM>(a, wl, wv, rho_frz);
+        if (act) write_admm_zy<MM, CONE>(a, wl, wv, muc, rho_frz);
         if (act) {
             a.iters[w] = it_done;
             a.status[w] = stbits;
@@ -583,7 +634,7 @@ __device__ inline LaneVec projector_cache(const FinPtrs<MM>& P, int lane) {
 // Returns whether the lane's grasp has finite, valid inputs.
 template <int MM>
 __device__ inline bool fin_setup(const KArgs& a, const FinPtrs<MM>& P, int nsl, int slot, int j,
-                                 const SlotInfo& si) {
+                                 const SlotInfo& si, bool cone = false) {
     constexpr int NV = 3 * MM, NG = 6 * NV;
     const int lane = threadIdx.x;
     const bool act = slot >= 0;
@@ -598,7 +649,7 @@ __device__ inline bool fin_setup(const KArgs& a, const FinPtrs<MM>& P, int nsl, 
             const double n[3] = {a.normals[base], a.normals[base + 1], a.normals[base + 2]};
             const double mu = a.mu[size_t(si.g) * a.ms + c];
             const bool ok = grasp_columns<double, NV>(p, n, double(a.kappa), c, P.G + size_t(slot) * NG);
-            P.muc[slot * 8 + c] = mu * kC8;
+            P.muc[slot * 8 + c] = cone ? mu : mu * kC8;
             if (!ok || !(mu > 0.0) || !isfinite(mu)) atomicOr(&P.flag[slot], 4);
         }
     }
@@ -783,9 +834,187 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) fi
 }
 
 // ---------------------------------------------------------------------------
+// Finalize kernel of the cone form: the FP64 barrier polish from the ADMM
+// point, objective, energy, KKT residual, outputs and the polished state.
+// ---------------------------------------------------------------------------
+template <int MM>
+struct ConeFinLds {
+    static constexpr int NV = 3 * MM, NG = 6 * NV;
+    // per slot G64 and mu (8); per lane the polish vectors f, d, ft, r
+    // (lane-interleaved); the energy reduction
+    static __host__ __device__ int vectors(bool) { return 4; }
+    static __host__ __device__ size_t bytes(int slots, bool gam) {
+        return size_t(slots) * (NG + 8) * 8 + size_t(vectors(gam)) * NV * kWave * 8 + size_t(kWave) * 8 +
+               kMaxSlots * 32 + 64;
+    }
+};
+
+// Polish schedule: start 1e-3 of the way toward the cone axis, barrier weight
+// 1e5 rising 60x per centring, loose intermediate centring, stop at
+// nu / t <= 1e-12.
+constexpr double kConePull = 1e-3, kConeT0 = 1e5, kConeGap = 1e-12, kConeGrowth = 60.0, kConeLoose = 1e-2;
+constexpr double kConeRetryPull = 0.5;
+
+// One wave per SIMD: the polish factors its 3 MM x 3 MM Newton matrix in
+// registers.
+template <int MM, bool GAM>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) cone_finalize_kernel(const KArgs a) {
+    constexpr int NV = 3 * MM, NG = 6 * NV;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int S = a.slots;
+    double* d = reinterpret_cast<double*>(smem);
+    FinPtrs<MM> P;
+    P.G = d;
+    d += size_t(S) * NG;
+    P.muc = d;
+    d += size_t(S) * 8;
+    double* work = d;
+    d += size_t(ConeFinLds<MM>::vectors(GAM)) * NV * kWave;
+    P.red = d;
+    d += kWave;
+    P.Gbar = nullptr;
+    P.work = work;
+    P.info = reinterpret_cast<SlotInfo*>(d);
+    P.flag = reinterpret_cast<int*>(P.info + kMaxSlots);
+    const int lane = threadIdx.x;
+    const ConeWork<LaneVec> W(LaneVec{work + lane, kWave}, LaneVec{work + NV * kWave + lane, kWave},
+                              LaneVec{work + 2 * NV * kWave + lane, kWave}, LaneVec{work + 3 * NV * kWave + lane, kWave});
+    __shared__ int sTile;
+    for (int t = fetch_tile(a, &sTile, -1); t < a.n_tiles; t = fetch_tile(a, &sTile, t)) {
+        int nsl;
+        load_slots(a, t, P.info, nsl);
+        int slot, j;
+        lane_slot(P.info, nsl, lane, slot, j);
+        const bool act = slot >= 0;
+        SlotInfo si = {0, 0, 1, 0};
+        if (act) si = P.info[slot];
+        const bool good = fin_setup<MM>(a, P, nsl, slot, j, si, true);
+        const int w = si.w0 + j;
+        double Q = 0.0;
+        if (act) {
+            const double* Gs = P.G + size_t(slot) * NG;
+            const size_t W_ = size_t(a.W);
+            ConeData<MM, const double*, GAM> D;
+            D.G = Gs;
+            D.mu = P.muc + slot * 8;
+            for (int r = 0; r < 6; ++r) D.bt[r] = double(a.beta) * double(a.wrench[size_t(w) * 6 + r]);
+            D.m = si.m;
+            D.fmax = a.fmax;
+            D.gamma = a.gamma;
+            D.eps = a.eps;
+            unsigned char st = a.status[w];
+            bool polished = false;
+            const bool finite_in = good && !(st & kStNonfinite);
+            if (finite_in && a.polish) {
+                const float* zs = a.z + w;
+                cone_start<MM>(D, [&](int r) { return double(zs[size_t(r) * W_]); }, kConePull, W);
+                ConePolishOut po = cone_polish<MM>(D, kConeT0, kConeGap, kConeGrowth, kConeLoose, a.polish_steps, W);
+                if (po.status != 0) {
+                    // once more from a point well inside (half way to the cone
+                    // axis), whose central path the barrier follows from a
+                    // small weight
+                    const int n1 = po.newton, e1 = po.evals, g1 = po.grads;
+                    cone_start<MM>(D, [&](int r) { return double(zs[size_t(r) * W_]); }, kConeRetryPull, W);
+                    po = cone_polish<MM>(D, kConeT0, kConeGap, kConeGrowth, kConeLoose, a.polish_steps, W);
+                    po.newton += n1;
+                    po.evals += e1;
+                    po.grads += g1;
+                }
+                if (a.pflops) a.pflops[w] = float(cone_polish_flops(si.m, po));
+                if (po.status == 0) {
+                    polished = true;
+                    st |= kStPolished;
+                    st &= ~kStPolishRej;
+                    // ADMM-form state of the polished (interior) point: z = x,
+                    // y from stationarity with the barrier's normal-sum
+                    // multiplier
+                    double r6[6], s1 = 0.0;
+                    cone_g_times<MM>(D, W.f, true, r6);
+#pragma unroll 1
+                    for (int i = 0; i < si.m; ++i) s1 += W.f[3 * i];
+                    const bool gam = GAM && a.gamma > 0.f;
+                    const double yg = gam ? -1.0 / (po.t * (s1 - D.gamma)) : 0.0;
+#pragma unroll 1
+                    for (int i = 0; i < a.ms; ++i) {
+                        const bool live = i < si.m;
+                        double g[3] = {0.0, 0.0, 0.0};
+                        if (live) cone_contact_grad<MM>(D, i, r6, W.f, g);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            const double fv = live ? W.f[3 * i + c] : 0.0;
+                            a.x[size_t(3 * i + c) * W_ + w] = float(fv);
+                            a.z[size_t(3 * i + c) * W_ + w] = float(fv);
+                            a.y[size_t(3 * i + c) * W_ + w] = live ? float(-g[c] - (c == 0 ? yg : 0.0)) : 0.f;
+                        }
+                    }
+                    a.z[size_t(3 * a.ms) * W_ + w] = fmaxf(float(s1), a.gamma);
+                    a.y[size_t(3 * a.ms) * W_ + w] = float(yg);
+                } else {
+                    st |= kStPolishRej;
+                    st &= ~kStPolished;
+                }
+            }
+            auto xval = [&](int c) -> double {
+                return polished ? (c < 3 * si.m ? W.f[c] : 0.0) : double(a.x[size_t(c) * W_ + w]);
+            };
+            double r6[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) r6[k] = -D.bt[k];
+            double ff = 0.0;
+#pragma unroll 1
+            for (int c = 0; c < 3 * a.ms; ++c) {
+                const double xc = xval(c);
+                if (c < 3 * si.m) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) r6[k] += Gs[k * NV + c] * xc;
+                }
+                ff += xc * xc;
+                a.forces[size_t(w) * 3 * a.ms + c] = finite_in ? float(xc) : NAN;
+            }
+            double rr2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) rr2 += r6[k] * r6[k];
+            Q = rr2 + double(a.eps) * ff;
+            double rel = NAN;
+            if (finite_in) {
+                const float* xs = a.x + w;
+                const float* zs = a.z + w;
+                const float* ys = a.y + w;
+                rel = cone_rel_kkt64<MM>(
+                    Gs, D.bt, si.m, double(a.eps), [&](int c) { return double(xs[size_t(c) * W_]); },
+                    [&](int r) { return double(zs[size_t(r) * W_]); }, [&](int r) { return double(ys[size_t(r) * W_]); },
+                    double(zs[size_t(3 * a.ms) * W_]), double(ys[size_t(3 * a.ms) * W_]));
+            }
+            if (rel <= double(a.tol))
+                st |= kStConverged;
+            else
+                st &= ~kStConverged;
+            if (!finite_in) {
+                st |= kStNonfinite;
+                Q = NAN;
+            }
+            a.status[w] = st;
+            a.kkt[w] = float(rel);
+            a.qobj[w] = float(Q);
+        }
+        P.red[lane] = Q;
+        __syncthreads();
+        if (act && j == 0) {
+            double E = 0.0;
+            for (int l = lane; l < lane + si.s; ++l) E += P.red[l];
+            a.energy[si.g] = float(E);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Backward kernel.
 // ---------------------------------------------------------------------------
-template <int MM, bool GAM>
+// CONE: the circular-cone form, whose polished forces the solve left in
+// state.x (FP32 rounding of the FP64 polish); the pyramid form re-runs its
+// polish from the state's duals.
+template <int MM, bool GAM, bool CONE>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) backward_kernel(const KArgs a) {
     constexpr int NV = 3 * MM, NG = 6 * NV;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -816,14 +1045,16 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) ba
             double bt[6];
 #pragma unroll
             for (int r = 0; r < 6; ++r) bt[r] = double(a.beta) * tw[r];
-            const LdsPolishData<MM, GAM> D = polish_data<MM, GAM>(a, P, slot, si, bt);
-            PolishState<MM> PS;
-            PS.S.pc = projector_cache<MM>(P, lane);
-            const StridedY<MM> y0{a.y + w, size_t(a.W), a.ms};
-            const PolishOut po = polish_qp<MM>(D, y0, a.polish_steps, W, PS);
-            if (po.status == 0) {
+            if constexpr (!CONE) {
+                const LdsPolishData<MM, GAM> D = polish_data<MM, GAM>(a, P, slot, si, bt);
+                PolishState<MM> PS;
+                PS.S.pc = projector_cache<MM>(P, lane);
+                const StridedY<MM> y0{a.y + w, size_t(a.W), a.ms};
+                const PolishOut po = polish_qp<MM>(D, y0, a.polish_steps, W, PS);
+                if (po.status == 0) {
 #pragma unroll
-                for (int c = 0; c < NV; ++c) f[c] = (c < 3 * si.m) ? W.x[c] : 0.0;
+                    for (int c = 0; c < NV; ++c) f[c] = (c < 3 * si.m) ? W.x[c] : 0.0;
+                }
             }
             if (a.dLdQ) om += a.dLdQ[w];
             if (a.dLdE) om += a.dLdE[si.g];

@@ -10,6 +10,11 @@ hipError_t launch_admm(int mm, int occ, const KArgs& a, int grid, size_t lds, hi
 hipError_t launch_finalize(int mm, const KArgs& a, int grid, size_t lds, hipStream_t st);
 hipError_t launch_backward(int mm, const KArgs& a, int grid, size_t lds, hipStream_t st);
 hipError_t launch_reset(int* q, int n, hipStream_t st);
+// Circular-cone form (KArgs::cone set).
+hipError_t launch_admm_cone(int mm, int occ, const KArgs& a, int grid, size_t lds, hipStream_t st);
+hipError_t launch_finalize_cone(int mm, const KArgs& a, int grid, size_t lds, hipStream_t st);
+size_t cone_fin_lds(int mm, int slots, bool gam);
+hipError_t launch_backward_cone(int mm, const KArgs& a, int grid, size_t lds, hipStream_t st);
 
 // Fine-stage surrogate energies (Detach trick): arrays [G][M][...], row-major
 // 3x3 link matrices; counts, wq, we may be null (all M contacts, zero

@@ -238,8 +238,9 @@ constexpr int kDefaultAdmmWaves = 2;
 
 hipError_t launch(Kind k, int mm, const KArgs& a, int grid, size_t lds, hipStream_t st, int occ = 0) {
     if (k == Kind::Admm) return bodex::launch_admm(mm, occ > 0 ? occ : kDefaultAdmmWaves, a, grid, lds, st);
-    if (k == Kind::Fin) return bodex::launch_finalize(mm, a, grid, lds, st);
-    return bodex::launch_backward(mm, a, grid, lds, st);
+    if (k == Kind::Fin)
+        return a.cone ? bodex::launch_finalize_cone(mm, a, grid, lds, st) : bodex::launch_finalize(mm, a, grid, lds, st);
+    return a.cone ? bodex::launch_backward_cone(mm, a, grid, lds, st) : bodex::launch_backward(mm, a, grid, lds, st);
 }
 
 int validate_params(const bodex_qp_params* p, bodex_qp* h) {
@@ -266,6 +267,8 @@ int validate_params(const bodex_qp_params* p, bodex_qp* h) {
     if (p->polish_steps < 0) return fail(h, BODEX_EINVAL, "polish_steps must be >= 0");
     if (p->admm_waves < 0 || p->admm_waves > 4) return fail(h, BODEX_EINVAL, "admm_waves must be in [0, 4]");
     if (!(p->admm_tol >= 0.f)) return fail(h, BODEX_EINVAL, "admm_tol must be >= 0");
+    if (p->friction_cone != BODEX_CONE_PYRAMID8 && p->friction_cone != BODEX_CONE_CIRCULAR)
+        return fail(h, BODEX_EINVAL, "friction_cone must be BODEX_CONE_PYRAMID8 or BODEX_CONE_CIRCULAR");
     return 0;
 }
 
@@ -299,6 +302,7 @@ KArgs make_args(const bodex_qp* h, const bodex_batch* in) {
     a.adaptive = (p.flags & BODEX_F_ADAPTIVE_RHO) ? 1 : 0;
     a.polish = (p.flags & BODEX_F_POLISH) ? 1 : 0;
     a.polish_steps = p.polish_steps;
+    a.cone = p.friction_cone == BODEX_CONE_CIRCULAR ? 1 : 0;
     return a;
 }
 
@@ -465,7 +469,8 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
     HIP_TRY(h, hipSetDevice(h->device));
 
     const int mm = kernel_mm(h->prm.m_max);
-    const int nv = 3 * h->prm.m_max, nr = 9 * h->prm.m_max + 1;
+    const bool cone = h->prm.friction_cone == BODEX_CONE_CIRCULAR;
+    const int nv = 3 * h->prm.m_max, nr = (cone ? 3 : 9) * h->prm.m_max + 1;
     const bool batched = (h->prm.flags & BODEX_F_BATCHED) != 0;
     Schedule S;
     build_schedule(in->contact_count, in->wrench_offset, G, batched, S);
@@ -498,7 +503,7 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
     const bool timing = (h->prm.flags & BODEX_F_TIMING) != 0;
     const bool graph = (h->prm.flags & BODEX_F_GRAPH) != 0 && h->stream != nullptr;
     const size_t lds_a = admm_lds(mm, S.slots);
-    const size_t lds_f = fin_lds(mm, S.slots, false);
+    const size_t lds_f = cone ? bodex::cone_fin_lds(mm, S.slots, h->prm.gamma > 0.f) : fin_lds(mm, S.slots, false);
     int per_cu = std::max(1, std::min(16, int((160 * 1024) / std::max<size_t>(lds_a, 1))));
     const int grid_a = batched ? occupancy_grid(h, per_cu, S.n_tiles) : S.n_tiles;
     // finalize: one block per tile (the polish keeps its state in registers)

@@ -13,16 +13,17 @@ __global__ void reset_counter_kernel(int* q, int n) {
 template <int MM>
 static hipError_t launch_admm_mm(int occ, const KArgs& a, int grid, size_t lds, hipStream_t st) {
     switch (occ) {
-        case 1: hipLaunchKernelGGL((admm_kernel<MM, 1>), dim3(grid), dim3(64), lds, st, a); break;
-        case 2: hipLaunchKernelGGL((admm_kernel<MM, 2>), dim3(grid), dim3(64), lds, st, a); break;
-        case 3: hipLaunchKernelGGL((admm_kernel<MM, 3>), dim3(grid), dim3(64), lds, st, a); break;
-        case 4: hipLaunchKernelGGL((admm_kernel<MM, 4>), dim3(grid), dim3(64), lds, st, a); break;
+        case 1: hipLaunchKernelGGL((admm_kernel<MM, 1, false>), dim3(grid), dim3(64), lds, st, a); break;
+        case 2: hipLaunchKernelGGL((admm_kernel<MM, 2, false>), dim3(grid), dim3(64), lds, st, a); break;
+        case 3: hipLaunchKernelGGL((admm_kernel<MM, 3, false>), dim3(grid), dim3(64), lds, st, a); break;
+        case 4: hipLaunchKernelGGL((admm_kernel<MM, 4, false>), dim3(grid), dim3(64), lds, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_admm(int mm, int occ, const KArgs& a, int grid, size_t lds, hipStream_t st) {
+    if (a.cone) return launch_admm_cone(mm, occ, a, grid, lds, st);
     switch (mm) {
         case 4: return launch_admm_mm<4>(occ, a, grid, lds, st);
         case 5: return launch_admm_mm<5>(occ, a, grid, lds, st);

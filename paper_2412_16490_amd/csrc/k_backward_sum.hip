@@ -6,8 +6,8 @@ namespace bodex {
 
 hipError_t launch_backward_sum(int mm, const KArgs& a, int grid, size_t lds, hipStream_t st) {
     switch (mm) {
-        case 4: hipLaunchKernelGGL((backward_kernel<4, true>), dim3(grid), dim3(64), lds, st, a); break;
-        case 5: hipLaunchKernelGGL((backward_kernel<5, true>), dim3(grid), dim3(64), lds, st, a); break;
+        case 4: hipLaunchKernelGGL((backward_kernel<4, true, false>), dim3(grid), dim3(64), lds, st, a); break;
+        case 5: hipLaunchKernelGGL((backward_kernel<5, true, false>), dim3(grid), dim3(64), lds, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -28,8 +28,10 @@ CSRC = os.path.join(HERE, "csrc")
 # The sources each measured kernel is built and launched from: a traffic
 # figure is reported only while these files are unchanged.
 KERNEL_FILES = {
-    "admm": ("bodex_math.h", "bodex_kernels.h", "k_admm.hip", "bodex_qp.hip"),
-    "finalize": ("bodex_math.h", "bodex_kernels.h", "k_finalize.hip", "k_finalize_sum.hip", "bodex_qp.hip"),
+    "admm": ("bodex_math.h", "bodex_cone.h", "bodex_kernels.h", "k_admm.hip", "bodex_qp.hip"),
+    "finalize": ("bodex_math.h", "bodex_cone.h", "bodex_kernels.h", "k_finalize.hip", "k_finalize_sum.hip",
+                 "bodex_qp.hip"),
+    "cone_finalize": ("bodex_math.h", "bodex_cone.h", "bodex_kernels.h", "k_finalize_cone.hip", "bodex_qp.hip"),
     "detach": ("bodex_launch.h", "k_detach.hip"),
 }
 

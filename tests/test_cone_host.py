@@ -1,0 +1,88 @@
+"""The solver's circular-cone code compiled for the host (the same header the
+GPU kernels use) against independent references:
+
+* its closed-form projection onto the truncated cone against the closest
+  point of the (axial, radial) triangle computed segment by segment;
+* its FP64 barrier polish, from a cold start and from a perturbed optimum,
+  against the cone oracle.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import cone as oc
+import oracle
+from paper_2412_16490_amd import workload as wl
+from test_oracle_cone import _project_contact
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+@pytest.fixture(scope="module")
+def host(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("cone_host") / "libcone_host.so")
+    subprocess.check_call(["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
+                           os.path.join(HERE, "cone_host.cpp"), "-o", out])
+    return ctypes.CDLL(out)
+
+
+def test_projection_matches_closest_point_of_triangle(host):
+    rng = np.random.default_rng(0)
+    for _ in range(2000):
+        f = rng.standard_normal(3) * rng.choice([0.1, 1.0, 3.0])
+        mu = rng.uniform(0.2, 1.5)
+        fmax = rng.uniform(0.5, 2.0)
+        z = np.zeros(3)
+        host.host_cone_project(ctypes.c_double(f[0]), ctypes.c_double(f[1]), ctypes.c_double(f[2]),
+                               ctypes.c_double(mu), ctypes.c_double(fmax), z.ctypes.data_as(_D))
+        np.testing.assert_allclose(z, _project_contact(f, mu, fmax), atol=1e-12)
+
+
+def _polish(host, b, g, z0, gamma=0.0, beta=1.0, cap=200):
+    m = int(b.counts[g])
+    s = int(b.woff[g + 1] - b.woff[g])
+    arr = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    P, N, mu, T = arr(b.points[g, :m]), arr(b.normals[g, :m]), arr(b.mu[g, :m]), arr(b.wrench[b.woff[g]:b.woff[g + 1]])
+    z = np.ascontiguousarray(z0, dtype=np.float32)
+    x = np.zeros((s, 15))
+    st = np.zeros(s, np.int32)
+    nw = np.zeros(s, np.int32)
+    p = lambda a: a.ctypes.data_as(_D)
+    host.host_cone_polish_grasp(m, p(P), p(N), p(mu), p(T), s, ctypes.c_double(20.0), ctypes.c_double(beta),
+                                ctypes.c_double(1e-6), ctypes.c_double(1.0), ctypes.c_double(gamma),
+                                z.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.c_double(1e-3),
+                                ctypes.c_double(1e5), ctypes.c_double(1e-12), ctypes.c_double(60.0),
+                                ctypes.c_double(1e-2), cap, x.ctypes.data_as(_D),
+                                st.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                nw.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    return x[:, :3 * m], st, nw
+
+
+@pytest.mark.parametrize("gamma,start", [(0.0, "cold"), (2.0, "cold"), (0.0, "perturbed"), (2.0, "perturbed")])
+def test_polish_matches_oracle(host, gamma, start):
+    b = wl.config(1, 6)
+    rng = np.random.default_rng(1)
+    for g in range(b.n_grasps):
+        m = int(b.counts[g])
+        s = int(b.woff[g + 1] - b.woff[g])
+        G = oracle.grasp_matrix(b.points[g, :m].astype(float), b.normals[g, :m].astype(float), 20.0)
+        refs = [oc.solve(G, b.mu[g, :m].astype(float), b.wrench[b.woff[g] + j].astype(float), gamma=gamma)
+                for j in range(s)]
+        z0 = np.zeros((s, 16))
+        if start == "perturbed":
+            for j in range(s):
+                z0[j, :3 * m] = refs[j]["f"] + 0.02 * rng.standard_normal(3 * m)
+        # a cold start (all contacts at the apex) first walks to the central
+        # path; a start near the optimum (as ADMM gives) converges in far fewer
+        cap = 400 if start == "cold" else 120
+        x, st, nw = _polish(host, b, g, z0, gamma=gamma, cap=cap)
+        assert np.all(st == 0)
+        for j in range(s):
+            f = x[j]
+            q = np.sum((G @ f - b.wrench[b.woff[g] + j]) ** 2) + 1e-6 * f @ f
+            assert q == pytest.approx(refs[j]["q"], rel=1e-9, abs=1e-11)
+            assert np.abs(f - refs[j]["f"]).max() <= 2e-5
