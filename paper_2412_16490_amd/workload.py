@@ -291,3 +291,99 @@ def fine_contacts(seed, n_grasps, m=5, m_choices=None, tip=0.02, gap=2e-3, drift
     f32 = lambda a: np.ascontiguousarray(a, np.float32)
     return FineContacts(f32(R), f32(T), f32(cw), f32(pf), f32(pc), counts.astype(np.int32),
                         f32(wq), f32(we))
+
+
+@dataclasses.dataclass
+class HandBatch:
+    """A floating hand over an analytic object per grasp, with the QP's
+    friction coefficients and desired wrenches (the coarse stage of
+    Sec. IV-C on analytic shapes).
+
+    tip_local [G, m_max, 3]  c_{i,l}: fingertip sphere centres in the hand frame
+    semi_axes [G, 3]         the object: ellipsoid sum (x_k / a_k)^2 <= 1 (a sphere when equal)
+    rot       [G, 3, 3]      hand rotation R (row-major)
+    trans     [G, 3]         hand translation T
+    counts    [G] int32      fingertips per grasp (padding tips are zero)
+    woff, mu, wrench         as in Batch
+    """
+    tip_local: np.ndarray
+    semi_axes: np.ndarray
+    rot: np.ndarray
+    trans: np.ndarray
+    counts: np.ndarray
+    woff: np.ndarray
+    mu: np.ndarray
+    wrench: np.ndarray
+    name: str = ""
+
+    @property
+    def n_grasps(self) -> int:
+        return int(self.counts.shape[0])
+
+    @property
+    def m_max(self) -> int:
+        return int(self.tip_local.shape[1])
+
+    @property
+    def n_qps(self) -> int:
+        return int(self.woff[-1])
+
+    def qp_batch(self, points, normals) -> Batch:
+        """The QP batch of these grasps at the given contacts."""
+        return Batch(np.ascontiguousarray(points, np.float32), np.ascontiguousarray(normals, np.float32),
+                     self.mu, self.wrench, self.counts, self.woff, self.name)
+
+
+def hand_batch(seed, n_grasps, m=5, m_choices=None, s=16, shape="ellipsoid", radius=0.01,
+               standoff=(0.005, 0.02), shift=0.005, force_axis=False, mu_range=(0.3, 0.8)):
+    """Rigid hands placed around analytic objects.  The fingertips sit on a
+    thumb-opposes-fingers pattern (the thumb at -y, the fingers spread along
+    x at +y, all tilted towards +z) jittered per grasp, at a distance
+    max(a) + radius + U[standoff] from the hand origin, so that every
+    fingertip sphere starts outside the object; R is a uniform random
+    rotation and T ~ U[-shift, shift]^3.  Objects: ellipsoids with semi-axes
+    ~ U[0.02, 0.08] m, spheres with radius ~ U[0.03, 0.06] m, or a 50/50 mix.
+    Wrenches: s random unit directions per grasp, or the six force axes."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if m_choices is None:
+        counts = np.full(n_grasps, m, np.int32)
+        m_max = m
+    else:
+        counts = rng.choice(np.asarray(m_choices, np.int32), size=n_grasps).astype(np.int32)
+        m_max = int(max(m_choices))
+    ell = rng.uniform(0.02, 0.08, size=(n_grasps, 3))
+    sph = np.repeat(rng.uniform(0.03, 0.06, size=(n_grasps, 1)), 3, axis=1)
+    if shape == "ellipsoid":
+        axes = ell
+    elif shape == "sphere":
+        axes = sph
+    elif shape == "mixed":
+        axes = np.where(rng.random((n_grasps, 1)) < 0.5, ell, sph)
+    else:
+        raise ValueError(shape)
+    tips = np.zeros((n_grasps, m_max, 3))
+    for g in range(n_grasps):
+        k = int(counts[g])
+        dirs = np.zeros((k, 3))
+        dirs[0] = (0.0, -1.0, 0.3)
+        xs = np.linspace(-0.6, 0.6, k - 1) if k > 2 else np.zeros(max(k - 1, 0))
+        for j in range(1, k):
+            dirs[j] = (xs[j - 1], 1.0, 0.3)
+        dirs += 0.1 * rng.standard_normal(dirs.shape)
+        dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+        r = axes[g].max() + radius + rng.uniform(standoff[0], standoff[1], size=(k, 1))
+        tips[g, :k] = r * dirs
+    R = random_rotations(rng, (n_grasps,))
+    T = rng.uniform(-shift, shift, size=(n_grasps, 3))
+    mu = np.zeros((n_grasps, m_max), np.float32)
+    mu[:] = rng.uniform(mu_range[0], mu_range[1], size=(n_grasps, 1))
+    if force_axis:
+        woff = (6 * np.arange(n_grasps + 1)).astype(np.int32)
+        wrench = np.tile(FORCE_AXIS_WRENCHES, (n_grasps, 1))
+    else:
+        woff = (s * np.arange(n_grasps + 1)).astype(np.int32)
+        wrench = wrench_dirs(rng, n_grasps * s)
+    f32 = lambda a: np.ascontiguousarray(a, np.float32)
+    return HandBatch(f32(tips), f32(axes), f32(R), f32(T), counts, woff, mu, wrench,
+                     "hand-%s-m%s-s%s" % (shape, m if m_choices is None else "".join(map(str, m_choices)),
+                                          "6fa" if force_axis else s))
