@@ -88,6 +88,8 @@ def main():
                     help="only run the circular-cone form and print its JSON")
     ap.add_argument("--detach-only", action="store_true",
                     help="only run the fine-stage surrogate (Detach) form at 2^20 grasps and print its JSON")
+    ap.add_argument("--descent-only", action="store_true",
+                    help="only run the coarse-stage descent form (floating hands on ellipsoids)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run device copies of MIB MiB (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -122,6 +124,9 @@ def main():
         return
     if args.detach_only:
         print(json.dumps({"detach_surrogate": detach_form(torch, api, wl, large_only=True)}), flush=True)
+        return
+    if args.descent_only:
+        print(json.dumps({"coarse_descent": descent_form(torch, api, wl)}), flush=True)
         return
 
     batch = wl.config(1)
@@ -293,6 +298,7 @@ def forms(torch, api, wl):
         sf.close()
     res["detach_surrogate"] = detach_form(torch, api, wl)
     res["circular_cone"] = cone_form(torch, api, wl)
+    res["coarse_descent"] = descent_form(torch, api, wl)
     # forward + backward (differentiation workload, same shape as the headline)
     b2 = wl.config(2)
     db2 = api.DeviceBatch(b2)
@@ -321,6 +327,60 @@ def forms(torch, api, wl):
                       "grasps_per_s": round(db2.n_grasps / tfb, 1)}
     s2.close()
     return res
+
+
+def descent_form(torch, api, wl, iters=20):
+    """The bilevel loop on synthetic data (coarse stage on analytic objects):
+    8192 floating 5-fingertip hands on ellipsoids, 16 wrenches each, `iters`
+    gradient steps of w_qp sum_j Q_j + w_dist E^c_d in one call (per step:
+    contact query, QP solve warm-started from the previous step, QP gradient,
+    pose gradient, pose update), timed with events on the solver's stream;
+    plus the per-launch times of the query and pose-gradient kernels."""
+    hb = wl.hand_batch(16497, 8192, m=5, s=16)
+    stream = torch.cuda.current_stream()
+    sv = api.Solver(api.default_params(m_max=5, s_max=16), stream=stream.cuda_stream)
+    dh = api.DeviceHand(hb)
+    st = api.new_state(dh.n_grasps, dh.n_qps, 5)
+    rs = api.new_result(dh.n_grasps, dh.n_qps, 5)
+    rot0, trans0 = dh.rot.clone(), dh.trans.clone()
+    sv.descend(dh, api.descent(iters=2), state=st, result=rs, trace=False)
+    dh.rot.copy_(rot0)
+    dh.trans.copy_(trans0)
+    d = api.descent(iters=iters)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    rs, tr = sv.descend(dh, d, state=st, result=rs)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    trn = tr.cpu().numpy()
+    conv = int(np.sum((rs["status"].cpu().numpy() & api.ST_CONVERGED) != 0))
+    # the two hand kernels on their own (same stream)
+    n = 50
+    q = sv.contact_query(dh)
+    e0.record(stream)
+    for _ in range(n):
+        sv.contact_query(dh, out=q)
+    e1.record(stream)
+    e1.synchronize()
+    q_us = e0.elapsed_time(e1) / n * 1e3
+    dP = torch.zeros((dh.n_grasps, 5, 3), device="cuda")
+    e0.record(stream)
+    for _ in range(n):
+        sv.pose_gradient(dh, dP, dP, 1000.0, 0.01, 0.0)
+    e1.record(stream)
+    e1.synchronize()
+    g_us = e0.elapsed_time(e1) / n * 1e3
+    sv.close()
+    return {"workload": "8192 floating hands x 5 fingertips on ellipsoids, 16 wrenches each (seed 16497)",
+            "iters": iters, "ms": round(ms, 3), "ms_per_step": round(ms / iters, 4),
+            "grasp_steps_per_s": round(dh.n_grasps * iters / (ms / 1e3), 1),
+            "qp_solves_per_s": round(dh.n_qps * iters / (ms / 1e3), 1),
+            "last_step_converged": conv, "loss_first_mean": round(float(trn[0].mean()), 5),
+            "loss_last_mean": round(float(trn[-1].mean()), 5),
+            "frac_grasps_lowered": round(float(np.mean(trn[-1] < trn[0])), 4),
+            "contact_query_kernel_us": round(q_us, 2), "pose_gradient_kernel_us": round(g_us, 2)}
 
 
 def cone_form(torch, api, wl):

@@ -260,6 +260,90 @@ int bodex_qp_detach_energy(bodex_qp_t *h, const bodex_fine_contacts *in,
                            float *e_dist, float *dL_dR, float *dL_dT,
                            int accumulate);
 
+/* A floating hand over an analytic object, one per grasp: the step before
+ * the QP in the coarse stage (Sec. IV-B forward kinematics for a hand whose
+ * fingertips share the root transform; Sec. IV-C nearest-point query and
+ * distance energy, here on analytic shapes).  Arrays [G][m][...] contiguous
+ * in that order. */
+typedef struct {
+    int n_grasps;             /* G >= 0                                       */
+    int m;                    /* fingertips per grasp in the layout, 1..8     */
+    const int *contact_count; /* device [G] fingertips used (<= m); NULL = m  */
+    const float *tip_local;   /* device [G][m][3] c_{i,l}: centre of the      */
+                              /* fingertip's sphere in the hand frame         */
+    const float *semi_axes;   /* device [G][3] the object: the solid ellipsoid */
+                              /* sum_k (x_k / a_k)^2 <= 1 centred at the world */
+                              /* origin (a sphere when equal); a_k > 0, not   */
+                              /* checked (non-positive axes give NaN outputs) */
+    float *hand_rot;          /* device [G][3][3] R, row-major rotation       */
+    float *hand_trans;        /* device [G][3] T                              */
+                              /* (both updated in place by bodex_qp_descend)  */
+} bodex_hand;
+
+/* Contacts of every fingertip: c_i = R c_{i,l} + T, the nearest point p_i of
+ * the object's surface, its inward unit normal n_i and the signed distance
+ * d_i of c_i (positive outside).  Computed in FP64 (the nearest point is the
+ * root of the Lagrange condition, found by a monotone Newton iteration).
+ * Where the nearest point is not unique (the medial ridge inside the object,
+ * including a sphere's centre) one of them is returned.  Outputs points,
+ * normals: device [G][m][3] (the layout of bodex_batch when m = m_max);
+ * dist: device [G][m] or NULL.  Fingertips at or beyond contact_count[g] get
+ * zeros.  Uses no workspace.  Errors: EINVAL (m outside 1..8, G < 0, a
+ * required pointer NULL, misaligned), EHIP. */
+int bodex_qp_contact_query(bodex_qp_t *h, const bodex_hand *in, float *points,
+                           float *normals, float *dist);
+
+/* Gradient with respect to the hand pose of
+ *     L = (the caller's loss through the contacts) + w_dist E^c_d,
+ *     E^c_d = sum_i (d_i - radius - offset)^2
+ * (the coarse distance energy of Sec. IV-C with the signed distance; radius
+ * is the fingertip sphere's radius alpha, offset the pre-grasp distance
+ * reduction of Sec. IV-D).  dL_dpoints, dL_dnormals: device [G][m][3], e.g.
+ * from bodex_qp_backward; either may be NULL (no such term).  The contacts'
+ * derivative is the exact Jacobian of the query (implicit function theorem;
+ * zero where the nearest point is not unique).  Outputs (each optional):
+ * e_dist [G] = E^c_d; dL_drot [G][3] = dL/domega for the world-frame
+ * rotation vector omega of R(omega) = Exp(omega) R, i.e.
+ * sum_i (R c_{i,l}) x dL/dc_i; dL_dtrans [G][3] = sum_i dL/dc_i.  Uses no
+ * workspace.  Errors: EINVAL, EHIP. */
+int bodex_qp_pose_gradient(bodex_qp_t *h, const bodex_hand *in,
+                           const float *dL_dpoints, const float *dL_dnormals,
+                           float w_dist, float radius, float offset,
+                           float *e_dist, float *dL_drot, float *dL_dtrans);
+
+/* Upper-level descent of the bilevel problem (Eq. 4-6 with the QPs of
+ * Eq. 7-9) for floating hands on analytic objects. */
+typedef struct {
+    int iters;        /* gradient steps, >= 0                              */
+    float w_qp;       /* weight of E_g = sum_j Q_j                         */
+    float w_dist;     /* weight of E^c_d (see bodex_qp_pose_gradient)      */
+    float radius;     /* fingertip sphere radius alpha                     */
+    float offset;     /* distance reduction delta (pre-grasp)              */
+    float step_rot;   /* eta_R: R <- Exp(-eta_R dL/domega) R               */
+    float step_trans; /* eta_T: T <- T - eta_T dL/dT                       */
+} bodex_descent;
+
+/* `iters` steps of gradient descent on L = w_qp E_g + w_dist E^c_d over the
+ * hand pose: per step, the contacts of the current pose (as
+ * bodex_qp_contact_query), the QPs of every wrench at those contacts (as
+ * bodex_qp_solve with the handle's parameters; from the second step on the
+ * ADMM warm-starts from the previous step's state), the QP gradient (as
+ * bodex_qp_backward with dL/dE_g = w_qp), the pose gradient (as
+ * bodex_qp_pose_gradient) and the update of hand->hand_rot / hand_trans in
+ * place.  `qp` gives the QP side: contact_count and wrench_offset (HOST), mu,
+ * wrench_dir; its points and normals must be NULL (the library writes the
+ * contacts into its workspace), and hand->contact_count must be NULL (the
+ * counts are qp->contact_count); hand->m must equal the handle's m_max.
+ * `out` receives the QP results of the last step and holds the state (its
+ * state pointers may be NULL: the library's workspace); the first step
+ * warm-starts only with BODEX_F_WARM_START.  loss_trace: optional device
+ * [iters][G], L of each grasp at the pose before each step.  Everything is
+ * enqueued on the handle's stream.  Errors: EINVAL, EUNSUP, EINFEAS,
+ * EBUDGET, EHIP. */
+int bodex_qp_descend(bodex_qp_t *h, const bodex_hand *hand,
+                     const bodex_batch *qp, const bodex_descent *d,
+                     bodex_result *out, float *loss_trace);
+
 #ifdef __cplusplus
 }
 #endif

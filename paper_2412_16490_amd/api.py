@@ -66,6 +66,23 @@ class FineContacts(ctypes.Structure):
     ]
 
 
+class Hand(ctypes.Structure):
+    _fields_ = [
+        ("n_grasps", ctypes.c_int), ("m", ctypes.c_int),
+        ("contact_count", ctypes.c_void_p), ("tip_local", ctypes.c_void_p),
+        ("semi_axes", ctypes.c_void_p), ("hand_rot", ctypes.c_void_p),
+        ("hand_trans", ctypes.c_void_p),
+    ]
+
+
+class Descent(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int), ("w_qp", ctypes.c_float), ("w_dist", ctypes.c_float),
+        ("radius", ctypes.c_float), ("offset", ctypes.c_float),
+        ("step_rot", ctypes.c_float), ("step_trans", ctypes.c_float),
+    ]
+
+
 class State(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("z", ctypes.c_void_p),
                 ("y", ctypes.c_void_p), ("rho", ctypes.c_void_p)]
@@ -121,6 +138,14 @@ def lib():
         L.bodex_qp_detach_energy.argtypes = [ctypes.c_void_p, ctypes.POINTER(FineContacts)] + [ctypes.c_void_p] * 6 + [
             ctypes.c_int]
         L.bodex_qp_detach_energy.restype = ctypes.c_int
+        L.bodex_qp_contact_query.argtypes = [ctypes.c_void_p, ctypes.POINTER(Hand)] + [ctypes.c_void_p] * 3
+        L.bodex_qp_contact_query.restype = ctypes.c_int
+        L.bodex_qp_pose_gradient.argtypes = [ctypes.c_void_p, ctypes.POINTER(Hand), ctypes.c_void_p,
+                                             ctypes.c_void_p] + [ctypes.c_float] * 3 + [ctypes.c_void_p] * 3
+        L.bodex_qp_pose_gradient.restype = ctypes.c_int
+        L.bodex_qp_descend.argtypes = [ctypes.c_void_p, ctypes.POINTER(Hand), ctypes.POINTER(Batch),
+                                       ctypes.POINTER(Descent), ctypes.POINTER(Result), ctypes.c_void_p]
+        L.bodex_qp_descend.restype = ctypes.c_int
         _lib = L
         return L
 
@@ -128,7 +153,8 @@ def lib():
 EXPORTED = ("bodex_qp_default_params", "bodex_qp_create", "bodex_qp_set_stream",
             "bodex_qp_solve", "bodex_qp_backward", "bodex_qp_destroy",
             "bodex_qp_last_error", "bodex_qp_state_bytes", "bodex_qp_last_stats",
-            "bodex_qp_kernel_times", "bodex_qp_detach_energy")
+            "bodex_qp_kernel_times", "bodex_qp_detach_energy", "bodex_qp_contact_query",
+            "bodex_qp_pose_gradient", "bodex_qp_descend")
 
 
 def default_params(**overrides) -> Params:
@@ -240,6 +266,19 @@ def _c_state(st) -> State:
     return s
 
 
+def _c_result(result: dict, state: dict | None) -> Result:
+    r = Result()
+    r.forces = _ptr(result["forces"])
+    r.qp_obj = _ptr(result["qp_obj"])
+    r.energy = _ptr(result["energy"])
+    r.kkt_rel = _ptr(result["kkt_rel"])
+    r.iters = _ptr(result["iters"])
+    r.status = _ptr(result["status"])
+    r.state = _c_state(state)
+    r.polish_flops = _ptr(result["polish_flops"]) if result.get("polish_flops") is not None else None
+    return r
+
+
 def bodex_qp_solve(h, batch: DeviceBatch, result: dict, state: dict | None = None) -> None:
     r = Result()
     r.forces = _ptr(result["forces"])
@@ -311,6 +350,83 @@ def bodex_qp_detach_energy(h, fc: DeviceFineContacts, q_surr, e_dist, w_q=None, 
                                         _ptr(dL_dR), _ptr(dL_dT), 1 if accumulate else 0), h)
 
 
+class DeviceHand:
+    """Device copies of a workload.HandBatch: the hand side (fingertips,
+    object, pose; the pose tensors are updated in place by descend) and the
+    QP side (host CSR arrays, friction, desired wrenches)."""
+
+    def __init__(self, hb, device="cuda"):
+        import torch
+        t = lambda a, dt=np.float32: torch.as_tensor(np.ascontiguousarray(a, dt), device=device).clone()
+        self.counts = np.ascontiguousarray(hb.counts, dtype=np.int32)
+        self.woff = np.ascontiguousarray(hb.woff, dtype=np.int32)
+        self.d_counts = t(hb.counts, np.int32)
+        self.tip = t(hb.tip_local)
+        self.axes = t(hb.semi_axes)
+        self.rot = t(hb.rot)
+        self.trans = t(hb.trans)
+        self.mu = t(hb.mu)
+        self.wrench = t(hb.wrench)
+        self.n_grasps = int(self.counts.shape[0])
+        self.n_qps = int(self.woff[-1])
+        self.m = int(self.tip.shape[1])
+
+    def c_struct(self, counts=True) -> Hand:
+        h = Hand()
+        h.n_grasps = self.n_grasps
+        h.m = self.m
+        h.contact_count = _ptr(self.d_counts) if counts else None
+        h.tip_local = _ptr(self.tip)
+        h.semi_axes = _ptr(self.axes)
+        h.hand_rot = _ptr(self.rot)
+        h.hand_trans = _ptr(self.trans)
+        return h
+
+    def c_qp(self) -> Batch:
+        """The QP side for descend (points and normals NULL)."""
+        b = Batch()
+        b.n_grasps = self.n_grasps
+        b.n_qps = self.n_qps
+        b.contact_count = self.counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        b.wrench_offset = self.woff.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        b.points = None
+        b.normals = None
+        b.mu = _ptr(self.mu)
+        b.wrench_dir = _ptr(self.wrench)
+        return b
+
+
+def bodex_qp_contact_query(h, hand: DeviceHand, points, normals, dist=None, counts: bool = True) -> None:
+    c = hand.c_struct(counts)
+    _check(lib().bodex_qp_contact_query(h, ctypes.byref(c), _ptr(points), _ptr(normals), _ptr(dist)), h)
+
+
+def bodex_qp_pose_gradient(h, hand: DeviceHand, dL_dpoints=None, dL_dnormals=None, w_dist=0.0, radius=0.0,
+                           offset=0.0, e_dist=None, dL_drot=None, dL_dtrans=None, counts: bool = True) -> None:
+    c = hand.c_struct(counts)
+    _check(lib().bodex_qp_pose_gradient(h, ctypes.byref(c), _ptr(dL_dpoints), _ptr(dL_dnormals), float(w_dist),
+                                        float(radius), float(offset), _ptr(e_dist), _ptr(dL_drot),
+                                        _ptr(dL_dtrans)), h)
+
+
+def descent(iters=20, w_qp=1.0, w_dist=1000.0, radius=0.01, offset=0.0, step_rot=2e-3,
+            step_trans=1e-5) -> Descent:
+    """Descent parameters (defaults: the synthetic coarse-stage setting)."""
+    d = Descent()
+    d.iters, d.w_qp, d.w_dist, d.radius, d.offset = int(iters), w_qp, w_dist, radius, offset
+    d.step_rot, d.step_trans = step_rot, step_trans
+    return d
+
+
+def bodex_qp_descend(h, hand: DeviceHand, d: Descent, result: dict, state: dict | None = None,
+                     loss_trace=None) -> None:
+    c = hand.c_struct(counts=False)
+    b = hand.c_qp()
+    r = _c_result(result, state)
+    _check(lib().bodex_qp_descend(h, ctypes.byref(c), ctypes.byref(b), ctypes.byref(d), ctypes.byref(r),
+                                  _ptr(loss_trace)), h)
+
+
 class Solver:
     """A handle on one device and stream (torch's current stream by default)."""
 
@@ -356,6 +472,44 @@ class Solver:
         bodex_qp_detach_energy(self.h, fc, out["q_surr"], out["e_dist"], fc.w_q, fc.w_e,
                                out.get("dL_dR"), out.get("dL_dT"), accumulate)
         return out
+
+    def contact_query(self, hand: DeviceHand, out=None):
+        """points, normals [G][m][3] and signed distances [G][m] of the pose."""
+        import torch
+        G, m = hand.n_grasps, hand.m
+        dev = hand.tip.device
+        if out is None:
+            out = {"points": torch.empty((G, m, 3), dtype=torch.float32, device=dev),
+                   "normals": torch.empty((G, m, 3), dtype=torch.float32, device=dev),
+                   "dist": torch.empty((G, m), dtype=torch.float32, device=dev)}
+        bodex_qp_contact_query(self.h, hand, out["points"], out["normals"], out.get("dist"))
+        return out
+
+    def pose_gradient(self, hand: DeviceHand, dL_dpoints=None, dL_dnormals=None, w_dist=0.0, radius=0.0,
+                      offset=0.0):
+        """E^c_d [G], dL/domega [G][3], dL/dT [G][3]."""
+        import torch
+        G = hand.n_grasps
+        dev = hand.tip.device
+        out = {"e_dist": torch.empty(G, dtype=torch.float32, device=dev),
+               "dL_drot": torch.empty((G, 3), dtype=torch.float32, device=dev),
+               "dL_dtrans": torch.empty((G, 3), dtype=torch.float32, device=dev)}
+        bodex_qp_pose_gradient(self.h, hand, dL_dpoints, dL_dnormals, w_dist, radius, offset,
+                               out["e_dist"], out["dL_drot"], out["dL_dtrans"])
+        return out
+
+    def descend(self, hand: DeviceHand, d: Descent | None = None, state: dict | None = None,
+                result: dict | None = None, trace: bool = True):
+        """Run d.iters descent steps (hand.rot / hand.trans updated in place);
+        returns the last step's QP result and the loss trace [iters][G]."""
+        import torch
+        d = d if d is not None else descent()
+        if result is None:
+            result = new_result(hand.n_grasps, hand.n_qps, self.params.m_max)
+        tr = torch.empty((max(d.iters, 1), hand.n_grasps), dtype=torch.float32, device=hand.tip.device) \
+            if trace else None
+        bodex_qp_descend(self.h, hand, d, result, state, tr)
+        return result, tr
 
     def stats(self):
         return last_stats(self.h)

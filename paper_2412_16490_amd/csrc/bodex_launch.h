@@ -30,4 +30,27 @@ struct DetachArgs {
 };
 hipError_t launch_detach(const DetachArgs& a, hipStream_t st);
 int detach_blocks(int G, int M);
+
+// Floating hand over an analytic object (coarse stage): arrays [G][M][...];
+// counts may be null (all M).  The query writes points, normals (and dist if
+// set).  The step kernel reads dLdp / dLdn (either may be null), writes the
+// optional e_dist, dLdrot, dLdtrans and trace (= w_qp e_qp + w_dist E^c_d,
+// e_qp may be null), updates rot / trans when `step` is set, and then, when
+// `requery` is set, writes the contacts of the (new) pose like the query.
+struct HandArgs {
+    int G, M;
+    const int* counts;
+    const float *tip, *axes;
+    float *rot, *trans;
+    float *points, *normals, *dist;
+    const float *dLdp, *dLdn, *e_qp;
+    float w_qp, w_dist, radius, offset;
+    float *e_dist, *dLdrot, *dLdtrans, *trace;
+    float step_rot, step_trans;
+    int step, requery;
+};
+hipError_t launch_hand_query(const HandArgs& a, hipStream_t st);
+hipError_t launch_hand_step(const HandArgs& a, hipStream_t st);
+hipError_t launch_fill(float* p, int n, float v, hipStream_t st);
+int hand_blocks(int G, int M);
 }  // namespace bodex

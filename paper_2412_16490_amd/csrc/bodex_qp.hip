@@ -61,6 +61,9 @@ struct bodex_qp {
     // internal state when the caller passes none
     float* d_state = nullptr;
     size_t d_state_cap = 0;
+    // descent workspace: contacts, their gradients, distances, loss weights
+    float* d_hand = nullptr;
+    size_t d_hand_cap = 0;
     // graphs
     std::vector<GraphEntry> graphs;
     uint64_t graph_clock = 0;
@@ -373,6 +376,34 @@ void bind_desc(KArgs& a, const int* d, int G, const Schedule& S) {
     a.slots = S.slots;
 }
 
+// Validate a hand batch (pointers only; device contents are not read).
+int validate_hand(bodex_qp* h, const bodex_hand* in) {
+    if (!in) return fail(h, BODEX_EINVAL, "hand is NULL");
+    if (in->n_grasps < 0) return fail(h, BODEX_EINVAL, "n_grasps %d < 0", in->n_grasps);
+    if (in->m < 1 || in->m > BODEX_MAX_CONTACTS)
+        return fail(h, BODEX_EINVAL, "m %d outside 1..%d", in->m, BODEX_MAX_CONTACTS);
+    if (in->n_grasps == 0) return 0;
+    if (!in->tip_local || !in->semi_axes || !in->hand_rot || !in->hand_trans)
+        return fail(h, BODEX_EINVAL, "a hand array is NULL");
+    const void* all[] = {in->contact_count, in->tip_local, in->semi_axes, in->hand_rot, in->hand_trans};
+    for (const void* p : all)
+        if (!aligned4(p)) return fail(h, BODEX_EINVAL, "hand arrays must be 4-byte aligned");
+    return 0;
+}
+
+bodex::HandArgs hand_args(const bodex_hand* in) {
+    bodex::HandArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.G = in->n_grasps;
+    a.M = in->m;
+    a.counts = in->contact_count;
+    a.tip = in->tip_local;
+    a.axes = in->semi_axes;
+    a.rot = in->hand_rot;
+    a.trans = in->hand_trans;
+    return a;
+}
+
 int occupancy_grid(bodex_qp* h, int blocks_per_cu_cap, int n_tiles) {
     int g = h->n_cu * blocks_per_cu_cap;
     return std::max(1, std::min(g, n_tiles));
@@ -659,6 +690,7 @@ int bodex_qp_destroy(bodex_qp_t* h) {
     }
     if (h->d_desc) (void)hipFree(h->d_desc);
     if (h->d_state) (void)hipFree(h->d_state);
+    if (h->d_hand) (void)hipFree(h->d_hand);
     if (h->h_desc) (void)hipHostFree(h->h_desc);
     if (h->desc_ev) (void)hipEventDestroy(h->desc_ev);
     for (auto& e : h->tev)
@@ -698,6 +730,182 @@ int bodex_qp_last_stats(bodex_qp_t* h, int* launches, int* graph_replays, int* t
     if (launches) *launches = h->last_launches;
     if (graph_replays) *graph_replays = h->last_replays;
     if (tiles) *tiles = h->last_tiles;
+    return 0;
+}
+
+int bodex_qp_contact_query(bodex_qp_t* h, const bodex_hand* in, float* points, float* normals, float* dist) {
+    if (!h) return BODEX_EINVAL;
+    int rc = validate_hand(h, in);
+    if (rc) return rc;
+    if (in->n_grasps == 0) return 0;
+    if (!points || !normals) return fail(h, BODEX_EINVAL, "points / normals are NULL");
+    if (!aligned4(points) || !aligned4(normals) || !aligned4(dist))
+        return fail(h, BODEX_EINVAL, "outputs must be 4-byte aligned");
+    HIP_TRY(h, hipSetDevice(h->device));
+    bodex::HandArgs a = hand_args(in);
+    a.points = points;
+    a.normals = normals;
+    a.dist = dist;
+    HIP_TRY(h, bodex::launch_hand_query(a, h->stream));
+    h->last_launches = 1;
+    return 0;
+}
+
+int bodex_qp_pose_gradient(bodex_qp_t* h, const bodex_hand* in, const float* dL_dpoints, const float* dL_dnormals,
+                           float w_dist, float radius, float offset, float* e_dist, float* dL_drot,
+                           float* dL_dtrans) {
+    if (!h) return BODEX_EINVAL;
+    int rc = validate_hand(h, in);
+    if (rc) return rc;
+    if (!std::isfinite(w_dist) || !std::isfinite(radius) || !std::isfinite(offset))
+        return fail(h, BODEX_EINVAL, "w_dist, radius and offset must be finite");
+    if (in->n_grasps == 0) return 0;
+    const void* all[] = {dL_dpoints, dL_dnormals, e_dist, dL_drot, dL_dtrans};
+    for (const void* p : all)
+        if (!aligned4(p)) return fail(h, BODEX_EINVAL, "arrays must be 4-byte aligned");
+    HIP_TRY(h, hipSetDevice(h->device));
+    bodex::HandArgs a = hand_args(in);
+    a.dLdp = dL_dpoints;
+    a.dLdn = dL_dnormals;
+    a.w_dist = w_dist;
+    a.radius = radius;
+    a.offset = offset;
+    a.e_dist = e_dist;
+    a.dLdrot = dL_drot;
+    a.dLdtrans = dL_dtrans;
+    HIP_TRY(h, bodex::launch_hand_step(a, h->stream));
+    h->last_launches = 1;
+    return 0;
+}
+
+int bodex_qp_descend(bodex_qp_t* h, const bodex_hand* hand, const bodex_batch* qp, const bodex_descent* d,
+                     bodex_result* out, float* loss_trace) {
+    if (!h) return BODEX_EINVAL;
+    int rc = validate_hand(h, hand);
+    if (rc) return rc;
+    if (!qp || !d || !out) return fail(h, BODEX_EINVAL, "qp batch, descent parameters or result is NULL");
+    if (hand->contact_count) return fail(h, BODEX_EINVAL, "hand->contact_count must be NULL (qp->contact_count is used)");
+    if (qp->points || qp->normals) return fail(h, BODEX_EINVAL, "qp->points and qp->normals must be NULL");
+    if (hand->m != h->prm.m_max) return fail(h, BODEX_EINVAL, "hand->m %d != m_max %d", hand->m, h->prm.m_max);
+    if (qp->n_grasps != hand->n_grasps)
+        return fail(h, BODEX_EINVAL, "qp->n_grasps %d != hand->n_grasps %d", qp->n_grasps, hand->n_grasps);
+    if (d->iters < 0) return fail(h, BODEX_EINVAL, "iters %d < 0", d->iters);
+    const float fp[] = {d->w_qp, d->w_dist, d->radius, d->offset, d->step_rot, d->step_trans};
+    for (float v : fp)
+        if (!std::isfinite(v)) return fail(h, BODEX_EINVAL, "descent parameters must be finite");
+    if (!aligned4(loss_trace)) return fail(h, BODEX_EINVAL, "loss_trace must be 4-byte aligned");
+    const int G = hand->n_grasps, M = hand->m;
+    h->last_launches = 0;
+    if (G == 0 || d->iters == 0) return 0;
+    if (!out->forces || !out->qp_obj || !out->energy || !out->kkt_rel || !out->iters || !out->status)
+        return fail(h, BODEX_EINVAL, "an output pointer is NULL");
+    const bodex_state& st = out->state;
+    const bool have_state = st.x || st.z || st.y || st.rho;
+    if (have_state && !(st.x && st.z && st.y && st.rho))
+        return fail(h, BODEX_EINVAL, "state pointers must be all set or all NULL");
+    if ((h->prm.flags & BODEX_F_WARM_START) && !have_state)
+        return fail(h, BODEX_EINVAL, "warm start needs the caller's state");
+    HIP_TRY(h, hipSetDevice(h->device));
+
+    // workspace: points, normals, dL/dpoints, dL/dnormals [G][M][3], dist [G][M], w_qp [G]
+    const size_t gm = size_t(G) * M;
+    rc = ensure_device(h, reinterpret_cast<void**>(&h->d_hand), &h->d_hand_cap, (12 * gm + gm + G) * sizeof(float));
+    if (rc) return rc;
+    float* P = h->d_hand;
+    float* N = P + 3 * gm;
+    float* dP = N + 3 * gm;
+    float* dN = dP + 3 * gm;
+    float* D = dN + 3 * gm;
+    float* wq = D + gm;
+    bodex_batch qb = *qp;
+    qb.points = P;
+    qb.normals = N;
+    rc = validate_batch(h, &qb);
+    if (rc) return rc;
+    const int W = qb.n_qps;
+
+    const int mm = kernel_mm(h->prm.m_max);
+    const bool cone = h->prm.friction_cone == BODEX_CONE_CIRCULAR;
+    const int nv = 3 * h->prm.m_max, nr = (cone ? 3 : 9) * h->prm.m_max + 1;
+    const bool batched = (h->prm.flags & BODEX_F_BATCHED) != 0;
+    Schedule S;
+    build_schedule(qb.contact_count, qb.wrench_offset, G, batched, S);
+    h->last_tiles = S.n_tiles;
+    KArgs a = make_args(h, &qb);
+    if (have_state) {
+        a.x = st.x;
+        a.z = st.z;
+        a.y = st.y;
+        a.rho = st.rho;
+    } else {
+        const size_t need = (size_t(W) * (nv + 2 * nr) + size_t(G)) * sizeof(float);
+        rc = ensure_device(h, reinterpret_cast<void**>(&h->d_state), &h->d_state_cap, need);
+        if (rc) return rc;
+        a.x = h->d_state;
+        a.z = a.x + size_t(W) * nv;
+        a.y = a.z + size_t(W) * nr;
+        a.rho = a.y + size_t(W) * nr;
+    }
+    a.forces = out->forces;
+    a.qobj = out->qp_obj;
+    a.energy = out->energy;
+    a.kkt = out->kkt_rel;
+    a.iters = out->iters;
+    a.status = out->status;
+    a.pflops = out->polish_flops;
+    const size_t n_ints = size_t(G) * 3 + 1 + S.n_tiles + 1 + 4;
+    rc = ensure_device(h, reinterpret_cast<void**>(&h->d_desc), &h->d_desc_cap, n_ints * sizeof(int));
+    if (rc) return rc;
+    size_t up = 0;
+    rc = upload_desc(h, &qb, S, h->d_desc, &up);
+    if (rc) return rc;
+    bind_desc(a, h->d_desc, G, S);
+    int* d_queue = h->d_desc + (n_ints - 4);
+    const size_t lds_a = admm_lds(mm, S.slots);
+    const size_t lds_f = cone ? bodex::cone_fin_lds(mm, S.slots, h->prm.gamma > 0.f) : fin_lds(mm, S.slots, false);
+    const size_t lds_b = fin_lds(mm, S.slots, true);
+    const int per_cu = std::max(1, std::min(16, int((160 * 1024) / std::max<size_t>(lds_a, 1))));
+    const int grid_a = batched ? occupancy_grid(h, per_cu, S.n_tiles) : S.n_tiles;
+
+    bodex::HandArgs ha = hand_args(hand);
+    ha.counts = a.counts;  // the uploaded copy of qp->contact_count
+    ha.points = P;
+    ha.normals = N;
+    ha.dist = D;
+    HIP_TRY(h, bodex::launch_fill(wq, G, d->w_qp, h->stream));
+    HIP_TRY(h, bodex::launch_hand_query(ha, h->stream));
+    for (int k = 0; k < d->iters; ++k) {
+        KArgs ak = a;
+        if (k > 0) ak.warm = 1;
+        HIP_TRY(h, bodex::launch_reset(d_queue, 4, h->stream));
+        ak.queue = batched ? d_queue : nullptr;
+        HIP_TRY(h, launch(Kind::Admm, mm, ak, grid_a, lds_a, h->stream, h->prm.admm_waves));
+        ak.queue = nullptr;
+        HIP_TRY(h, launch(Kind::Fin, mm, ak, S.n_tiles, lds_f, h->stream));
+        KArgs ab = a;
+        ab.queue = nullptr;
+        ab.dLdE = wq;
+        ab.dLdQ = nullptr;
+        ab.dP = dP;
+        ab.dN = dN;
+        ab.accumulate = 0;
+        HIP_TRY(h, launch(Kind::Bwd, mm, ab, S.n_tiles, lds_b, h->stream));
+        bodex::HandArgs hs = ha;
+        hs.dLdp = dP;
+        hs.dLdn = dN;
+        hs.e_qp = out->energy;
+        hs.w_qp = d->w_qp;
+        hs.w_dist = d->w_dist;
+        hs.radius = d->radius;
+        hs.offset = d->offset;
+        hs.trace = loss_trace ? loss_trace + size_t(k) * G : nullptr;
+        hs.step = 1;
+        hs.step_rot = d->step_rot;
+        hs.step_trans = d->step_trans;
+        hs.requery = 1;
+        HIP_TRY(h, bodex::launch_hand_step(hs, h->stream));
+    }
+    h->last_launches = 2 + 5 * d->iters;
     return 0;
 }
 

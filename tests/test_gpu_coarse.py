@@ -1,0 +1,253 @@
+"""GPU parity of the coarse stage on analytic objects (floating hand, nearest
+point on an ellipsoid, E^c_d, pose gradient and descent; Sec. IV-B and the
+coarse stage of Sec. IV-C) against the FP64 oracle, through the C ABI.
+
+Tolerances.  The kernels compute in FP64 from the same FP32 inputs the oracle
+reads, so contacts, distances and pose gradients differ from the oracle by the
+FP32 rounding of the outputs (u = 2^-24 relative) plus FP64 rounding: points
+and distances 2u |value| + 1e-12 m, normals 4u, gradients 4u times the sum of
+the fingertips' absolute contributions.  A descent step moves the pose by
+eta times the gradient, whose QP part carries the QP gradient tolerance (1e-3
+relative per grasp); the pose after one step is compared at that bound plus
+the FP32 rounding of the stored pose.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import coarse as oc
+from paper_2412_16490_amd import api
+from paper_2412_16490_amd import workload as wl
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -24
+# the kernels read these as FP32; the oracle gets the same rounded values
+_f32 = lambda v: float(np.float32(v))
+DESC = {k: _f32(v) for k, v in dict(w_qp=1.0, w_dist=1000.0, radius=0.01, offset=0.0, step_rot=2e-3,
+                                     step_trans=1e-5).items()}
+
+
+@pytest.fixture(scope="module")
+def solver():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = api.Solver(api.default_params(m_max=5, s_max=16))
+    yield s
+    s.close()
+
+
+def _np(t):
+    return t.cpu().numpy().astype(np.float64)
+
+
+def _f64(hb):
+    return (hb.rot.astype(np.float64), hb.trans.astype(np.float64), hb.tip_local.astype(np.float64),
+            hb.semi_axes.astype(np.float64))
+
+
+@pytest.mark.parametrize("shape,mc,G", [("ellipsoid", None, 700), ("sphere", None, 300), ("mixed", (4, 5), 513)])
+def test_contact_query_parity(solver, shape, mc, G):
+    import torch
+    hb = wl.hand_batch(100 + G, G, m_choices=mc, shape=shape)
+    print("contact query: %s G=%d m_choices=%s" % (shape, G, mc), flush=True)
+    dh = api.DeviceHand(hb)
+    out = solver.contact_query(dh)
+    torch.cuda.synchronize()
+    R, T, cl, ax = _f64(hb)
+    P, N, D = oc.contact_query(R, T, cl, ax, hb.counts)
+    p, n, d = _np(out["points"]), _np(out["normals"]), _np(out["dist"])
+    assert np.all(np.abs(p - P) <= 2 * U * np.abs(P) + 1e-12)
+    assert np.all(np.abs(n - N) <= 4 * U)
+    assert np.all(np.abs(d - D) <= 2 * U * np.abs(D) + 1e-12)
+    live = np.arange(hb.m_max)[None, :] < hb.counts[:, None]
+    assert np.all(p[~live] == 0) and np.all(n[~live] == 0) and np.all(d[~live] == 0)
+
+
+def test_contact_query_degenerate_points(solver):
+    # fingertips at the object's centre, on its medial ridge and on its surface
+    import torch
+    hb = wl.hand_batch(7, 4, m=5)
+    hb.semi_axes[:] = [0.03, 0.05, 0.07]
+    hb.semi_axes[3] = [0.05, 0.05, 0.05]
+    hb.rot[:] = np.eye(3, dtype=np.float32)
+    hb.trans[:] = 0.0
+    tips = np.array([[0.0, 0.0, 0.0], [0.0, 0.004, -0.003], [0.0, 0.0, 0.001], [0.03, 0.0, 0.0],
+                     [0.0, 0.05, 0.0]], np.float32)
+    hb.tip_local[:] = tips
+    dh = api.DeviceHand(hb)
+    out = solver.contact_query(dh)
+    g = solver.pose_gradient(dh, w_dist=1.0, radius=_f32(0.01))
+    torch.cuda.synchronize()
+    R, T, cl, ax = _f64(hb)
+    P, N, D = oc.contact_query(R, T, cl, ax)
+    np.testing.assert_allclose(_np(out["points"]), P, atol=2 * U * 0.07 + 1e-12)
+    np.testing.assert_allclose(_np(out["normals"]), N, atol=4 * U)
+    np.testing.assert_allclose(_np(out["dist"]), D, atol=2 * U * 0.07 + 1e-12)
+    E, dw, dT = oc.pose_gradient(R, T, cl, ax, None, None, 1.0, _f32(0.01), 0.0)
+    np.testing.assert_allclose(_np(g["e_dist"]), E, rtol=4 * U, atol=1e-12)
+    np.testing.assert_allclose(_np(g["dL_dtrans"]), dT, atol=1e-6)
+    assert np.all(np.isfinite(_np(g["dL_drot"])))
+
+
+def _tip_scales(hb, dLdp, dLdn, w_dist, radius, offset):
+    """Per grasp: sum_i |g_i| and sum_i |R c_l| |g_i| of the oracle's
+    fingertip contributions (the scale of the rounding in the sums)."""
+    R, T, cl, ax = _f64(hb)
+    cw = oc.hand_points(R, T, cl)
+    sT = np.zeros(hb.n_grasps)
+    sw = np.zeros(hb.n_grasps)
+    for g in range(hb.n_grasps):
+        for i in range(int(hb.counts[g])):
+            _, _, d, _ = oc.nearest_point(cw[g, i], ax[g])
+            Jp, Jn, Jd = oc.query_jacobian(cw[g, i], ax[g])
+            gi = np.abs(Jp.T @ dLdp[g, i]) + np.abs(Jn.T @ dLdn[g, i]) + np.abs(2 * w_dist * (d - radius - offset) * Jd)
+            sT[g] += np.linalg.norm(gi)
+            sw[g] += np.linalg.norm(cw[g, i] - T[g]) * np.linalg.norm(gi)
+    return sT, sw
+
+
+@pytest.mark.parametrize("shape,mc", [("ellipsoid", None), ("mixed", (4, 5))])
+def test_pose_gradient_parity(solver, shape, mc):
+    import torch
+    hb = wl.hand_batch(21, 300, m_choices=mc, shape=shape)
+    rng = np.random.default_rng(3)
+    dLdp = rng.standard_normal((hb.n_grasps, hb.m_max, 3)).astype(np.float32)
+    dLdn = rng.standard_normal((hb.n_grasps, hb.m_max, 3)).astype(np.float32)
+    w_dist, radius, offset = _f32(300.0), _f32(0.01), _f32(0.01)
+    dh = api.DeviceHand(hb)
+    g = solver.pose_gradient(dh, torch.as_tensor(dLdp, device="cuda"), torch.as_tensor(dLdn, device="cuda"),
+                             w_dist, radius, offset)
+    torch.cuda.synchronize()
+    R, T, cl, ax = _f64(hb)
+    E, dw, dT = oc.pose_gradient(R, T, cl, ax, dLdp.astype(np.float64), dLdn.astype(np.float64), w_dist, radius,
+                                 offset, hb.counts)
+    sT, sw = _tip_scales(hb, dLdp.astype(np.float64), dLdn.astype(np.float64), w_dist, radius, offset)
+    assert np.all(np.abs(_np(g["e_dist"]) - E) <= 4 * U * E + 1e-15)
+    assert np.all(np.abs(_np(g["dL_dtrans"]) - dT).max(axis=1) <= 4 * U * sT + 1e-12)
+    assert np.all(np.abs(_np(g["dL_drot"]) - dw).max(axis=1) <= 4 * U * sw + 1e-12)
+
+
+def _descend(solver, hb, iters, **kw):
+    import torch
+    dh = api.DeviceHand(hb)
+    d = api.descent(iters=iters, **{**DESC, **kw})
+    st = api.new_state(dh.n_grasps, dh.n_qps, solver.params.m_max,
+                       cone=solver.params.friction_cone == api.CONE_CIRCULAR)
+    res, tr = solver.descend(dh, d, state=st)
+    torch.cuda.synchronize()
+    return dh, res, _np(tr)
+
+
+def _oracle_descend(hb, iters, qps=None):
+    R, T, cl, ax = _f64(hb)
+    return oc.descend(R, T, cl, ax, hb.counts, hb.woff, hb.mu, hb.wrench, iters, **DESC)
+
+
+def test_descend_one_step_matches_oracle(solver):
+    hb = wl.hand_batch(31, 64, m=5, s=16)
+    print("descend: 64 grasps x 5 fingertips x 16 wrenches, 1 step", flush=True)
+    dh, res, tr = _descend(solver, hb, 1)
+    R1, T1, trace = _oracle_descend(hb, 1)
+    L0 = trace[0]
+    s = np.diff(hb.woff)
+    assert np.all(np.abs(tr[0] - L0) <= 1e-5 * np.maximum(L0, 1e-2 * s))
+    R0, T0 = hb.rot.astype(np.float64), hb.trans.astype(np.float64)
+    dT_ref = np.linalg.norm(T1 - T0, axis=1)
+    dR_ref = np.linalg.norm((R1 - R0).reshape(-1, 9), axis=1)
+    eT = np.linalg.norm(_np(dh.trans) - T1, axis=1)
+    eR = np.linalg.norm((_np(dh.rot) - R1).reshape(-1, 9), axis=1)
+    assert np.all(eT <= 1e-3 * dT_ref + 4 * U * np.linalg.norm(T1, axis=1) + 1e-12)
+    assert np.all(eR <= 1e-3 * dR_ref + 6 * U)
+
+
+def test_descend_tracks_the_oracle_and_lowers_the_loss(solver):
+    hb = wl.hand_batch(32, 48, m=5, s=16)
+    K = 8
+    print("descend: 48 grasps, %d steps" % K, flush=True)
+    dh, res, tr = _descend(solver, hb, K)
+    R1, T1, trace = _oracle_descend(hb, K)
+    rel = np.abs(tr - trace) / np.maximum(trace, 1e-2)
+    print("max rel loss deviation per step:", np.round(rel.max(axis=1), 7))
+    # the trajectories separate only through the per-step gradient tolerance
+    assert rel.max() <= 1e-3
+    assert np.mean(tr[-1] < tr[0]) >= 0.95
+    assert np.all(np.isfinite(_np(dh.rot))) and np.all(np.isfinite(_np(dh.trans)))
+    # the contacts of the final pose are those the query returns for it
+    st = np.asarray(res["status"].cpu().numpy())
+    assert np.all(st & api.ST_CONVERGED)
+
+
+def test_descend_mixed_counts_and_circular_cone():
+    import torch
+    hb = wl.hand_batch(33, 40, m_choices=(4, 5), s=12, shape="mixed")
+    for cone in (api.CONE_PYRAMID8, api.CONE_CIRCULAR):
+        p = api.default_params(m_max=5, s_max=16)
+        p.friction_cone = cone
+        s = api.Solver(p)
+        dh, res, tr = _descend(s, hb, 5)
+        s.close()
+        print("cone %d: loss %.4f -> %.4f" % (cone, tr[0].mean(), tr[-1].mean()))
+        assert np.mean(tr[-1] < tr[0]) >= 0.9
+        assert np.all(np.asarray(res["status"].cpu().numpy()) & api.ST_CONVERGED)
+        if cone == api.CONE_PYRAMID8:
+            R1, T1, trace = _oracle_descend(hb, 5)
+            assert np.all(np.abs(tr - trace) <= 1e-3 * np.maximum(trace, 1e-2))
+
+
+def test_descend_full_size_sampled(solver):
+    # the headline shape: 8192 grasps x 5 fingertips x 16 wrenches
+    hb = wl.hand_batch(16497, 8192, m=5, s=16)
+    print("descend: 8192 grasps, 2 steps", flush=True)
+    dh, res, tr = _descend(solver, hb, 2)
+    rng = np.random.default_rng(9)
+    gs = np.unique(np.concatenate([rng.integers(0, 8192, 48), [0, 8191]]))
+    sub = wl.HandBatch(hb.tip_local[gs], hb.semi_axes[gs], hb.rot[gs], hb.trans[gs], hb.counts[gs],
+                       (16 * np.arange(len(gs) + 1)).astype(np.int32), hb.mu[gs],
+                       np.concatenate([hb.wrench[16 * g:16 * g + 16] for g in gs]))
+    R1, T1, trace = _oracle_descend(sub, 2)
+    assert np.all(np.abs(tr[:, gs] - trace) <= 1e-3 * np.maximum(trace, 1e-2))
+    assert np.all(np.isfinite(tr))
+
+
+def test_descend_argument_errors(solver):
+    import torch
+    hb = wl.hand_batch(34, 8, m=5, s=4)
+    dh = api.DeviceHand(hb)
+    L = api.lib()
+    res = api.new_result(dh.n_grasps, dh.n_qps, 5)
+    r = api._c_result(res, None)
+    d = api.descent(iters=2)
+    # contacts come from the library: qp points must be NULL
+    c, b = dh.c_struct(counts=False), dh.c_qp()
+    b.points = ctypes.c_void_p(dh.tip.data_ptr())
+    assert L.bodex_qp_descend(solver.h, ctypes.byref(c), ctypes.byref(b), ctypes.byref(d), ctypes.byref(r),
+                              None) == api.EINVAL
+    # the counts are the QP batch's: hand counts must be NULL
+    c, b = dh.c_struct(counts=True), dh.c_qp()
+    assert L.bodex_qp_descend(solver.h, ctypes.byref(c), ctypes.byref(b), ctypes.byref(d), ctypes.byref(r),
+                              None) == api.EINVAL
+    c = dh.c_struct(counts=False)
+    c.m = 4
+    assert L.bodex_qp_descend(solver.h, ctypes.byref(c), ctypes.byref(dh.c_qp()), ctypes.byref(d),
+                              ctypes.byref(r), None) == api.EINVAL
+    d.iters = -1
+    assert L.bodex_qp_descend(solver.h, ctypes.byref(dh.c_struct(counts=False)), ctypes.byref(dh.c_qp()),
+                              ctypes.byref(d), ctypes.byref(r), None) == api.EINVAL
+    # nothing to do: zero steps and an empty batch
+    d.iters = 0
+    rot0 = dh.rot.clone()
+    assert L.bodex_qp_descend(solver.h, ctypes.byref(dh.c_struct(counts=False)), ctypes.byref(dh.c_qp()),
+                              ctypes.byref(d), ctypes.byref(r), None) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(rot0, dh.rot)
+    c = dh.c_struct()
+    c.n_grasps = 0
+    assert L.bodex_qp_contact_query(solver.h, ctypes.byref(c), None, None, None) == 0
+    c = dh.c_struct()
+    c.m = 9
+    assert L.bodex_qp_contact_query(solver.h, ctypes.byref(c), None, None, None) == api.EINVAL
+    assert L.bodex_qp_pose_gradient(solver.h, ctypes.byref(dh.c_struct()), None, None, float("nan"), 0.0, 0.0,
+                                    None, None, None) == api.EINVAL
