@@ -114,7 +114,10 @@ typedef struct {
     int admm_waves;       /* ADMM kernel register budget as resident waves   */
                           /* per SIMD: 1, 2, 3 or 4 (0 = library default)     */
     float admm_tol;       /* ADMM stops a QP at this relative KKT residual;   */
-                          /* the polish then lifts it to tol_rel (0 = tol_rel) */
+                          /* the polish then lifts it to tol_rel (0 = the     */
+                          /* friction model's default: 1e-1 for PYRAMID8,     */
+                          /* 1e-2 for CIRCULAR; without BODEX_F_POLISH ADMM   */
+                          /* always runs to tol_rel)                          */
     int friction_cone;    /* BODEX_CONE_PYRAMID8 (default) or                 */
                           /* BODEX_CONE_CIRCULAR                              */
 } bodex_qp_params;
@@ -163,7 +166,7 @@ typedef struct bodex_qp bodex_qp_t;
  * eps 1e-6, torque_scale 20, tol 1e-5, 500 iterations, rho0 0.3, alpha 1.6,
  * check every 10, rho in [1e-4, 1e4], hysteresis 5, fp64_cond 1e4, 128 polish
  * steps, 20 iterations per chunk, flags POLISH | ADAPTIVE_RHO, admm_waves 0,
- * admm_tol 1e-2 (with the polish on, ADMM only has to find the active set
+ * admm_tol 0 (the model's default; with the polish on, ADMM only has to find the active set
  * roughly; the polish then solves each QP exactly). */
 void bodex_qp_default_params(bodex_qp_params *p);
 

@@ -692,8 +692,14 @@ __device__ inline LdsPolishData<MM, GAM> polish_data(const KArgs& a, const FinPt
 // Finalize kernel: polish, objective, energy, KKT residual, outputs.  GAM:
 // the polish handles the normal-sum row (gamma > 0).
 // ---------------------------------------------------------------------------
+// Resident waves per SIMD the finalize kernel is compiled for (its register
+// budget): 2 leaves 256 VGPRs per lane.
+#ifndef BODEX_FIN_WAVES
+#define BODEX_FIN_WAVES 2
+#endif
+
 template <int MM, bool GAM>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) finalize_kernel(const KArgs a) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BODEX_FIN_WAVES))) finalize_kernel(const KArgs a) {
     constexpr int NG = 6 * 3 * MM;
     extern __shared__ __align__(16) unsigned char smem[];
     const FinPtrs<MM> P = fin_carve<MM>(smem, a.slots, false);

@@ -238,6 +238,8 @@ int ensure_device(bodex_qp* h, void** ptr, size_t* cap, size_t need) {
 enum class Kind { Admm, Fin, Bwd };
 
 constexpr int kDefaultAdmmWaves = 2;
+// ADMM stopping tolerances with the polish on, per friction model (admm_tol 0)
+constexpr float kAdmmTolPyramid = 1e-1f, kAdmmTolCone = 1e-2f;
 
 hipError_t launch(Kind k, int mm, const KArgs& a, int grid, size_t lds, hipStream_t st, int occ = 0) {
     if (k == Kind::Admm) return bodex::launch_admm(mm, occ > 0 ? occ : kDefaultAdmmWaves, a, grid, lds, st);
@@ -291,8 +293,12 @@ KArgs make_args(const bodex_qp* h, const bodex_batch* in) {
     a.fmax = p.force_max;
     a.gamma = p.gamma;
     a.tol = p.tol_rel;
-    // without the polish nothing lifts a QP past the ADMM tolerance
-    a.admm_tol = (p.admm_tol > 0.f && (p.flags & BODEX_F_POLISH)) ? p.admm_tol : p.tol_rel;
+    // without the polish nothing lifts a QP past the ADMM tolerance; 0 picks
+    // the friction model's default (the pyramid's active-set polish costs the
+    // same from a rough ADMM point, the cone's barrier polish takes fewer
+    // Newton steps from a closer one)
+    const float model_tol = p.friction_cone == BODEX_CONE_CIRCULAR ? kAdmmTolCone : kAdmmTolPyramid;
+    a.admm_tol = !(p.flags & BODEX_F_POLISH) ? p.tol_rel : (p.admm_tol > 0.f ? p.admm_tol : model_tol);
     a.rho0 = p.rho0;
     a.alpha = p.alpha;
     a.rho_min = p.rho_min;
@@ -435,7 +441,7 @@ void bodex_qp_default_params(bodex_qp_params* p) {
     p->iters_per_chunk = 20;
     p->flags = BODEX_F_POLISH | BODEX_F_ADAPTIVE_RHO;
     p->admm_waves = 0;
-    p->admm_tol = 1e-2f;
+    p->admm_tol = 0.0f;
 }
 
 int bodex_qp_create(const bodex_qp_params* p, int device, void* hip_stream, size_t hbm_budget_bytes,

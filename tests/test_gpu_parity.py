@@ -40,10 +40,11 @@ def test_ellipsoid_m5_s16_subsets(ng):
     check_state_kkt(b, gpu, 1e-5, range(0, b.n_qps, max(1, b.n_qps // 200)))
 
 
-@pytest.mark.parametrize("admm_tol", [0.0, 1e-3, 1e30])
+@pytest.mark.parametrize("admm_tol", [1e-5, 1e-3, 1e-2, 0.0, 1e30])
 def test_admm_tolerance_does_not_change_the_result(admm_tol):
-    # ADMM run to tol_rel (0), to 1e-3, or stopped at its first check (1e30):
-    # the polish reaches the same minimiser
+    # ADMM run to tol_rel (1e-5), to 1e-3 or 1e-2, to the pyramid's default
+    # (0: 1e-1), or stopped at its first check (1e30): the polish reaches the
+    # same minimiser
     b = wl.config(1, 96)
     gpu = run_gpu(b, admm_tol=admm_tol)
     ref = _ref(b)
