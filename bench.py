@@ -373,7 +373,34 @@ def descent_form(torch, api, wl, iters=20):
     e1.synchronize()
     g_us = e0.elapsed_time(e1) / n * 1e3
     sv.close()
+    # a small batch (64 hands): the step is launch-bound, so the descent
+    # captured once in a hipGraph and replayed against eager launches
+    # (a stream of its own: graphs are captured on a non-default stream)
+    small = {}
+    hs = wl.hand_batch(16498, 64, m=5, s=16)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for label, flags in (("eager", 0), ("graph", api.F_GRAPH)):
+        ss = api.Solver(api.default_params(m_max=5, s_max=16, flags_set=flags), stream=stream.cuda_stream)
+        dhs = api.DeviceHand(hs)
+        r0, t0_ = dhs.rot.clone(), dhs.trans.clone()
+        sts = api.new_state(dhs.n_grasps, dhs.n_qps, 5)
+        rss = api.new_result(dhs.n_grasps, dhs.n_qps, 5)
+        ts = []
+        for rep in range(4):
+            with torch.cuda.stream(stream):
+                dhs.rot.copy_(r0)
+                dhs.trans.copy_(t0_)
+            e0.record(stream)
+            ss.descend(dhs, d, state=sts, result=rss, trace=False)
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        small[label + "_ms_per_step"] = round(float(np.median(ts[1:])) / iters, 4)
+        small[label + "_launches"] = ss.stats()["launches"]
+        ss.close()
     return {"workload": "8192 floating hands x 5 fingertips on ellipsoids, 16 wrenches each (seed 16497)",
+            "small_batch_64_hands": small,
             "iters": iters, "ms": round(ms, 3), "ms_per_step": round(ms / iters, 4),
             "grasp_steps_per_s": round(dh.n_grasps * iters / (ms / 1e3), 1),
             "qp_solves_per_s": round(dh.n_qps * iters / (ms / 1e3), 1),

@@ -235,6 +235,44 @@ int ensure_device(bodex_qp* h, void** ptr, size_t* cap, size_t need) {
     return 0;
 }
 
+// The cached graph for `key`, or a new entry (descriptor buffer of n_ints
+// allocated, exec still null: the caller captures it).  At most 8 graphs are
+// kept; the least recently launched one makes room.
+int graph_entry(bodex_qp* h, uint64_t key, size_t n_ints, GraphEntry** out) {
+    for (auto& g : h->graphs)
+        if (g.key == key && g.exec) {
+            *out = &g;
+            return 0;
+        }
+    // a failed capture may have left an entry without a graph
+    for (size_t i = 0; i < h->graphs.size(); ++i)
+        if (!h->graphs[i].exec) {
+            if (h->graphs[i].d_desc) HIP_TRY(h, hipFree(h->graphs[i].d_desc));
+            h->owned_bytes -= h->graphs[i].desc_ints * sizeof(int);
+            h->graphs.erase(h->graphs.begin() + i);
+            break;
+        }
+    if (h->graphs.size() >= 8) {
+        auto oldest = std::min_element(h->graphs.begin(), h->graphs.end(),
+                                       [](const GraphEntry& x, const GraphEntry& y) { return x.stamp < y.stamp; });
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        if (oldest->exec) HIP_TRY(h, hipGraphExecDestroy(oldest->exec));
+        if (oldest->d_desc) HIP_TRY(h, hipFree(oldest->d_desc));
+        h->owned_bytes -= oldest->desc_ints * sizeof(int);
+        h->graphs.erase(oldest);
+    }
+    GraphEntry e;
+    e.key = key;
+    e.desc_ints = n_ints;
+    if (h->owned_bytes + n_ints * sizeof(int) > h->budget)
+        return fail(h, BODEX_EBUDGET, "graph descriptors exceed the budget");
+    HIP_TRY(h, hipMalloc(reinterpret_cast<void**>(&e.d_desc), n_ints * sizeof(int)));
+    h->owned_bytes += n_ints * sizeof(int);
+    h->graphs.push_back(e);
+    *out = &h->graphs.back();
+    return 0;
+}
+
 enum class Kind { Admm, Fin, Bwd };
 
 constexpr int kDefaultAdmmWaves = 2;
@@ -591,42 +629,21 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
     key = fnv1a(key, &a, sizeof(a));
     key = fnv1a(key, &h->prm, sizeof(h->prm));
     GraphEntry* hit = nullptr;
-    for (auto& g : h->graphs)
-        if (g.key == key) hit = &g;
-    if (!hit) {
-        if (h->graphs.size() >= 8) {
-            auto oldest = std::min_element(h->graphs.begin(), h->graphs.end(),
-                                           [](const GraphEntry& x, const GraphEntry& y) { return x.stamp < y.stamp; });
-            HIP_TRY(h, hipStreamSynchronize(h->stream));
-            if (oldest->exec) HIP_TRY(h, hipGraphExecDestroy(oldest->exec));
-            if (oldest->d_desc) HIP_TRY(h, hipFree(oldest->d_desc));
-            h->owned_bytes -= oldest->desc_ints * sizeof(int);
-            h->graphs.erase(oldest);
-        }
-        GraphEntry e;
-        e.key = key;
-        e.desc_ints = n_ints;
-        if (h->owned_bytes + n_ints * sizeof(int) > h->budget)
-            return fail(h, BODEX_EBUDGET, "graph descriptors exceed the budget");
-        HIP_TRY(h, hipMalloc(reinterpret_cast<void**>(&e.d_desc), n_ints * sizeof(int)));
-        h->owned_bytes += n_ints * sizeof(int);
+    rc = graph_entry(h, key, n_ints, &hit);
+    if (rc) return rc;
+    if (!hit->exec) {
         size_t up = 0;
-        rc = upload_desc(h, in, S, e.d_desc, &up);
-        if (rc) {
-            (void)hipFree(e.d_desc);
-            return rc;
-        }
+        rc = upload_desc(h, in, S, hit->d_desc, &up);
+        if (rc) return rc;
         hipGraph_t gr = nullptr;
         HIP_TRY(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-        rc = enqueue(e.d_desc, false);
+        rc = enqueue(hit->d_desc, false);
         hipError_t ce = hipStreamEndCapture(h->stream, &gr);
         if (rc) return rc;
         if (ce != hipSuccess) return hip_fail(h, ce, "hipStreamEndCapture");
-        ce = hipGraphInstantiate(&e.exec, gr, nullptr, nullptr, 0);
+        ce = hipGraphInstantiate(&hit->exec, gr, nullptr, nullptr, 0);
         (void)hipGraphDestroy(gr);
         if (ce != hipSuccess) return hip_fail(h, ce, "hipGraphInstantiate");
-        h->graphs.push_back(e);
-        hit = &h->graphs.back();
     } else {
         h->last_replays = 1;
     }
@@ -860,58 +877,107 @@ int bodex_qp_descend(bodex_qp_t* h, const bodex_hand* hand, const bodex_batch* q
     a.status = out->status;
     a.pflops = out->polish_flops;
     const size_t n_ints = size_t(G) * 3 + 1 + S.n_tiles + 1 + 4;
-    rc = ensure_device(h, reinterpret_cast<void**>(&h->d_desc), &h->d_desc_cap, n_ints * sizeof(int));
-    if (rc) return rc;
-    size_t up = 0;
-    rc = upload_desc(h, &qb, S, h->d_desc, &up);
-    if (rc) return rc;
-    bind_desc(a, h->d_desc, G, S);
-    int* d_queue = h->d_desc + (n_ints - 4);
     const size_t lds_a = admm_lds(mm, S.slots);
     const size_t lds_f = cone ? bodex::cone_fin_lds(mm, S.slots, h->prm.gamma > 0.f) : fin_lds(mm, S.slots, false);
     const size_t lds_b = fin_lds(mm, S.slots, true);
     const int per_cu = std::max(1, std::min(16, int((160 * 1024) / std::max<size_t>(lds_a, 1))));
     const int grid_a = batched ? occupancy_grid(h, per_cu, S.n_tiles) : S.n_tiles;
 
-    bodex::HandArgs ha = hand_args(hand);
-    ha.counts = a.counts;  // the uploaded copy of qp->contact_count
-    ha.points = P;
-    ha.normals = N;
-    ha.dist = D;
-    HIP_TRY(h, bodex::launch_fill(wq, G, d->w_qp, h->stream));
-    HIP_TRY(h, bodex::launch_hand_query(ha, h->stream));
-    for (int k = 0; k < d->iters; ++k) {
-        KArgs ak = a;
-        if (k > 0) ak.warm = 1;
-        HIP_TRY(h, bodex::launch_reset(d_queue, 4, h->stream));
-        ak.queue = batched ? d_queue : nullptr;
-        HIP_TRY(h, launch(Kind::Admm, mm, ak, grid_a, lds_a, h->stream, h->prm.admm_waves));
-        ak.queue = nullptr;
-        HIP_TRY(h, launch(Kind::Fin, mm, ak, S.n_tiles, lds_f, h->stream));
-        KArgs ab = a;
-        ab.queue = nullptr;
-        ab.dLdE = wq;
-        ab.dLdQ = nullptr;
-        ab.dP = dP;
-        ab.dN = dN;
-        ab.accumulate = 0;
-        HIP_TRY(h, launch(Kind::Bwd, mm, ab, S.n_tiles, lds_b, h->stream));
-        bodex::HandArgs hs = ha;
-        hs.dLdp = dP;
-        hs.dLdn = dN;
-        hs.e_qp = out->energy;
-        hs.w_qp = d->w_qp;
-        hs.w_dist = d->w_dist;
-        hs.radius = d->radius;
-        hs.offset = d->offset;
-        hs.trace = loss_trace ? loss_trace + size_t(k) * G : nullptr;
-        hs.step = 1;
-        hs.step_rot = d->step_rot;
-        hs.step_trans = d->step_trans;
-        hs.requery = 1;
-        HIP_TRY(h, bodex::launch_hand_step(hs, h->stream));
+    // The whole descent for the descriptors at `desc`: loss weights, the
+    // first contacts, then per step reset, ADMM, finalize, backward and the
+    // pose step (which re-queries the contacts of the new pose).
+    auto enqueue = [&](int* desc) -> int {
+        KArgs ad = a;
+        bind_desc(ad, desc, G, S);
+        int* d_queue = desc + (n_ints - 4);
+        bodex::HandArgs ha = hand_args(hand);
+        ha.counts = ad.counts;  // the uploaded copy of qp->contact_count
+        ha.points = P;
+        ha.normals = N;
+        ha.dist = D;
+        HIP_TRY(h, bodex::launch_fill(wq, G, d->w_qp, h->stream));
+        HIP_TRY(h, bodex::launch_hand_query(ha, h->stream));
+        for (int k = 0; k < d->iters; ++k) {
+            KArgs ak = ad;
+            if (k > 0) ak.warm = 1;
+            HIP_TRY(h, bodex::launch_reset(d_queue, 4, h->stream));
+            ak.queue = batched ? d_queue : nullptr;
+            HIP_TRY(h, launch(Kind::Admm, mm, ak, grid_a, lds_a, h->stream, h->prm.admm_waves));
+            ak.queue = nullptr;
+            HIP_TRY(h, launch(Kind::Fin, mm, ak, S.n_tiles, lds_f, h->stream));
+            KArgs ab = ad;
+            ab.queue = nullptr;
+            ab.dLdE = wq;
+            ab.dLdQ = nullptr;
+            ab.dP = dP;
+            ab.dN = dN;
+            ab.accumulate = 0;
+            HIP_TRY(h, launch(Kind::Bwd, mm, ab, S.n_tiles, lds_b, h->stream));
+            bodex::HandArgs hs = ha;
+            hs.dLdp = dP;
+            hs.dLdn = dN;
+            hs.e_qp = out->energy;
+            hs.w_qp = d->w_qp;
+            hs.w_dist = d->w_dist;
+            hs.radius = d->radius;
+            hs.offset = d->offset;
+            hs.trace = loss_trace ? loss_trace + size_t(k) * G : nullptr;
+            hs.step = 1;
+            hs.step_rot = d->step_rot;
+            hs.step_trans = d->step_trans;
+            hs.requery = 1;
+            HIP_TRY(h, bodex::launch_hand_step(hs, h->stream));
+        }
+        return 0;
+    };
+
+    const bool graph = (h->prm.flags & BODEX_F_GRAPH) != 0 && h->stream != nullptr;
+    h->last_replays = 0;
+    if (!graph) {
+        rc = ensure_device(h, reinterpret_cast<void**>(&h->d_desc), &h->d_desc_cap, n_ints * sizeof(int));
+        if (rc) return rc;
+        size_t up = 0;
+        rc = upload_desc(h, &qb, S, h->d_desc, &up);
+        if (rc) return rc;
+        rc = enqueue(h->d_desc);
+        if (rc) return rc;
+        h->last_launches = 2 + 5 * d->iters;
+        return 0;
     }
-    h->last_launches = 2 + 5 * d->iters;
+    // Graph path: the descent's launches captured once per shape, pointers
+    // and parameters, then replayed as one launch.
+    uint64_t key = 0x9e3779b97f4a7c15ull;
+    key = fnv1a(key, &G, sizeof(G));
+    key = fnv1a(key, qb.contact_count, sizeof(int) * G);
+    key = fnv1a(key, qb.wrench_offset, sizeof(int) * (G + 1));
+    key = fnv1a(key, &a, sizeof(a));
+    key = fnv1a(key, hand, sizeof(*hand));
+    key = fnv1a(key, d, sizeof(*d));
+    key = fnv1a(key, &loss_trace, sizeof(loss_trace));
+    key = fnv1a(key, &h->d_hand, sizeof(h->d_hand));
+    key = fnv1a(key, &h->prm, sizeof(h->prm));
+    GraphEntry* hit = nullptr;
+    rc = graph_entry(h, key, n_ints, &hit);
+    if (rc) return rc;
+    if (!hit->exec) {
+        size_t up = 0;
+        rc = upload_desc(h, &qb, S, hit->d_desc, &up);
+        if (rc) return rc;
+        hipGraph_t gr = nullptr;
+        HIP_TRY(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        rc = enqueue(hit->d_desc);
+        hipError_t ce = hipStreamEndCapture(h->stream, &gr);
+        if (rc) return rc;
+        if (ce != hipSuccess) return hip_fail(h, ce, "hipStreamEndCapture");
+        ce = hipGraphInstantiate(&hit->exec, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (ce != hipSuccess) return hip_fail(h, ce, "hipGraphInstantiate");
+    } else {
+        h->last_replays = 1;
+    }
+    hit->stamp = ++h->graph_clock;
+    HIP_TRY(h, hipGraphLaunch(hit->exec, h->stream));
+    h->last_launches = 1;
     return 0;
 }
 

@@ -251,3 +251,42 @@ def test_descend_argument_errors(solver):
     assert L.bodex_qp_contact_query(solver.h, ctypes.byref(c), None, None, None) == api.EINVAL
     assert L.bodex_qp_pose_gradient(solver.h, ctypes.byref(dh.c_struct()), None, None, float("nan"), 0.0, 0.0,
                                     None, None, None) == api.EINVAL
+
+
+def test_descend_graph_replays_match_eager():
+    # the descent captured in a hipGraph and replayed: every replay, with
+    # eager work (pose reset) and synchronisations between them, gives the
+    # eager run's poses, trace and QP results exactly
+    import torch
+    hb = wl.hand_batch(35, 64, m=5, s=16)
+    d = api.descent(iters=4, **DESC)
+    p_e = api.default_params(m_max=5, s_max=16)
+    se = api.Solver(p_e)
+    dh_e = api.DeviceHand(hb)
+    st_e = api.new_state(dh_e.n_grasps, dh_e.n_qps, 5)
+    res_e, tr_e = se.descend(dh_e, d, state=st_e)
+    torch.cuda.synchronize()
+    ref = (dh_e.rot.clone(), dh_e.trans.clone(), tr_e.clone(), res_e["qp_obj"].clone(), res_e["forces"].clone())
+    se.close()
+    p_g = api.default_params(m_max=5, s_max=16, flags_set=api.F_GRAPH)
+    import torch.cuda as tc
+    stream = tc.Stream()
+    with tc.stream(stream):
+        sg = api.Solver(p_g, stream=stream.cuda_stream)
+        dh = api.DeviceHand(hb)
+        rot0, trans0 = dh.rot.clone(), dh.trans.clone()
+        st = api.new_state(dh.n_grasps, dh.n_qps, 5)
+        res = api.new_result(dh.n_grasps, dh.n_qps, 5)
+        tr = torch.empty((4, dh.n_grasps), device="cuda")
+        for rep in range(3):
+            dh.rot.copy_(rot0)
+            dh.trans.copy_(trans0)
+            st["x"].zero_()
+            api.bodex_qp_descend(sg.h, dh, d, res, st, tr)
+            stats = sg.stats()
+            stream.synchronize()
+            assert stats["launches"] == 1 and stats["graph_replays"] == (1 if rep else 0)
+            got = (dh.rot, dh.trans, tr, res["qp_obj"], res["forces"])
+            for g_, r_ in zip(got, ref):
+                assert torch.equal(g_, r_), "replay %d differs from the eager run" % rep
+        sg.close()
