@@ -290,3 +290,55 @@ def test_descend_graph_replays_match_eager():
             for g_, r_ in zip(got, ref):
                 assert torch.equal(g_, r_), "replay %d differs from the eager run" % rep
         sg.close()
+
+
+def test_descend_continues_from_the_callers_state():
+    # 3 steps, then 2 more warm-started from the caller's state, equal 5
+    # steps in one call (steps after the first warm-start in both)
+    import torch
+    hb = wl.hand_batch(36, 40, m_choices=(4, 5), s=12)
+    d5 = api.descent(iters=5, **DESC)
+    s = api.Solver(api.default_params(m_max=5, s_max=16))
+    dh1 = api.DeviceHand(hb)
+    st1 = api.new_state(dh1.n_grasps, dh1.n_qps, 5)
+    r1, tr1 = s.descend(dh1, d5, state=st1)
+    torch.cuda.synchronize()
+    dh2 = api.DeviceHand(hb)
+    st2 = api.new_state(dh2.n_grasps, dh2.n_qps, 5)
+    r2, tr2a = s.descend(dh2, api.descent(iters=3, **DESC), state=st2)
+    s.close()
+    sw = api.Solver(api.default_params(m_max=5, s_max=16, flags_set=api.F_WARM_START))
+    r2, tr2b = sw.descend(dh2, api.descent(iters=2, **DESC), state=st2, result=r2)
+    torch.cuda.synchronize()
+    sw.close()
+    assert torch.equal(dh1.rot, dh2.rot) and torch.equal(dh1.trans, dh2.trans)
+    assert torch.equal(tr1, torch.cat([tr2a, tr2b]))
+    assert torch.equal(r1["forces"], r2["forces"])
+
+
+def test_descend_batched_schedule_matches_plain():
+    # the persistent cost-sorted schedule (uneven fingertip and wrench
+    # counts) gives the plain schedule's descent
+    import torch
+    hb = wl.hand_batch(37, 96, m_choices=(4, 5), s=8, shape="mixed")
+    rng = np.random.default_rng(1)
+    s_g = rng.integers(4, 17, hb.n_grasps)
+    woff = np.zeros(hb.n_grasps + 1, np.int32)
+    woff[1:] = np.cumsum(s_g)
+    hb = wl.HandBatch(hb.tip_local, hb.semi_axes, hb.rot, hb.trans, hb.counts, woff, hb.mu,
+                      wl.wrench_dirs(rng, int(woff[-1])), "uneven")
+    d = api.descent(iters=3, **DESC)
+    out = []
+    for flags in (0, api.F_BATCHED):
+        s = api.Solver(api.default_params(m_max=5, s_max=16, flags_set=flags))
+        dh = api.DeviceHand(hb)
+        st = api.new_state(dh.n_grasps, dh.n_qps, 5)
+        res, tr = s.descend(dh, d, state=st)
+        torch.cuda.synchronize()
+        out.append((_np(dh.rot), _np(dh.trans), _np(tr), res["status"].cpu().numpy()))
+        s.close()
+    (R0, T0, L0, s0), (R1, T1, L1, s1) = out
+    assert np.all(s0 & api.ST_CONVERGED) and np.all(s1 & api.ST_CONVERGED)
+    np.testing.assert_allclose(L1, L0, rtol=1e-5, atol=1e-7)
+    np.testing.assert_allclose(T1, T0, rtol=0, atol=1e-7)
+    np.testing.assert_allclose(R1, R0, rtol=0, atol=1e-6)
