@@ -506,8 +506,8 @@ class Solver:
         d = d if d is not None else descent()
         if result is None:
             result = new_result(hand.n_grasps, hand.n_qps, self.params.m_max)
-        tr = torch.empty((max(d.iters, 1), hand.n_grasps), dtype=torch.float32, device=hand.tip.device) \
-            if trace else None
+        tr = torch.empty((d.iters, hand.n_grasps), dtype=torch.float32, device=hand.tip.device) \
+            if trace and d.iters > 0 else None
         bodex_qp_descend(self.h, hand, d, result, state, tr)
         return result, tr
 
