@@ -95,8 +95,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (got --gpus %d, WORLD_SIZE %d); "
-              "the path shards by grasps with no exchange, see DESIGN.md" % (args.gpus, world),
+        print("bench.py: measures one GPU only (got --gpus %d, WORLD_SIZE %d); the path shards by "
+              "contiguous grasp ranges with no exchange between GPUs" % (args.gpus, world),
               file=sys.stderr)
         sys.exit(2)
 

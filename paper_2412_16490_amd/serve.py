@@ -186,7 +186,7 @@ class Server:
                                            "forces": a.forces.cpu().numpy(),
                                            "grad_points": a.grad_p.cpu().numpy()}
 
-    # -- driver --------------------------------------------------------------
+    # -- main loop -----------------------------------------------------------
     def run(self, requests, realtime=True):
         """Serve an iterable of requests sorted by arrival.  With realtime the
         arrivals follow the wall clock from the start of the run."""
