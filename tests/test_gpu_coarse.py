@@ -342,3 +342,31 @@ def test_descend_batched_schedule_matches_plain():
     np.testing.assert_allclose(L1, L0, rtol=1e-5, atol=1e-7)
     np.testing.assert_allclose(T1, T0, rtol=0, atol=1e-7)
     np.testing.assert_allclose(R1, R0, rtol=0, atol=1e-6)
+
+
+@pytest.mark.parametrize("m,mc,G", [(1, None, 257), (8, None, 333), (None, (1, 8), 401)])
+def test_query_and_gradient_extreme_layouts(solver, m, mc, G):
+    # one fingertip, the maximum of eight, and a ragged mix of both; odd
+    # batch sizes leave a partial last block
+    import torch
+    hb = wl.hand_batch(200 + G, G, m=m or 5, m_choices=mc, shape="mixed")
+    dh = api.DeviceHand(hb)
+    out = solver.contact_query(dh)
+    rng = np.random.default_rng(G)
+    dLdp = rng.standard_normal((G, hb.m_max, 3)).astype(np.float32)
+    dLdn = rng.standard_normal((G, hb.m_max, 3)).astype(np.float32)
+    w_dist, radius, offset = _f32(50.0), _f32(0.01), _f32(0.0)
+    g = solver.pose_gradient(dh, torch.as_tensor(dLdp, device="cuda"), torch.as_tensor(dLdn, device="cuda"),
+                             w_dist, radius, offset)
+    torch.cuda.synchronize()
+    R, T, cl, ax = _f64(hb)
+    P, N, D = oc.contact_query(R, T, cl, ax, hb.counts)
+    assert np.all(np.abs(_np(out["points"]) - P) <= 2 * U * np.abs(P) + 1e-12)
+    assert np.all(np.abs(_np(out["normals"]) - N) <= 4 * U)
+    assert np.all(np.abs(_np(out["dist"]) - D) <= 2 * U * np.abs(D) + 1e-12)
+    E, dw, dT = oc.pose_gradient(R, T, cl, ax, dLdp.astype(np.float64), dLdn.astype(np.float64), w_dist, radius,
+                                 offset, hb.counts)
+    sT, sw = _tip_scales(hb, dLdp.astype(np.float64), dLdn.astype(np.float64), w_dist, radius, offset)
+    assert np.all(np.abs(_np(g["e_dist"]) - E) <= 4 * U * E + 1e-15)
+    assert np.all(np.abs(_np(g["dL_dtrans"]) - dT).max(axis=1) <= 4 * U * sT + 1e-12)
+    assert np.all(np.abs(_np(g["dL_drot"]) - dw).max(axis=1) <= 4 * U * sw + 1e-12)
