@@ -370,3 +370,26 @@ def test_query_and_gradient_extreme_layouts(solver, m, mc, G):
     assert np.all(np.abs(_np(g["e_dist"]) - E) <= 4 * U * E + 1e-15)
     assert np.all(np.abs(_np(g["dL_dtrans"]) - dT).max(axis=1) <= 4 * U * sT + 1e-12)
     assert np.all(np.abs(_np(g["dL_drot"]) - dw).max(axis=1) <= 4 * U * sw + 1e-12)
+
+
+def test_descend_force_axis_wrenches_with_gamma():
+    # the paper's energy: six force-axis wrenches and a minimum normal-force
+    # sum (Eq. 9), descended on the GPU and by the oracle
+    import torch
+    hb = wl.hand_batch(38, 40, m=5, force_axis=True)
+    gamma = _f32(0.5)
+    p = api.default_params(m_max=5, s_max=16)
+    p.gamma = gamma
+    s = api.Solver(p)
+    dh = api.DeviceHand(hb)
+    st = api.new_state(dh.n_grasps, dh.n_qps, 5)
+    res, tr = s.descend(dh, api.descent(iters=4, **DESC), state=st)
+    torch.cuda.synchronize()
+    s.close()
+    R, T, cl, ax = _f64(hb)
+    R1, T1, trace = oc.descend(R, T, cl, ax, hb.counts, hb.woff, hb.mu, hb.wrench, 4,
+                               prm=oracle.params(gamma=gamma), **DESC)
+    trn = _np(tr)
+    assert np.all(np.asarray(res["status"].cpu().numpy()) & api.ST_CONVERGED)
+    assert np.all(np.abs(trn - trace) <= 1e-3 * np.maximum(trace, 1e-2))
+    assert np.mean(trn[-1] < trn[0]) >= 0.9
