@@ -92,7 +92,8 @@ extern "C" {
 #define BODEX_CONE_CIRCULAR 1
 
 typedef struct {
-    int m_max;            /* contacts per grasp, 1..5 (array padding)        */
+    int m_max;            /* contacts per grasp, 1..8 (array padding); 1..5  */
+                          /* with BODEX_CONE_CIRCULAR                        */
     int s_max;            /* wrenches per grasp, 1..64                        */
     float force_max;      /* fmax, upper bound of f_i1 (Eq. 1: 1.0)           */
     float gamma;          /* lower bound of sum_i f_i1 (Eq. 9); 0 = unused    */
@@ -172,8 +173,10 @@ void bodex_qp_default_params(bodex_qp_params *p);
 
 /* Create a handle on `device` that enqueues on `hip_stream` (a hipStream_t;
  * NULL = the default stream).  hbm_budget_bytes caps the library-owned
- * workspace (0 = 4 GiB).  Errors: EINVAL (bad params), EUNSUP (m_max above
- * the contact counts the kernels are compiled for: 4 and 5), ENODEV, EHIP. */
+ * workspace (0 = 4 GiB).  The kernels are compiled for 4, 5, 6, 7 and 8
+ * contacts (a batch runs on the smallest size >= m_max; the circular cone's
+ * for 4 and 5).  Errors: EINVAL (bad params), EUNSUP (m_max above 5 with
+ * BODEX_CONE_CIRCULAR), ENODEV, EHIP. */
 int bodex_qp_create(const bodex_qp_params *p, int device, void *hip_stream,
                     size_t hbm_budget_bytes, bodex_qp_t **out);
 

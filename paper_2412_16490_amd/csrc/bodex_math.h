@@ -22,6 +22,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #if defined(__HIPCC__)
 #define BODEX_HD __host__ __device__
 #else
@@ -639,15 +641,21 @@ struct PolishWork {
 // Active set: bit 9i+kk of mask is row kk of contact i; gam: the normal-sum
 // row; L: the factor of eps I6 + G Pi G^T; the contacts' projectors, kept
 // from the last factorisation.
+// Bits of the contact rows' active set: 9 per contact (64 bits up to 7
+// contacts, 128 for 8).
+template <int MM>
+using RowMask = typename std::conditional<(9 * MM <= 64), uint64_t, unsigned __int128>::type;
+
 template <int MM>
 struct ActiveSet {
-    uint64_t mask;
+    RowMask<MM> mask;
     bool gam;
     Sym6 L;
     LaneVec pc;  // per contact: the unit e of its projector (a, k follow from the mask)
 };
 
-BODEX_FI unsigned contact_mask(uint64_t mask, int i) { return unsigned(mask >> (9 * i)) & 0x1FFu; }
+template <class Mask>
+BODEX_FI unsigned contact_mask(Mask mask, int i) { return unsigned(mask >> (9 * i)) & 0x1FFu; }
 
 template <typename D, int MM>
 BODEX_FI void contact_geom(const D& Dt, const ActiveSet<MM>& S, int i, ContactRows& R, ContactProj& P) {
@@ -1086,7 +1094,7 @@ BODEX_FI void polish_begin(const D& Dt, YP y0, PolishState<MM>& PS) {
             used |= 1u << best;
             mk |= 1u << best;
         }
-        S.mask |= uint64_t(mk) << (9 * i);
+        S.mask |= RowMask<MM>(mk) << (9 * i);
     }
     S.gam = false;
     if (use_gam && double(y0[9 * MM]) < 0.0) S.gam = sum_row_norm2(Dt, S) > 1e-12 * m;
@@ -1235,7 +1243,7 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
                 if (D::kGam && wbit == 9 * MM)
                     S.gam = false;
                 else
-                    S.mask &= ~(uint64_t(1) << wbit);
+                    S.mask &= ~(RowMask<MM>(1) << wbit);
                 refactor = true;
                 mode = kEqp0;
                 return false;
@@ -1409,7 +1417,7 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
         if (p.pk == 9)
             S.gam = true;
         else
-            S.mask |= uint64_t(1) << (9 * p.pi + p.pk);
+            S.mask |= RowMask<MM>(1) << (9 * p.pi + p.pk);
         phase = kFinal;
         mp = none;
         mup = 0.0;
@@ -1419,7 +1427,7 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
         if (D::kGam && lbit == 9 * MM)
             S.gam = false;
         else
-            S.mask &= ~(uint64_t(1) << lbit);
+            S.mask &= ~(RowMask<MM>(1) << lbit);
         mp = p;
         mup = up;
         mode = kStep;

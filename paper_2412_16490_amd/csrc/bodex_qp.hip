@@ -104,8 +104,10 @@ bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0
 
 // Contact counts the kernels are compiled for.  A batch with m_max contacts
 // per grasp runs on the smallest compiled size >= m_max (array strides stay
-// m_max; the extra contacts are inert padding).
-constexpr int kCompiledMM[] = {4, 5};
+// m_max; the extra contacts are inert padding).  The circular cone's polish
+// factors a dense 3 m x 3 m matrix per lane and is compiled up to 5.
+constexpr int kCompiledMM[] = {4, 5, 6, 7, 8};
+constexpr int kConeMaxMM = 5;
 
 int kernel_mm(int m_max) {
     for (int mm : kCompiledMM)
@@ -117,6 +119,9 @@ size_t admm_lds(int mm, int slots) {
     switch (mm) {
         case 4: return bodex::AdmmLds<4>::bytes(slots);
         case 5: return bodex::AdmmLds<5>::bytes(slots);
+        case 6: return bodex::AdmmLds<6>::bytes(slots);
+        case 7: return bodex::AdmmLds<7>::bytes(slots);
+        case 8: return bodex::AdmmLds<8>::bytes(slots);
     }
     return 0;
 }
@@ -125,6 +130,9 @@ size_t fin_lds(int mm, int slots, bool bwd) {
     switch (mm) {
         case 4: return bodex::FinLds<4>::bytes(slots, bwd);
         case 5: return bodex::FinLds<5>::bytes(slots, bwd);
+        case 6: return bodex::FinLds<6>::bytes(slots, bwd);
+        case 7: return bodex::FinLds<7>::bytes(slots, bwd);
+        case 8: return bodex::FinLds<8>::bytes(slots, bwd);
     }
     return 0;
 }
@@ -490,6 +498,9 @@ int bodex_qp_create(const bodex_qp_params* p, int device, void* hip_stream, size
     if (rc) return rc;
     if (kernel_mm(p->m_max) == 0)
         return fail(nullptr, BODEX_EUNSUP, "m_max=%d exceeds the contact counts this library was built for",
+                    p->m_max);
+    if (p->friction_cone == BODEX_CONE_CIRCULAR && p->m_max > kConeMaxMM)
+        return fail(nullptr, BODEX_EUNSUP, "the circular cone is built for m_max <= %d (got %d)", kConeMaxMM,
                     p->m_max);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)

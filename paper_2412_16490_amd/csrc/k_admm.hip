@@ -27,6 +27,9 @@ hipError_t launch_admm(int mm, int occ, const KArgs& a, int grid, size_t lds, hi
     switch (mm) {
         case 4: return launch_admm_mm<4>(occ, a, grid, lds, st);
         case 5: return launch_admm_mm<5>(occ, a, grid, lds, st);
+        case 6: return launch_admm_mm<6>(occ, a, grid, lds, st);
+        case 7: return launch_admm_mm<7>(occ, a, grid, lds, st);
+        case 8: return launch_admm_mm<8>(occ, a, grid, lds, st);
         default: return hipErrorInvalidValue;
     }
 }

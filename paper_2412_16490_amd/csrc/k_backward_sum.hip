@@ -8,6 +8,9 @@ hipError_t launch_backward_sum(int mm, const KArgs& a, int grid, size_t lds, hip
     switch (mm) {
         case 4: hipLaunchKernelGGL((backward_kernel<4, true, false>), dim3(grid), dim3(64), lds, st, a); break;
         case 5: hipLaunchKernelGGL((backward_kernel<5, true, false>), dim3(grid), dim3(64), lds, st, a); break;
+        case 6: hipLaunchKernelGGL((backward_kernel<6, true, false>), dim3(grid), dim3(64), lds, st, a); break;
+        case 7: hipLaunchKernelGGL((backward_kernel<7, true, false>), dim3(grid), dim3(64), lds, st, a); break;
+        case 8: hipLaunchKernelGGL((backward_kernel<8, true, false>), dim3(grid), dim3(64), lds, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

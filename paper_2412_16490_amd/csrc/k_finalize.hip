@@ -11,6 +11,9 @@ hipError_t launch_finalize(int mm, const KArgs& a, int grid, size_t lds, hipStre
     switch (mm) {
         case 4: hipLaunchKernelGGL((finalize_kernel<4, false>), dim3(grid), dim3(64), lds, st, a); break;
         case 5: hipLaunchKernelGGL((finalize_kernel<5, false>), dim3(grid), dim3(64), lds, st, a); break;
+        case 6: hipLaunchKernelGGL((finalize_kernel<6, false>), dim3(grid), dim3(64), lds, st, a); break;
+        case 7: hipLaunchKernelGGL((finalize_kernel<7, false>), dim3(grid), dim3(64), lds, st, a); break;
+        case 8: hipLaunchKernelGGL((finalize_kernel<8, false>), dim3(grid), dim3(64), lds, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
