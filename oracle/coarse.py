@@ -221,25 +221,39 @@ def descent_step(R, T, dw, dT, step_rot, step_trans):
     return Rn, np.asarray(T, np.float64) - step_trans * np.asarray(dT, np.float64)
 
 
-def loss(R, T, cl, axes, counts, woff, mu, wrench, w_qp=1.0, w_dist=0.0, radius=0.0, offset=0.0, prm=None):
-    """L per grasp at the pose (R, T), with the pyramid QP oracle; also the
-    contacts and the QP solution."""
+def _solve_qps(counts, woff, P, N, mu, wrench, prm, cone):
+    """The QPs at the contacts: the pyramid oracle, or with cone=True the
+    circular-cone oracle (the same kappa, beta, eps, fmax and gamma)."""
+    if not cone:
+        return _qp.solve_batch(counts, woff, P, N, mu, wrench, prm)
+    from oracle import cone as _cone
+    prm = prm or _qp.params()
+    return _cone.solve_batch(counts, woff, P, N, mu, wrench, kappa=prm.kappa, beta=prm.beta, eps=prm.eps,
+                             fmax=prm.fmax, gamma=prm.gamma)
+
+
+def loss(R, T, cl, axes, counts, woff, mu, wrench, w_qp=1.0, w_dist=0.0, radius=0.0, offset=0.0, prm=None,
+         cone=False):
+    """L per grasp at the pose (R, T), with the pyramid QP oracle (or the
+    circular-cone one); also the contacts and the QP solution."""
     P, N, D = contact_query(R, T, cl, axes, counts)
-    res = _qp.solve_batch(counts, woff, P, N, mu, wrench, prm)
+    res = _solve_qps(counts, woff, P, N, mu, wrench, prm, cone)
     live = np.arange(P.shape[1])[None, :] < np.asarray(counts)[:, None]
     Ec = np.sum(np.where(live, (D - radius - offset) ** 2, 0.0), axis=1)
     return w_qp * res["energy"] + w_dist * Ec, P, N, res
 
 
 def descend(R, T, cl, axes, counts, woff, mu, wrench, iters, w_qp=1.0, w_dist=0.0, radius=0.0, offset=0.0,
-            step_rot=0.0, step_trans=0.0, prm=None):
+            step_rot=0.0, step_trans=0.0, prm=None, cone=False):
     """`iters` upper-level gradient steps; returns the final (R, T) and the
-    loss [iters, G] at each pose before its step."""
+    loss [iters, G] at each pose before its step.  The QP gradient is
+    Danskin's (a function of the optimal forces only), so the same chain rule
+    serves the pyramid and the circular cone."""
     R = np.asarray(R, np.float64).copy()
     T = np.asarray(T, np.float64).copy()
     trace = []
     for _ in range(iters):
-        L, P, N, res = loss(R, T, cl, axes, counts, woff, mu, wrench, w_qp, w_dist, radius, offset, prm)
+        L, P, N, res = loss(R, T, cl, axes, counts, woff, mu, wrench, w_qp, w_dist, radius, offset, prm, cone)
         trace.append(L)
         G = P.shape[0]
         dP, dN = _qp.grad_batch(counts, woff, P, N, wrench, res["forces"], we=np.full(G, float(w_qp)), prm=prm)

@@ -138,22 +138,22 @@ def test_rodrigues_matches_scipy():
         np.testing.assert_allclose(oc.rodrigues(w), Rot.from_rotvec(w).as_matrix(), atol=1e-15)
 
 
-def _loss(hb, R, T, w_dist=200.0, radius=0.01, offset=0.005):
+def _loss(hb, R, T, w_dist=200.0, radius=0.01, offset=0.005, cone=False):
     L, _, _, _ = oc.loss(R, T, hb.tip_local, hb.semi_axes, hb.counts, hb.woff, hb.mu, hb.wrench,
-                         w_qp=1.0, w_dist=w_dist, radius=radius, offset=offset)
+                         w_qp=1.0, w_dist=w_dist, radius=radius, offset=offset, cone=cone)
     return L
 
 
-def _grad(hb, R, T, w_dist=200.0, radius=0.01, offset=0.005, drop_normals=False):
+def _grad(hb, R, T, w_dist=200.0, radius=0.01, offset=0.005, drop_normals=False, cone=False):
     L, P, N, res = oc.loss(R, T, hb.tip_local, hb.semi_axes, hb.counts, hb.woff, hb.mu, hb.wrench,
-                           w_qp=1.0, w_dist=w_dist, radius=radius, offset=offset)
+                           w_qp=1.0, w_dist=w_dist, radius=radius, offset=offset, cone=cone)
     dP, dN = oracle.grad_batch(hb.counts, hb.woff, P, N, hb.wrench, res["forces"], we=np.ones(hb.n_grasps))
     _, dw, dT = oc.pose_gradient(R, T, hb.tip_local, hb.semi_axes, dP, None if drop_normals else dN,
                                  w_dist, radius, offset, hb.counts)
     return dw, dT
 
 
-def _fd_pose(hb, R, T, h=1e-6):
+def _fd_pose(hb, R, T, h=1e-6, cone=False):
     G = hb.n_grasps
     dw = np.zeros((G, 3))
     dT = np.zeros((G, 3))
@@ -161,10 +161,10 @@ def _fd_pose(hb, R, T, h=1e-6):
         e = np.zeros(3)
         e[k] = h
         Tp, Tm = T + e, T - e
-        dT[:, k] = (_loss(hb, R, Tp) - _loss(hb, R, Tm)) / (2 * h)
+        dT[:, k] = (_loss(hb, R, Tp, cone=cone) - _loss(hb, R, Tm, cone=cone)) / (2 * h)
         Rp = np.stack([oc.rodrigues(e) @ R[g] for g in range(G)])
         Rm = np.stack([oc.rodrigues(-e) @ R[g] for g in range(G)])
-        dw[:, k] = (_loss(hb, Rp, T) - _loss(hb, Rm, T)) / (2 * h)
+        dw[:, k] = (_loss(hb, Rp, T, cone=cone) - _loss(hb, Rm, T, cone=cone)) / (2 * h)
     return dw, dT
 
 
@@ -174,6 +174,18 @@ def test_pose_gradient_matches_central_differences_through_the_qp(shape, mc):
     R, T = hb.rot.astype(np.float64), hb.trans.astype(np.float64)
     dw, dT = _grad(hb, R, T)
     fw, fT = _fd_pose(hb, R, T)
+    for g in range(hb.n_grasps):
+        assert np.linalg.norm(dT[g] - fT[g]) <= 1e-5 * max(np.linalg.norm(fT[g]), 1.0)
+        assert np.linalg.norm(dw[g] - fw[g]) <= 1e-5 * max(np.linalg.norm(fw[g]), 1.0)
+
+
+def test_pose_gradient_through_the_circular_cone_matches_central_differences():
+    # the same chain rule with the cone oracle's forces (Danskin's gradient
+    # depends on the QP only through f*)
+    hb = wl.hand_batch(14, 3, s=4)
+    R, T = hb.rot.astype(np.float64), hb.trans.astype(np.float64)
+    dw, dT = _grad(hb, R, T, cone=True)
+    fw, fT = _fd_pose(hb, R, T, cone=True)
     for g in range(hb.n_grasps):
         assert np.linalg.norm(dT[g] - fT[g]) <= 1e-5 * max(np.linalg.norm(fT[g]), 1.0)
         assert np.linalg.norm(dw[g] - fw[g]) <= 1e-5 * max(np.linalg.norm(fw[g]), 1.0)
