@@ -393,3 +393,43 @@ def test_descend_force_axis_wrenches_with_gamma():
     assert np.all(np.asarray(res["status"].cpu().numpy()) & api.ST_CONVERGED)
     assert np.all(np.abs(trn - trace) <= 1e-3 * np.maximum(trace, 1e-2))
     assert np.mean(trn[-1] < trn[0]) >= 0.9
+
+
+def test_descend_circular_cone_matches_the_cone_oracle():
+    import torch
+    hb = wl.hand_batch(40, 16, m=5, s=8)
+    p = api.default_params(m_max=5, s_max=16)
+    p.friction_cone = api.CONE_CIRCULAR
+    s = api.Solver(p)
+    dh = api.DeviceHand(hb)
+    st = api.new_state(dh.n_grasps, dh.n_qps, 5, cone=True)
+    res, tr = s.descend(dh, api.descent(iters=3, **DESC), state=st)
+    torch.cuda.synchronize()
+    s.close()
+    R, T, cl, ax = _f64(hb)
+    R1, T1, trace = oc.descend(R, T, cl, ax, hb.counts, hb.woff, hb.mu, hb.wrench, 3, cone=True, **DESC)
+    trn = _np(tr)
+    assert np.all(np.asarray(res["status"].cpu().numpy()) & api.ST_POLISHED)
+    assert np.all(np.abs(trn - trace) <= 1e-3 * np.maximum(trace, 1e-2))
+
+
+@pytest.mark.parametrize("which", ["points", "normals"])
+def test_pose_gradient_with_one_contact_gradient(solver, which):
+    import torch
+    hb = wl.hand_batch(41, 200, m=5)
+    rng = np.random.default_rng(4)
+    v = rng.standard_normal((hb.n_grasps, hb.m_max, 3)).astype(np.float32)
+    dh = api.DeviceHand(hb)
+    tv = torch.as_tensor(v, device="cuda")
+    g = solver.pose_gradient(dh, tv if which == "points" else None, tv if which == "normals" else None,
+                             _f32(10.0), _f32(0.01), 0.0)
+    torch.cuda.synchronize()
+    R, T, cl, ax = _f64(hb)
+    v64 = v.astype(np.float64)
+    E, dw, dT = oc.pose_gradient(R, T, cl, ax, v64 if which == "points" else None,
+                                 v64 if which == "normals" else None, _f32(10.0), _f32(0.01), 0.0)
+    zero = np.zeros_like(v64)
+    sT, sw = _tip_scales(hb, v64 if which == "points" else zero, v64 if which == "normals" else zero, _f32(10.0),
+                         _f32(0.01), 0.0)
+    assert np.all(np.abs(_np(g["dL_dtrans"]) - dT).max(axis=1) <= 4 * U * sT + 1e-12)
+    assert np.all(np.abs(_np(g["dL_drot"]) - dw).max(axis=1) <= 4 * U * sw + 1e-12)

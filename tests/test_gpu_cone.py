@@ -177,3 +177,20 @@ def test_cone_rejects_bad_model_value():
     p.friction_cone = 7
     h = ctypes.c_void_p()
     assert api.lib().bodex_qp_create(ctypes.byref(p), 0, None, 0, ctypes.byref(h)) == api.EINVAL
+
+
+def test_cone_backward_with_the_normal_sum_row():
+    # gamma > 0: the chain rule of the backward against the oracle's on the
+    # same forces, the forces against the oracle's minimiser
+    b = wl.config(2, 24)
+    gpu = _solve(b, gamma=1.0, backward=True)
+    ref = _oracle(b, gamma=1.0)
+    _check(b, gpu, ref)
+    P0, N0 = b.points.astype(np.float64), b.normals.astype(np.float64)
+    f_gpu = gpu["forces"].astype(np.float64)
+    rp, rn = oracle.grad_batch(b.counts, b.woff, P0, N0, b.wrench, f_gpu, we=np.ones(b.n_grasps))
+    rel = lambda a, r: np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-4)
+    ep = max(rel(gpu["dP"][g], rp[g]) for g in range(b.n_grasps))
+    en = max(rel(gpu["dN"][g], rn[g]) for g in range(b.n_grasps))
+    print("cone gamma 1 grad rel err points %.2e normals %.2e" % (ep, en))
+    assert ep <= 1e-3 and en <= 1e-3
