@@ -145,6 +145,12 @@ typedef struct {
     float *z;   /* device [9 m_max + 1][W]                                    */
     float *y;   /* device [9 m_max + 1][W]  dual variables                    */
     float *rho; /* device [G]               per-grasp ADMM step size          */
+    float *r;   /* optional device [6][W]: the wrench residual G f - beta t */
+                /* of the returned forces, formed in FP64 and rounded; the  */
+                /* backward uses it (formed from the FP32 forces it loses   */
+                /* its digits to cancellation when it is small).  NULL: not */
+                /* written; the backward then recovers f* in FP64 (pyramid: */
+                /* one more polish) or uses the FP32 forces (cone).         */
 } bodex_state;
 
 typedef struct {
@@ -211,8 +217,8 @@ int bodex_qp_destroy(bodex_qp_t *h);
  * h is NULL).  Valid until the next call on the handle. */
 const char *bodex_qp_last_error(const bodex_qp_t *h);
 
-/* Device bytes of a caller-held state for a batch (x, z, y, rho); the
- * pyramid layout, an upper bound for the circular cone's. */
+/* Device bytes of a caller-held state for a batch (x, z, y, rho and the
+ * residual r); the pyramid layout, an upper bound for the circular cone's. */
 size_t bodex_qp_state_bytes(int n_grasps, int n_qps, int m_max);
 
 /* Statistics of the last solve (host copies, filled after the stream is

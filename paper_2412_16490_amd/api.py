@@ -85,7 +85,8 @@ class Descent(ctypes.Structure):
 
 class State(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("z", ctypes.c_void_p),
-                ("y", ctypes.c_void_p), ("rho", ctypes.c_void_p)]
+                ("y", ctypes.c_void_p), ("rho", ctypes.c_void_p),
+                ("r", ctypes.c_void_p)]
 
 
 class Result(ctypes.Structure):
@@ -231,17 +232,21 @@ class DeviceBatch:
         return b
 
 
-def new_state(n_grasps, n_qps, m_max, device="cuda", cone=False):
+def new_state(n_grasps, n_qps, m_max, device="cuda", cone=False, residual=True):
     """Caller-held ADMM state; cone: the circular-cone layout (3 m_max + 1
-    rows of z and y instead of 9 m_max + 1)."""
+    rows of z and y instead of 9 m_max + 1); residual: also the wrench
+    residual the backward uses (state.r)."""
     import torch
     nr = (3 if cone else 9) * m_max + 1
-    return {
+    st = {
         "x": torch.zeros((3 * m_max, n_qps), dtype=torch.float32, device=device),
         "z": torch.zeros((nr, n_qps), dtype=torch.float32, device=device),
         "y": torch.zeros((nr, n_qps), dtype=torch.float32, device=device),
         "rho": torch.zeros((n_grasps,), dtype=torch.float32, device=device),
     }
+    if residual:
+        st["r"] = torch.zeros((6, n_qps), dtype=torch.float32, device=device)
+    return st
 
 
 def new_result(n_grasps, n_qps, m_max, device="cuda", polish_flops=False):
@@ -263,6 +268,7 @@ def _c_state(st) -> State:
     s = State()
     if st is not None:
         s.x, s.z, s.y, s.rho = _ptr(st["x"]), _ptr(st["z"]), _ptr(st["y"]), _ptr(st["rho"])
+        s.r = _ptr(st["r"]) if st.get("r") is not None else None
     return s
 
 

@@ -68,6 +68,7 @@ struct KArgs {
     int* iters;
     unsigned char* status;
     float* pflops;  // optional: polish flops per QP
+    float* resid;   // optional state: [6][W] wrench residual G f - beta t of the returned forces (FP64, rounded)
     // backward
     const float* dLdE;
     const float* dLdQ;
@@ -806,6 +807,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BODEX_F
 #pragma unroll
             for (int k = 0; k < 6; ++k) rr2 += r6[k] * r6[k];
             Q = rr2 + double(a.eps) * ff;
+            if (a.resid) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) a.resid[size_t(k) * W_ + w] = finite_in ? float(r6[k]) : NAN;
+            }
             double rel = NAN;
             if (finite_in) {
                 const float* xs = a.x + w;
@@ -981,6 +986,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) co
 #pragma unroll
             for (int k = 0; k < 6; ++k) rr2 += r6[k] * r6[k];
             Q = rr2 + double(a.eps) * ff;
+            if (a.resid) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) a.resid[size_t(k) * W_ + w] = finite_in ? float(r6[k]) : NAN;
+            }
             double rel = NAN;
             if (finite_in) {
                 const float* xs = a.x + w;
@@ -1017,9 +1026,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) co
 // ---------------------------------------------------------------------------
 // Backward kernel.
 // ---------------------------------------------------------------------------
-// CONE: the circular-cone form, whose polished forces the solve left in
-// state.x (FP32 rounding of the FP64 polish); the pyramid form re-runs its
-// polish from the state's duals.
+// f* is the point the solve left in state.x (FP32 rounding of its FP64
+// polish).  With the state's residual (state.r, G f* - beta t formed in FP64
+// by the solve) the gradient uses it directly; without it the pyramid form
+// re-runs its polish from the state's duals to recover f* in FP64, and the
+// cone form forms the residual from the FP32 forces.
 template <int MM, bool GAM, bool CONE>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) backward_kernel(const KArgs a) {
     constexpr int NV = 3 * MM, NG = 6 * NV;
@@ -1051,7 +1062,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) ba
             double bt[6];
 #pragma unroll
             for (int r = 0; r < 6; ++r) bt[r] = double(a.beta) * tw[r];
-            if constexpr (!CONE) {
+            if (!CONE && !a.resid) {
                 const LdsPolishData<MM, GAM> D = polish_data<MM, GAM>(a, P, slot, si, bt);
                 PolishState<MM> PS;
                 PS.S.pc = projector_cache<MM>(P, lane);
@@ -1074,6 +1085,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) ba
                 double v = -double(a.beta) * tw[r];
 #pragma unroll
                 for (int c = 0; c < NV; ++c) v += Gs[r * NV + c] * f[c];
+                // the stored residual carries the digits that G f - beta t
+                // loses to cancellation when formed from FP32 forces
+                if (a.resid) v = a.resid[size_t(r) * a.W + w];
                 rw[r] = 2.0 * om * v;
             }
 #pragma unroll

@@ -568,6 +568,7 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
         a.z = st.z;
         a.y = st.y;
         a.rho = st.rho;
+        a.resid = st.r;
     } else {
         const size_t need = (size_t(W) * (nv + 2 * nr) + size_t(G)) * sizeof(float);
         rc = ensure_device(h, reinterpret_cast<void**>(&h->d_state), &h->d_state_cap, need);
@@ -686,6 +687,7 @@ int bodex_qp_backward(bodex_qp_t* h, const bodex_batch* in, const bodex_state* s
     a.z = st->z;
     a.y = st->y;
     a.rho = st->rho;
+    a.resid = st->r;
     a.dLdE = dL_dE;
     a.dLdQ = dL_dQ;
     a.dP = dL_dpoints;
@@ -740,7 +742,7 @@ const char* bodex_qp_last_error(const bodex_qp_t* h) {
 size_t bodex_qp_state_bytes(int n_grasps, int n_qps, int m_max) {
     if (n_grasps < 0 || n_qps < 0 || m_max < 1) return 0;
     const size_t nv = 3 * size_t(m_max), nr = 9 * size_t(m_max) + 1;
-    return (size_t(n_qps) * (nv + 2 * nr) + size_t(n_grasps)) * sizeof(float);
+    return (size_t(n_qps) * (nv + 2 * nr + 6) + size_t(n_grasps)) * sizeof(float);
 }
 
 int bodex_qp_kernel_times(bodex_qp_t* h, float* admm_ms, float* finalize_ms, float* backward_ms) {
@@ -871,14 +873,17 @@ int bodex_qp_descend(bodex_qp_t* h, const bodex_hand* hand, const bodex_batch* q
         a.z = st.z;
         a.y = st.y;
         a.rho = st.rho;
+        a.resid = st.r;
     } else {
-        const size_t need = (size_t(W) * (nv + 2 * nr) + size_t(G)) * sizeof(float);
+        // the library's state, with the residual the backward of each step uses
+        const size_t need = (size_t(W) * (nv + 2 * nr + 6) + size_t(G)) * sizeof(float);
         rc = ensure_device(h, reinterpret_cast<void**>(&h->d_state), &h->d_state_cap, need);
         if (rc) return rc;
         a.x = h->d_state;
         a.z = a.x + size_t(W) * nv;
         a.y = a.z + size_t(W) * nr;
         a.rho = a.y + size_t(W) * nr;
+        a.resid = a.rho + size_t(G);
     }
     a.forces = out->forces;
     a.qobj = out->qp_obj;

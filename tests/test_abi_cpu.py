@@ -59,7 +59,8 @@ def test_create_without_device_reports_enodev(L):
 
 
 def test_state_bytes(L):
-    assert api.bodex_qp_state_bytes(10, 100, 5) == (100 * (15 + 2 * 46) + 10) * 4
+    # x (15), z and y (46 each) and the residual (6) per QP, rho per grasp
+    assert api.bodex_qp_state_bytes(10, 100, 5) == (100 * (15 + 2 * 46 + 6) + 10) * 4
     assert api.bodex_qp_state_bytes(-1, 1, 5) == 0
 
 

@@ -15,14 +15,14 @@ from gpu_common import oracle_params, run_gpu
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_grad(b, dE=None, dQ=None, **params):
+def _gpu_grad(b, dE=None, dQ=None, residual=True, **params):
     import torch
     p = api.default_params(m_max=b.m_max, s_max=int(np.max(np.diff(b.woff))))
     for k, v in params.items():
         setattr(p, k, v)
     s = api.Solver(p)
     db = api.DeviceBatch(b)
-    st = api.new_state(db.n_grasps, db.n_qps, db.m_max)
+    st = api.new_state(db.n_grasps, db.n_qps, db.m_max, residual=residual)
     res = s.solve(db, state=st)
     tE = torch.as_tensor(dE, dtype=torch.float32, device="cuda") if dE is not None else None
     tQ = torch.as_tensor(dQ, dtype=torch.float32, device="cuda") if dQ is not None else None
@@ -48,6 +48,20 @@ def test_backward_matches_oracle_gradient():
     ep = max(_rel(gp[g], rp[g]) for g in range(b.n_grasps))
     en = max(_rel(gn[g], rn[g]) for g in range(b.n_grasps))
     print("grad rel err points %.2e normals %.2e" % (ep, en))
+    assert ep <= 1e-3 and en <= 1e-3
+
+
+def test_backward_without_the_stored_residual():
+    # a state without state.r: the backward re-runs the polish to recover f*
+    # in FP64 (the path of callers that keep the smaller state)
+    b = wl.config(2, 128)
+    gp, gn, res = _gpu_grad(b, dE=np.ones(b.n_grasps), residual=False)
+    P0, N0 = b.points.astype(np.float64), b.normals.astype(np.float64)
+    ref = oracle.solve_batch(b.counts, b.woff, P0, N0, b.mu, b.wrench)
+    rp, rn = oracle.grad_batch(b.counts, b.woff, P0, N0, b.wrench, ref["forces"], we=np.ones(b.n_grasps))
+    ep = max(_rel(gp[g], rp[g]) for g in range(b.n_grasps))
+    en = max(_rel(gn[g], rn[g]) for g in range(b.n_grasps))
+    print("no residual: grad rel err points %.2e normals %.2e" % (ep, en))
     assert ep <= 1e-3 and en <= 1e-3
 
 
