@@ -88,6 +88,8 @@ def main():
                     help="only run the circular-cone form and print its JSON")
     ap.add_argument("--detach-only", action="store_true",
                     help="only run the fine-stage surrogate (Detach) form at 2^20 grasps and print its JSON")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="only run the batch-size sweep of the headline shape")
     ap.add_argument("--descent-only", action="store_true",
                     help="only run the coarse-stage descent form (floating hands on ellipsoids)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -124,6 +126,9 @@ def main():
         return
     if args.detach_only:
         print(json.dumps({"detach_surrogate": detach_form(torch, api, wl, large_only=True)}), flush=True)
+        return
+    if args.sweep_only:
+        print(json.dumps({"size_sweep": size_sweep(torch, api, wl)}), flush=True)
         return
     if args.descent_only:
         print(json.dumps({"coarse_descent": descent_form(torch, api, wl)}), flush=True)
@@ -299,6 +304,7 @@ def forms(torch, api, wl):
     res["detach_surrogate"] = detach_form(torch, api, wl)
     res["circular_cone"] = cone_form(torch, api, wl)
     res["coarse_descent"] = descent_form(torch, api, wl)
+    res["size_sweep"] = size_sweep(torch, api, wl)
     # forward + backward (differentiation workload, same shape as the headline)
     b2 = wl.config(2)
     db2 = api.DeviceBatch(b2)
@@ -327,6 +333,38 @@ def forms(torch, api, wl):
                       "grasps_per_s": round(db2.n_grasps / tfb, 1)}
     s2.close()
     return res
+
+
+def size_sweep(torch, api, wl, sizes=(2048, 8192, 32768, 131072)):
+    """The headline shape (5 contacts, 16 wrenches, ellipsoids) at several
+    batch sizes: 8192 grasps are exactly one round of waves on the chip (the
+    finalize's time is then its slowest waves'); larger batches run several
+    rounds, which the hardware dispatcher balances."""
+    out = {}
+    stream = torch.cuda.current_stream()
+    for G in sizes:
+        b = wl.uniform_batch(16491, G, 5, 16, name="sweep")
+        db = api.DeviceBatch(b)
+        p = api.default_params(m_max=5, s_max=16)
+        sv = api.Solver(p, stream=stream.cuda_stream)
+        st = api.new_state(db.n_grasps, db.n_qps, 5)
+        r = api.new_result(db.n_grasps, db.n_qps, 5)
+        sv.solve(db, state=st, result=r)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record(stream)
+        for _ in range(reps):
+            sv.solve(db, state=st, result=r)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        conv = int(np.sum((r["status"].cpu().numpy() & api.ST_CONVERGED) != 0))
+        out[str(G)] = {"qps": db.n_qps, "ms": round(ms, 3), "qps_per_s": round(conv / (ms / 1e3), 1),
+                       "converged": conv}
+        sv.close()
+        del db, st, r
+    return out
 
 
 def descent_form(torch, api, wl, iters=20):
