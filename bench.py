@@ -200,7 +200,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32+f64",  # FP32 ADMM iterations, FP64 polish and outputs' checks
         "data": "synthetic",
         "config": {"workload": "ellipsoid-m5-s16 (8192 grasps x 5 contacts x 16 wrenches, seed 16491)",
                    "qps": int(db.n_qps), "tol_rel": float(p.tol_rel), "form": "plain",
