@@ -153,6 +153,26 @@ def test_full_mixed_batched_graph_sampled():
     assert np.all(np.isfinite(gpu["forces"]))
 
 
+def test_largest_swept_batch_sampled():
+    # 131,072 grasps x 16 wrenches (2.1 M QPs, the largest batch the
+    # benchmark sweeps): sampled grasps against the oracle, every QP checked
+    # for convergence
+    b = wl.uniform_batch(16491, 131072, 5, 16, name="sweep")
+    gpu = run_gpu(b)
+    rng = np.random.default_rng(13)
+    grasps = np.sort(rng.choice(b.n_grasps, 48, replace=False))
+    grasps = np.unique(np.concatenate([grasps, [0, b.n_grasps - 1]]))
+    sub = b.subset(grasps)
+    ref = _ref(sub)
+    qps = np.concatenate([np.arange(b.woff[g], b.woff[g + 1]) for g in grasps])
+    sub_gpu = {k: gpu[k][qps] for k in ("forces", "qp_obj", "status", "kkt_rel", "iters")}
+    sub_gpu["energy"] = gpu["energy"][grasps]
+    print("2.1M QPs sampled:", check_forward(sub, sub_gpu, ref))
+    check_energy(sub, sub_gpu, ref)
+    assert np.all(gpu["status"] & api.ST_CONVERGED)
+    assert np.all(np.isfinite(gpu["forces"]))
+
+
 def test_gamma_and_bounds_parity():
     b = wl.config(1, 40)
     for gamma, fmax, beta in [(0.5, 1.0, 1.0), (1.2, 0.5, 2.0)]:
