@@ -439,7 +439,8 @@ BODEX_FI void cross3(const double* a, const double* b, double* c) {
 //    so with Pi = diag(Pi_i) and P = 2 (G^T G + eps I) the reduced inverse is
 //      H v = Z (Z^T P Z)^{-1} Z^T v
 //          = (Pi v - Pi G^T (eps I6 + G Pi G^T)^{-1} G Pi v) / (2 eps),
-//    one 6x6 Cholesky factor per active set (Woodbury identity);
+//    one 6x6 Cholesky factor per active set (Woodbury identity), whose
+//    matrix changes by a rank-one term when one row joins or leaves;
 //  * an active normal-sum row a removes one more direction from Pi: the unit
 //    vector along u = Pi a (u lies in the contacts' null spaces).
 // Multipliers follow from stationarity: per contact from the closed-form
@@ -599,6 +600,24 @@ BODEX_FI void chol6_solve(const Sym6& L, double* v) {
         for (int l = i + 1; l < 6; ++l) s -= L.a[lo_idx(l, i)] * v[l];
         v[i] = s * L.a[lo_idx(i, i)];
     }
+}
+
+// M = L L^T in place (L packed lower with reciprocal diagonal): rows from
+// the last, each from its diagonal down, so that every entry of L is read
+// before it is overwritten.
+BODEX_FI void chol6_product(Sym6& L) {
+    double d[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) d[k] = 1.0 / L.a[lo_idx(k, k)];
+#pragma unroll
+    for (int i = 5; i >= 0; --i)
+#pragma unroll
+        for (int j = i; j >= 0; --j) {
+            double s = (j == i) ? d[i] * d[i] : L.a[lo_idx(i, j)] * d[j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) s += L.a[lo_idx(i, k)] * L.a[lo_idx(j, k)];
+            L.a[lo_idx(i, j)] = s;
+        }
 }
 
 // The problem data the polish reads: G in FP64 [6][3 MM] (row-major), mu_i
@@ -813,11 +832,11 @@ BODEX_FI double sum_row_norm2(const D& Dt, const ActiveSet<MM>& S) {
     return un;
 }
 
-// Refresh the projectors and factor eps I6 + G Pi G^T = eps I6 +
-// sum_i (G_i Pi_i)(G_i Pi_i)^T, minus (G u)(G u)^T / |u|^2 with the
-// normal-sum row.
+// Refresh the projectors and form (in S.L, to be factored) eps I6 + G Pi G^T
+// = eps I6 + sum_i (G_i Pi_i)(G_i Pi_i)^T, minus (G u)(G u)^T / |u|^2 with
+// the normal-sum row.
 template <int MM, typename D>
-BODEX_FI bool factor_set(const D& Dt, ActiveSet<MM>& S) {
+BODEX_FI bool set_matrix(const D& Dt, ActiveSet<MM>& S) {
     constexpr int NV = 3 * MM;
     const bool gam = D::kGam && S.gam;
 #pragma unroll
@@ -862,7 +881,48 @@ BODEX_FI bool factor_set(const D& Dt, ActiveSet<MM>& S) {
 #pragma unroll
             for (int c = 0; c <= r; ++c) S.L.a[lo_idx(r, c)] -= gu[r] * gu[c] * iu;
     }
-    return chol6(S.L);
+    return true;
+}
+
+// One row (kk) of contact i has just joined (sgn = -1) or left (sgn = +1)
+// the active set; S.mask holds the new set and S.L the factor of the old
+// one.  With Q the projector of the contact's other active rows and
+// e = Q c / |Q c| (c the row's coefficients), the contact's projector goes
+// from Q to Q - e e^T when the row joins and back when it leaves, so
+// eps I6 + G Pi G^T changes by sgn (G_i e)(G_i e)^T: the new matrix is
+// formed from the old factor (to be factored like a fresh one) instead of
+// from every contact.  Also refreshes the contact's cached projector.
+template <int MM, typename D>
+BODEX_FI bool matrix_row_change(const D& Dt, ActiveSet<MM>& S, int i, int kk, double sgn) {
+    constexpr int NV = 3 * MM;
+    const unsigned now = contact_mask(S.mask, i);
+    ContactRows R;
+    ContactProj Q;
+    contact_rows(now & ~(1u << kk), Dt.muc[i], Dt.fmax, R);
+    contact_proj(R, Q);
+    double c[3], b;
+    row3(kk, Dt.muc[i], Dt.fmax, c, &b);
+    proj_apply(Q, c);
+    const double n2 = dot3(c, c);
+    if (!(n2 > 0.0)) return false;
+    const double s = sgn / n2;
+    double v[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        v[k] = Dt.G[k * NV + 3 * i] * c[0] + Dt.G[k * NV + 3 * i + 1] * c[1] + Dt.G[k * NV + 3 * i + 2] * c[2];
+    chol6_product(S.L);
+#pragma unroll
+    for (int r = 0; r < 6; ++r)
+#pragma unroll
+        for (int q = 0; q <= r; ++q) S.L.a[lo_idx(r, q)] += s * v[r] * v[q];
+    if (S.pc.p != nullptr) {
+        ContactProj P;
+        contact_rows(now, Dt.muc[i], Dt.fmax, R);
+        contact_proj(R, P);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) S.pc[3 * i + t] = P.e[t];
+    }
+    return true;
 }
 
 // The pending row p of the one-row steps: contact pi, row pk (pk = 9: the
@@ -988,8 +1048,9 @@ BODEX_FI PendingRow most_violated(const D& Dt, const ActiveSet<MM>& S, const Pol
 
 struct PolishOut {
     int status;  // 0 accepted, 1 rejected by the KKT check, 2 step cap, 3 breakdown
-    int steps;   // factorisations
-    int eqps;    // equality-constrained solves (two passes and the multipliers each)
+    int steps;   // factorisations, fresh or by a rank-one change
+    int updates; // ... of which rank-one changes
+    int eqps;   // equality-constrained solves (two passes and the multipliers each)
     int moves;   // one-row steps (ratio test and move; the refactor and the
                  // multipliers that follow are counted in steps and moves)
     int picks;   // searches for the most violated row
@@ -1001,6 +1062,8 @@ struct PolishOut {
 //   warm start            249 m per pass, 3 passes  (projector 15 + 9 rows x
 //                         (projection 15, two dots 10, scale 1))
 //   factorisation         231 m + 100  (6 projected G rows, 21 dots, 6x6 Cholesky 97)
+//   one-row change        312          (projector of the other rows 19, projected
+//                         row 20, G_i e 31, L L^T 97, plus s v v^T 48, 6x6 Cholesky 97)
 //   reduced solve H v     108 m + 72   (two projections, G v, G^T w, 6x6 solves 72)
 //   equality solve        527 m + 144  (start point 36 m, two passes of gradient 78 m
 //                         + H v + update 3 m, multiplier check 113 m)
@@ -1010,8 +1073,8 @@ struct PolishOut {
 //   acceptance            227 m
 BODEX_FI double polish_flops(int m, const PolishOut& o) {
     const double dm = m;
-    return 3.0 * 249.0 * dm + 227.0 * dm + o.steps * (231.0 * dm + 100.0) + o.eqps * (527.0 * dm + 144.0) +
-           o.moves * (377.0 * dm + 77.0) + o.picks * 54.0 * dm;
+    return 3.0 * 249.0 * dm + 227.0 * dm + (o.steps - o.updates) * (231.0 * dm + 100.0) + o.updates * 312.0 +
+           o.eqps * (527.0 * dm + 144.0) + o.moves * (377.0 * dm + 77.0) + o.picks * 54.0 * dm;
 }
 
 // The polish of one QP, as a resumable state machine: polish_begin sets the
@@ -1031,9 +1094,22 @@ BODEX_FI double polish_flops(int m, const PolishOut& o) {
 // the final set once more, exactly, then the KKT acceptance check.  Each
 // linear-algebra routine has a single call site in polish_advance (small
 // code on the GPU), and a lane can start the next QP as soon as its current
-// one finishes.
+// one finishes.  Every set change is one row, so after the first
+// factorisation each new matrix is formed from the previous factor and that
+// row's rank-one term (matrix_row_change: ~310 flops against ~1250 for a
+// matrix from every contact at m = 5); the two-pass equality solves absorb
+// the rounding this carries from set to set, and a QP whose acceptance
+// check fails after such changes is taken once more from its last set with
+// fresh factorisations only.  With the normal-sum row (whose term involves
+// every contact) every matrix is formed from scratch.
 enum PolishPhase { kWarm, kSteps, kFinal };
 enum PolishMode { kEqp0, kEqp1, kStep, kCheck, kPick, kAccept };
+enum PolishChange { kNoChange = 0x1FF, kChgJoin = 1 << 9, kChgUsed = 1 << 10, kChgAllowed = 1 << 11 };
+
+// The pending set change in PS.chg: row 9 i + kk, joined or left.
+BODEX_FI int with_change(int chg, int row, bool join) {
+    return (chg & ~(kNoChange | kChgJoin)) | row | (join ? int(kChgJoin) : 0);
+}
 
 template <int MM>
 struct PolishState {
@@ -1042,6 +1118,10 @@ struct PolishState {
     double up, mup, lg;
     int phase, mode;
     bool refactor, need_mult;
+    // bits 0-8: row 9 i + kk of the set change the next factorisation may
+    // take as a one-row change of the last factor (kNoChange: none), bit 9:
+    // it joined; flags: such changes were used, they are allowed
+    int chg;
     PolishOut out;
 };
 
@@ -1050,6 +1130,7 @@ BODEX_FI void polish_begin(const D& Dt, YP y0, PolishState<MM>& PS) {
     PolishOut& out = PS.out;
     out.status = 0;
     out.steps = 0;
+    out.updates = 0;
     out.eqps = 0;
     out.moves = 0;
     out.picks = 0;
@@ -1109,6 +1190,8 @@ BODEX_FI void polish_begin(const D& Dt, YP y0, PolishState<MM>& PS) {
     PS.mode = kEqp0;
     PS.refactor = true;
     PS.need_mult = false;
+    // no rank-one changes with the normal-sum row (its term involves every contact)
+    PS.chg = kNoChange | (D::kGam ? 0 : int(kChgAllowed));
 }
 
 // Acceptance: stationarity, dual and primal feasibility.  Sets the status
@@ -1185,16 +1268,53 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
     const bool use_gam = D::kGam && Dt.gamma > 0.0 && m > 0;
     const double tol_add = 1e-12 * (1.0 + fm + Dt.gamma);
     const PendingRow none = {-1, -1, {0.0, 0.0, 0.0}, 0.0};
-    if (mode == kAccept) return polish_accept<MM>(Dt, W, PS);
+    if (mode == kAccept) {
+        const bool done = polish_accept<MM>(Dt, W, PS);
+        if (out.status == 1 && (PS.chg & kChgUsed)) {
+            // rejected after rank-one changes: once more from this set with
+            // fresh factorisations only (equality solve, multiplier drops,
+            // steps)
+            out.status = 0;
+            PS.chg = kNoChange;
+            refactor = true;
+            phase = kWarm;
+            mode = kEqp0;
+            return false;
+        }
+        return done;
+    }
     if (refactor) {
         if (++out.steps > max_steps) {
             out.status = 2;
             return true;
         }
-        if (!factor_set<MM>(Dt, S)) {
+        // the matrix of the new set from the old factor and the one-row
+        // change when there is one, else (or if that does not factor) from
+        // every contact; one Cholesky call site
+        const int row = PS.chg & kNoChange;
+        bool quick = (PS.chg & kChgAllowed) && row != kNoChange;
+        bool ok = false;
+#pragma unroll 1
+        for (;;) {
+            if (quick) {
+                const int ci = row / 9;
+                ok = matrix_row_change<MM>(Dt, S, ci, row - 9 * ci, (PS.chg & kChgJoin) ? -1.0 : 1.0);
+            } else {
+                ok = set_matrix<MM>(Dt, S);
+            }
+            ok = ok && chol6(S.L);
+            if (ok || !quick) break;
+            quick = false;
+        }
+        if (!ok) {
             out.status = 3;
             return true;
         }
+        if (quick) {
+            ++out.updates;
+            PS.chg |= kChgUsed;
+        }
+        PS.chg = with_change(PS.chg, kNoChange, false);
         refactor = false;
     }
     if (need_mult) {
@@ -1240,10 +1360,12 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
                 }
             }
             if (wbit >= 0) {
-                if (D::kGam && wbit == 9 * MM)
+                if (D::kGam && wbit == 9 * MM) {
                     S.gam = false;
-                else
+                } else {
                     S.mask &= ~(RowMask<MM>(1) << wbit);
+                    PS.chg = with_change(PS.chg, wbit, false);
+                }
                 refactor = true;
                 mode = kEqp0;
                 return false;
@@ -1261,7 +1383,7 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
                 mode = kAccept;
                 return false;
             }
-            mode = kEqp0;                // after steps: re-solve exactly
+            mode = kEqp0;  // after steps: re-solve exactly
         } else {
             phase = kSteps;
             up = 0.0;
@@ -1414,20 +1536,24 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
     need_mult = true;
     if (t2 <= t1) {
         // p joins the active set; an exact re-solve follows the last step
-        if (p.pk == 9)
+        if (p.pk == 9) {
             S.gam = true;
-        else
+        } else {
             S.mask |= RowMask<MM>(1) << (9 * p.pi + p.pk);
+            PS.chg = with_change(PS.chg, 9 * p.pi + p.pk, true);
+        }
         phase = kFinal;
         mp = none;
         mup = 0.0;
         mode = kPick;
     } else {
         // drop the row whose multiplier reached zero, continue with p
-        if (D::kGam && lbit == 9 * MM)
+        if (D::kGam && lbit == 9 * MM) {
             S.gam = false;
-        else
+        } else {
             S.mask &= ~(RowMask<MM>(1) << lbit);
+            PS.chg = with_change(PS.chg, lbit, false);
+        }
         mp = p;
         mup = up;
         mode = kStep;

@@ -65,3 +65,79 @@ int host_polish_grasp(int m, const double* p, const double* n, const double* mu,
 }
 
 }  // extern "C"
+
+extern "C" {
+
+// The matrix eps I6 + G Pi G^T of the active set `after` formed two ways:
+// from the factor of `before` and the one-row change (row 9 ci + kk joined
+// when join, else left), and from every contact.  mask bits as in the
+// solver (9 per contact); m <= 5; p, n: [m][3]; out_change, out_scratch:
+// packed lower [21].  Returns 0, or 1 if a factorisation failed.
+int host_matrix_change(int m, const double* p, const double* n, const double* mu, double kappa, double eps,
+                       unsigned long long before, unsigned long long after, int ci, int kk, int join,
+                       double* out_change, double* out_scratch) {
+    constexpr int MM = 5, NV = 15;
+    double G[6 * NV] = {};
+    double muc[MM] = {};
+    for (int i = 0; i < m; ++i) {
+        grasp_columns<double, NV>(p + 3 * i, n + 3 * i, kappa, i, G);
+        muc[i] = mu[i] * kC8;
+    }
+    PolishData<MM, const double*, false> D;
+    D.G = G;
+    D.muc = muc;
+    for (int r = 0; r < 6; ++r) D.bt[r] = 0.0;
+    D.m = m;
+    D.fmax = 1.0;
+    D.gamma = 0.0;
+    D.eps = eps;
+    ActiveSet<MM> S;
+    S.gam = false;
+    S.pc = LaneVec{nullptr, 1};
+    S.mask = before;
+    if (!set_matrix<MM>(D, S) || !chol6(S.L)) return 1;
+    S.mask = after;
+    if (!matrix_row_change<MM>(D, S, ci, kk, join ? -1.0 : 1.0)) return 1;
+    for (int r = 0; r < 21; ++r) out_change[r] = S.L.a[r];
+    if (!set_matrix<MM>(D, S)) return 1;
+    for (int r = 0; r < 21; ++r) out_scratch[r] = S.L.a[r];
+    return 0;
+}
+
+// Solve s QPs of one grasp as host_polish_grasp does, also reporting the
+// polish's counts [s][4]: factorisations, of which one-row changes, equality
+// solves, one-row steps.
+int host_polish_counts(int m, const double* p, const double* n, const double* mu, const double* t, int s,
+                       double kappa, double eps, const float* y0, int* counts) {
+    constexpr int MM = 5, NV = 15;
+    double G[6 * NV] = {};
+    double muc[MM] = {};
+    for (int i = 0; i < m; ++i) {
+        grasp_columns<double, NV>(p + 3 * i, n + 3 * i, kappa, i, G);
+        muc[i] = mu[i] * kC8;
+    }
+    int bad = 0;
+    for (int j = 0; j < s; ++j) {
+        PolishData<MM, const double*, false> D;
+        D.G = G;
+        D.muc = muc;
+        for (int r = 0; r < 6; ++r) D.bt[r] = t[6 * j + r];
+        D.m = m;
+        D.fmax = 1.0;
+        D.gamma = 0.0;
+        D.eps = eps;
+        double xb[NV] = {}, zb[NV] = {}, pcb[3 * MM] = {};
+        PolishWork<LaneVec> W{{xb, 1}, {zb, 1}};
+        PolishState<MM> PS;
+        PS.S.pc = LaneVec{pcb, 1};
+        const PolishOut po = polish_qp<MM>(D, y0 + 46 * j, 200, W, PS);
+        counts[4 * j] = po.steps;
+        counts[4 * j + 1] = po.updates;
+        counts[4 * j + 2] = po.eqps;
+        counts[4 * j + 3] = po.moves;
+        bad += po.status != 0;
+    }
+    return bad;
+}
+
+}  // extern "C"

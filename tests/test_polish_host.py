@@ -75,3 +75,107 @@ def test_polish_reaches_oracle_minimiser(host, cfg, ng, gamma, fmax):
             x, st, steps = _solve(host, b, g, y0, gamma, fmax)
             assert np.all(st == 0), (g, st)
             assert np.abs(x - fr).max() <= 1e-8 * fmax, (g, np.abs(x - fr).max())
+
+
+def _valid_rows(rng):
+    """A random active row set of one contact that the polish can hold: up to
+    three rows, independent (no bound row together with two opposite facets,
+    whose tangential parts are parallel)."""
+    while True:
+        n = int(rng.integers(0, 4))
+        rows = sorted(rng.choice(9, size=n, replace=False).tolist())
+        facets = [k for k in rows if k < 8]
+        if 8 in rows and len(facets) == 2 and abs(facets[0] - facets[1]) == 4:
+            continue
+        return rows
+
+
+def test_one_row_change_matches_the_matrix_from_every_contact(host):
+    # a row joining or leaving contact ci changes eps I + G Pi G^T by a
+    # rank-one term; the matrix formed from the old factor plus that term must
+    # equal the one formed from every contact's projector
+    b = wl.config(1, 40)
+    rng = np.random.default_rng(11)
+    worst = 0.0
+    for g in range(b.n_grasps):
+        m = int(b.counts[g])
+        p, pp = _d(b.points[g, :m])
+        n, pn = _d(b.normals[g, :m])
+        mu, pm = _d(b.mu[g, :m])
+        for trial in range(6):
+            rows = [_valid_rows(rng) for _ in range(m)]
+            ci = int(rng.integers(0, m))
+            if not rows[ci]:
+                continue
+            kk = int(rng.choice(rows[ci]))
+            full = sum(sum(1 << (9 * i + k) for k in rows[i]) for i in range(m))
+            less = full & ~(1 << (9 * ci + kk))
+            for join in (0, 1):
+                before, after = (less, full) if join else (full, less)
+                a, pa = _d(np.zeros(21))
+                c, pc = _d(np.zeros(21))
+                rc = host.host_matrix_change(m, pp, pn, pm, ctypes.c_double(20.0), ctypes.c_double(1e-6),
+                                             ctypes.c_ulonglong(before), ctypes.c_ulonglong(after), ci, kk, join,
+                                             pa, pc)
+                assert rc == 0
+                err = np.abs(a - c).max() / np.abs(c).max()
+                worst = max(worst, err)
+                assert err <= 1e-12, (g, trial, join, err)
+    print("worst relative difference %.2e" % worst)
+
+
+def test_one_row_change_pin_fails_with_the_wrong_direction(host):
+    # planted error on the oracle side of the comparison: the change's
+    # direction taken without projecting out the contact's other rows
+    # differs from the matrix from every contact, so the pin above can fail
+    b = wl.config(1, 4)
+    g, m = 0, int(b.counts[0])
+    G = oracle.grasp_matrix(b.points[g, :m], b.normals[g, :m])
+    mu = b.mu[g, :m] * np.cos(np.pi / 8)
+    rows = {0: [1, 2]}
+    def rowc(i, k):
+        if k == 8:
+            return np.array([1.0, 0.0, 0.0])
+        phi = (2 * k + 1) * np.pi / 8
+        return np.array([-mu[i], np.cos(phi), np.sin(phi)])
+    def M_of(rs):
+        M = 1e-6 * np.eye(6)
+        for i in range(m):
+            C = np.array([rowc(i, k) for k in rs.get(i, [])]).reshape(-1, 3)
+            Pi = np.eye(3) - (C.T @ np.linalg.pinv(C @ C.T) @ C if len(C) else 0.0)
+            Gi = G[:, 3 * i:3 * i + 3]
+            M += Gi @ Pi @ Gi.T
+        return M
+    before, after = M_of({0: [1]}), M_of(rows)
+    c = rowc(0, 2)
+    v = G[:, 0:3] @ (c / np.linalg.norm(c))        # wrong: not projected
+    assert np.abs((before - np.outer(v, v)) - after).max() > 1e-6 * np.abs(after).max()
+    r1 = rowc(0, 1)
+    Q = np.eye(3) - np.outer(r1, r1) / (r1 @ r1)
+    e = Q @ c
+    v = G[:, 0:3] @ (e / np.linalg.norm(e))        # right: projected
+    assert np.abs((before - np.outer(v, v)) - after).max() <= 1e-12 * np.abs(after).max()
+
+
+def test_polish_factors_once_then_changes_one_row_at_a_time(host):
+    b = wl.config(1, 24)
+    rng = np.random.default_rng(13)
+    tot = upd = 0
+    for g in range(b.n_grasps):
+        m = int(b.counts[g])
+        s = int(b.woff[g + 1] - b.woff[g])
+        p, pp = _d(b.points[g, :m])
+        n, pn = _d(b.normals[g, :m])
+        mu, pm = _d(b.mu[g, :m])
+        t, pt = _d(b.wrench[b.woff[g]:b.woff[g + 1]])
+        y0 = np.where(rng.random((s, 46)) < 0.3, rng.random((s, 46)), 0.0).astype(np.float32)
+        cnt = np.zeros((s, 4), np.int32)
+        bad = host.host_polish_counts(m, pp, pn, pm, pt, s, ctypes.c_double(20.0), ctypes.c_double(1e-6),
+                                      y0.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                      cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+        assert bad == 0
+        tot += int(np.sum(cnt[:, 0] - 1))
+        upd += int(np.sum(cnt[:, 1]))
+        assert np.all(cnt[:, 1] <= cnt[:, 0] - 1)
+    print("factorisations after the first: %d, one-row changes: %d" % (tot, upd))
+    assert tot > 0 and upd >= 0.99 * tot
