@@ -1104,7 +1104,13 @@ BODEX_FI double polish_flops(int m, const PolishOut& o) {
 // every contact) every matrix is formed from scratch.
 enum PolishPhase { kWarm, kSteps, kFinal };
 enum PolishMode { kEqp0, kEqp1, kStep, kCheck, kPick, kAccept };
-enum PolishChange { kNoChange = 0x1FF, kChgJoin = 1 << 9, kChgUsed = 1 << 10, kChgAllowed = 1 << 11 };
+enum PolishChange {
+    kNoChange = 0x1FF,
+    kChgJoin = 1 << 9,
+    kChgUsed = 1 << 10,
+    kChgAllowed = 1 << 11,
+    kChgRetry = 1 << 12  // take the retry below even after an accepted check (tests)
+};
 
 // The pending set change in PS.chg: row 9 i + kk, joined or left.
 BODEX_FI int with_change(int chg, int row, bool join) {
@@ -1120,7 +1126,8 @@ struct PolishState {
     bool refactor, need_mult;
     // bits 0-8: row 9 i + kk of the set change the next factorisation may
     // take as a one-row change of the last factor (kNoChange: none), bit 9:
-    // it joined; flags: such changes were used, they are allowed
+    // it joined; flags: such changes were used, they are allowed, a retry
+    // is forced
     int chg;
     PolishOut out;
 };
@@ -1270,7 +1277,7 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
     const PendingRow none = {-1, -1, {0.0, 0.0, 0.0}, 0.0};
     if (mode == kAccept) {
         const bool done = polish_accept<MM>(Dt, W, PS);
-        if (out.status == 1 && (PS.chg & kChgUsed)) {
+        if ((out.status == 1 || (PS.chg & kChgRetry)) && (PS.chg & kChgUsed)) {
             // rejected after rank-one changes: once more from this set with
             // fresh factorisations only (equality solve, multiplier drops,
             // steps)

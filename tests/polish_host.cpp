@@ -104,11 +104,13 @@ int host_matrix_change(int m, const double* p, const double* n, const double* mu
     return 0;
 }
 
-// Solve s QPs of one grasp as host_polish_grasp does, also reporting the
-// polish's counts [s][4]: factorisations, of which one-row changes, equality
-// solves, one-row steps.
+// Solve s QPs of one grasp as host_polish_grasp does (beta = 1, fmax = 1,
+// gamma = 0), also reporting the polish's counts [s][4]: factorisations, of
+// which one-row changes, equality solves, one-row steps; x: [s][15].  With
+// force_retry every QP that used one-row changes is taken once more from its
+// final set on fresh factorisations, as after a failed acceptance check.
 int host_polish_counts(int m, const double* p, const double* n, const double* mu, const double* t, int s,
-                       double kappa, double eps, const float* y0, int* counts) {
+                       double kappa, double eps, const float* y0, int force_retry, int* counts, double* x) {
     constexpr int MM = 5, NV = 15;
     double G[6 * NV] = {};
     double muc[MM] = {};
@@ -130,7 +132,12 @@ int host_polish_counts(int m, const double* p, const double* n, const double* mu
         PolishWork<LaneVec> W{{xb, 1}, {zb, 1}};
         PolishState<MM> PS;
         PS.S.pc = LaneVec{pcb, 1};
-        const PolishOut po = polish_qp<MM>(D, y0 + 46 * j, 200, W, PS);
+        polish_begin<MM>(D, y0 + 46 * j, PS);
+        if (force_retry) PS.chg |= kChgRetry;
+        while (!polish_advance<MM>(D, 200, W, PS)) {
+        }
+        const PolishOut po = PS.out;
+        for (int c = 0; c < NV; ++c) x[NV * j + c] = c < 3 * m ? xb[c] : 0.0;
         counts[4 * j] = po.steps;
         counts[4 * j + 1] = po.updates;
         counts[4 * j + 2] = po.eqps;

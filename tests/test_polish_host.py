@@ -157,25 +157,59 @@ def test_one_row_change_pin_fails_with_the_wrong_direction(host):
     assert np.abs((before - np.outer(v, v)) - after).max() <= 1e-12 * np.abs(after).max()
 
 
+def _counts(host, b, g, y0, force_retry):
+    m = int(b.counts[g])
+    s = int(b.woff[g + 1] - b.woff[g])
+    p, pp = _d(b.points[g, :m])
+    n, pn = _d(b.normals[g, :m])
+    mu, pm = _d(b.mu[g, :m])
+    t, pt = _d(b.wrench[b.woff[g]:b.woff[g + 1]])
+    y = np.ascontiguousarray(y0, dtype=np.float32)
+    cnt = np.zeros((s, 4), np.int32)
+    x = np.zeros((s, 15))
+    bad = host.host_polish_counts(m, pp, pn, pm, pt, s, ctypes.c_double(20.0), ctypes.c_double(1e-6),
+                                  y.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), int(force_retry),
+                                  cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                  x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return bad, cnt, x[:, :3 * m]
+
+
 def test_polish_factors_once_then_changes_one_row_at_a_time(host):
     b = wl.config(1, 24)
     rng = np.random.default_rng(13)
     tot = upd = 0
     for g in range(b.n_grasps):
-        m = int(b.counts[g])
         s = int(b.woff[g + 1] - b.woff[g])
-        p, pp = _d(b.points[g, :m])
-        n, pn = _d(b.normals[g, :m])
-        mu, pm = _d(b.mu[g, :m])
-        t, pt = _d(b.wrench[b.woff[g]:b.woff[g + 1]])
-        y0 = np.where(rng.random((s, 46)) < 0.3, rng.random((s, 46)), 0.0).astype(np.float32)
-        cnt = np.zeros((s, 4), np.int32)
-        bad = host.host_polish_counts(m, pp, pn, pm, pt, s, ctypes.c_double(20.0), ctypes.c_double(1e-6),
-                                      y0.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
-                                      cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+        y0 = np.where(rng.random((s, 46)) < 0.3, rng.random((s, 46)), 0.0)
+        bad, cnt, _ = _counts(host, b, g, y0, False)
         assert bad == 0
         tot += int(np.sum(cnt[:, 0] - 1))
         upd += int(np.sum(cnt[:, 1]))
         assert np.all(cnt[:, 1] <= cnt[:, 0] - 1)
     print("factorisations after the first: %d, one-row changes: %d" % (tot, upd))
     assert tot > 0 and upd >= 0.99 * tot
+
+
+def test_retry_on_fresh_factorisations_reaches_the_minimiser(host):
+    # the path a QP takes when its acceptance check fails after one-row
+    # changes (forced here): it restarts from its last set with fresh
+    # factorisations only and must still end at the oracle's minimiser
+    b = wl.config(1, 16)
+    ref = oracle.solve_batch(b.counts, b.woff, b.points, b.normals, b.mu, b.wrench, oracle.params())
+    rng = np.random.default_rng(17)
+    retried = 0
+    for g in range(b.n_grasps):
+        s = int(b.woff[g + 1] - b.woff[g])
+        m = int(b.counts[g])
+        y0 = np.where(rng.random((s, 46)) < 0.3, rng.random((s, 46)), 0.0)
+        bad0, c0, x0 = _counts(host, b, g, y0, False)
+        bad1, c1, x1 = _counts(host, b, g, y0, True)
+        assert bad0 == 0 and bad1 == 0
+        fr = ref["forces"][b.woff[g]:b.woff[g + 1], :3 * m]
+        assert np.abs(x1 - fr).max() <= 1e-8, (g, np.abs(x1 - fr).max())
+        used = c0[:, 1] > 0
+        # a retried QP factors afresh at least once more and makes no further one-row changes
+        assert np.all(c1[used, 0] > c0[used, 0]) and np.all(c1[used, 1] == c0[used, 1])
+        assert np.all(c1[~used] == c0[~used])
+        retried += int(used.sum())
+    assert retried > 0
