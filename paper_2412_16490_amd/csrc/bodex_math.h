@@ -1079,7 +1079,8 @@ BODEX_FI double polish_flops(int m, const PolishOut& o) {
 
 // The polish of one QP, as a resumable state machine: polish_begin sets the
 // warm active set, each polish_advance takes one step of the method and
-// returns true once the QP is finished (PS.out.status set: accepted or not).
+// returns true once the QP has reached its acceptance check or failed
+// (PS.out.status set), and polish_finish then runs the check.
 // On finish W.x holds the point, PS.S the active set and PS.lg the
 // normal-sum multiplier (contact_multipliers gives the others).  y0:
 // ADMM-form duals (rows 9i+kk and the normal-sum row 9 MM); rows with
@@ -1275,21 +1276,7 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
     const bool use_gam = D::kGam && Dt.gamma > 0.0 && m > 0;
     const double tol_add = 1e-12 * (1.0 + fm + Dt.gamma);
     const PendingRow none = {-1, -1, {0.0, 0.0, 0.0}, 0.0};
-    if (mode == kAccept) {
-        const bool done = polish_accept<MM>(Dt, W, PS);
-        if ((out.status == 1 || (PS.chg & kChgRetry)) && (PS.chg & kChgUsed)) {
-            // rejected after rank-one changes: once more from this set with
-            // fresh factorisations only (equality solve, multiplier drops,
-            // steps)
-            out.status = 0;
-            PS.chg = kNoChange;
-            refactor = true;
-            phase = kWarm;
-            mode = kEqp0;
-            return false;
-        }
-        return done;
-    }
+    if (mode == kAccept) return true;
     if (refactor) {
         if (++out.steps > max_steps) {
             out.status = 2;
@@ -1340,7 +1327,7 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
         // phase drop the most negative multiplier
         if (phase == kFinal) {
             mode = kAccept;
-            return false;
+            return true;
         }
         if (phase == kWarm) {
             int wbit = -1;
@@ -1388,7 +1375,7 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
         if (p.pk < 0) {
             if (phase != kFinal) {  // x is the minimiser on this set
                 mode = kAccept;
-                return false;
+                return true;
             }
             mode = kEqp0;  // after steps: re-solve exactly
         } else {
@@ -1568,13 +1555,39 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
     return false;
 }
 
-// The whole polish of one QP (see polish_begin / polish_advance).
+// After polish_advance has returned true: the acceptance check of a QP
+// that reached it (others keep their failure status).  Returns false when
+// the QP is to be taken once more: rejected after one-row changes of the
+// factor, it restarts from its last set with fresh factorisations only
+// (equality solve, multiplier drops, steps).
+template <int MM, typename D, class V>
+BODEX_FI bool polish_finish(const D& Dt, const PolishWork<V>& W, PolishState<MM>& PS) {
+    if (PS.mode != kAccept) return true;
+    polish_accept<MM>(Dt, W, PS);
+    if ((PS.out.status == 1 || (PS.chg & kChgRetry)) && (PS.chg & kChgUsed)) {
+        PS.out.status = 0;
+        PS.chg = kNoChange;
+        PS.refactor = true;
+        PS.phase = kWarm;
+        PS.mode = kEqp0;
+        return false;
+    }
+    return true;
+}
+
+// The whole polish of one QP (see polish_begin / polish_advance /
+// polish_finish).  The acceptance check sits after the stepping loop, so
+// the lanes of a wave, which reach it at different times, run it together
+// once instead of once per lane.
 template <int MM, typename YP, typename D, class V>
 BODEX_FI PolishOut polish_qp(const D& Dt, YP y0, int max_steps, const PolishWork<V>& W, PolishState<MM>& PS) {
     polish_begin<MM>(Dt, y0, PS);
 #pragma unroll 1
-    while (!polish_advance<MM>(Dt, max_steps, W, PS)) {
-    }
+    do {
+#pragma unroll 1
+        while (!polish_advance<MM>(Dt, max_steps, W, PS)) {
+        }
+    } while (!polish_finish<MM>(Dt, W, PS));
     return PS.out;
 }
 

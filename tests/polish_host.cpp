@@ -134,8 +134,10 @@ int host_polish_counts(int m, const double* p, const double* n, const double* mu
         PS.S.pc = LaneVec{pcb, 1};
         polish_begin<MM>(D, y0 + 46 * j, PS);
         if (force_retry) PS.chg |= kChgRetry;
-        while (!polish_advance<MM>(D, 200, W, PS)) {
-        }
+        do {
+            while (!polish_advance<MM>(D, 200, W, PS)) {
+            }
+        } while (!polish_finish<MM>(D, W, PS));
         const PolishOut po = PS.out;
         for (int c = 0; c < NV; ++c) x[NV * j + c] = c < 3 * m ? xb[c] : 0.0;
         counts[4 * j] = po.steps;
