@@ -469,32 +469,39 @@ BODEX_FI void contact_rows(unsigned mask, double muc, double fm, ContactRows& R)
     }
 }
 
-// Null-space projector of one contact, Pi v = a v + k (e . v) e with e a
-// unit vector: with n active rows, n = 0: a = 1, k = 0; n = 1: e along the
-// row, a = 1, k = -1; n = 2: e along c0 x c1, a = 0, k = 1; n = 3: a = k = 0.
+// Null-space projector of one contact, Pi v = a v + k (e . v) e: with n
+// active rows, n = 0: a = 1, k = 0; n = 1: e along the row, a = 1,
+// k = -1/|e|^2; n = 2: e along c0 x c1, a = 0, k = 1/|e|^2; n = 3: a = k = 0.
+// e need not be a unit vector (k carries the scale, so building a projector
+// takes one division and no square root).
 struct ContactProj {
     double e[3];
     double k, a;
 };
 
+// Coefficients for a unit e.
 BODEX_FI void proj_coeffs(int n, ContactProj& P) {
     P.k = (n == 1) ? -1.0 : (n == 2 ? 1.0 : 0.0);
     P.a = (n <= 1) ? 1.0 : 0.0;
 }
 
 BODEX_FI void contact_proj(const ContactRows& R, ContactProj& P) {
-    double e[3];
     if (R.n == 2) {
-        cross3(R.c[0], R.c[1], e);
+        cross3(R.c[0], R.c[1], P.e);
     } else {
-        e[0] = R.c[0][0];
-        e[1] = R.c[0][1];
-        e[2] = R.c[0][2];
-    }
-    const double s = (R.n == 1 || R.n == 2) ? 1.0 / sqrt(dot3(e, e)) : 0.0;
 #pragma unroll
-    for (int t = 0; t < 3; ++t) P.e[t] = s * e[t];
-    proj_coeffs(R.n, P);
+        for (int t = 0; t < 3; ++t) P.e[t] = R.c[0][t];
+    }
+    const double q = (R.n == 1 || R.n == 2) ? 1.0 / dot3(P.e, P.e) : 0.0;
+    P.k = (R.n == 1) ? -q : q;
+    P.a = (R.n <= 1) ? 1.0 : 0.0;
+}
+
+// The unit direction of a projector (for the cache, which keeps only e).
+BODEX_FI void proj_unit(const ContactProj& P, double* e) {
+    const double s = P.k != 0.0 ? sqrt(fabs(P.k)) : 1.0;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) e[t] = s * P.e[t];
 }
 
 BODEX_FI void proj_apply(const ContactProj& P, double* v) {
@@ -851,8 +858,10 @@ BODEX_FI bool set_matrix(const D& Dt, ActiveSet<MM>& S) {
         ContactProj P;
         contact_geom(Dt, S, i, R, P);
         if (S.pc.p != nullptr) {
+            double e[3];
+            proj_unit(P, e);
 #pragma unroll
-            for (int t = 0; t < 3; ++t) S.pc[3 * i + t] = P.e[t];
+            for (int t = 0; t < 3; ++t) S.pc[3 * i + t] = e[t];
         }
         double b[6][3];
 #pragma unroll
@@ -917,10 +926,12 @@ BODEX_FI bool matrix_row_change(const D& Dt, ActiveSet<MM>& S, int i, int kk, do
         for (int q = 0; q <= r; ++q) S.L.a[lo_idx(r, q)] += s * v[r] * v[q];
     if (S.pc.p != nullptr) {
         ContactProj P;
+        double e[3];
         contact_rows(now, Dt.muc[i], Dt.fmax, R);
         contact_proj(R, P);
+        proj_unit(P, e);
 #pragma unroll
-        for (int t = 0; t < 3; ++t) S.pc[3 * i + t] = P.e[t];
+        for (int t = 0; t < 3; ++t) S.pc[3 * i + t] = e[t];
     }
     return true;
 }
@@ -1062,7 +1073,7 @@ struct PolishOut {
 //   warm start            249 m per pass, 3 passes  (projector 15 + 9 rows x
 //                         (projection 15, two dots 10, scale 1))
 //   factorisation         231 m + 100  (6 projected G rows, 21 dots, 6x6 Cholesky 97)
-//   one-row change        312          (projector of the other rows 19, projected
+//   one-row change        308          (projector of the other rows 15, projected
 //                         row 20, G_i e 31, L L^T 97, plus s v v^T 48, 6x6 Cholesky 97)
 //   reduced solve H v     108 m + 72   (two projections, G v, G^T w, 6x6 solves 72)
 //   equality solve        527 m + 144  (start point 36 m, two passes of gradient 78 m
@@ -1073,7 +1084,7 @@ struct PolishOut {
 //   acceptance            227 m
 BODEX_FI double polish_flops(int m, const PolishOut& o) {
     const double dm = m;
-    return 3.0 * 249.0 * dm + 227.0 * dm + (o.steps - o.updates) * (231.0 * dm + 100.0) + o.updates * 312.0 +
+    return 3.0 * 249.0 * dm + 227.0 * dm + (o.steps - o.updates) * (231.0 * dm + 100.0) + o.updates * 308.0 +
            o.eqps * (527.0 * dm + 144.0) + o.moves * (377.0 * dm + 77.0) + o.picks * 54.0 * dm;
 }
 
