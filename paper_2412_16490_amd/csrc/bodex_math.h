@@ -542,6 +542,41 @@ BODEX_FI void rows_coeffs(const ContactRows& R, const double* w, double* r) {
     }
 }
 
+// Row coefficients of two vectors in the span of the rows (w -> r, h -> l),
+// sharing the inverse of the rows' Gram (or triple-product) denominator.
+BODEX_FI void rows_coeffs2(const ContactRows& R, const double* w, const double* h, double* r, double* l) {
+    r[0] = r[1] = r[2] = 0.0;
+    l[0] = l[1] = l[2] = 0.0;
+    if (R.n == 1) {
+        const double ia = 1.0 / dot3(R.c[0], R.c[0]);
+        r[0] = dot3(R.c[0], w) * ia;
+        l[0] = dot3(R.c[0], h) * ia;
+    } else if (R.n == 2) {
+        const double a = dot3(R.c[0], R.c[0]), b = dot3(R.c[0], R.c[1]), d = dot3(R.c[1], R.c[1]);
+        const double id = 1.0 / (a * d - b * b);
+        const double p = dot3(R.c[0], w), q = dot3(R.c[1], w);
+        const double ph = dot3(R.c[0], h), qh = dot3(R.c[1], h);
+        r[0] = (d * p - b * q) * id;
+        r[1] = (a * q - b * p) * id;
+        l[0] = (d * ph - b * qh) * id;
+        l[1] = (a * qh - b * ph) * id;
+    } else if (R.n >= 3) {
+        double k[3], t[3];
+        cross3(R.c[1], R.c[2], k);
+        const double iD = 1.0 / dot3(R.c[0], k);
+        r[0] = dot3(w, k) * iD;
+        l[0] = dot3(h, k) * iD;
+        cross3(w, R.c[2], t);
+        r[1] = dot3(R.c[0], t) * iD;
+        cross3(h, R.c[2], t);
+        l[1] = dot3(R.c[0], t) * iD;
+        cross3(R.c[1], w, t);
+        r[2] = dot3(R.c[0], t) * iD;
+        cross3(R.c[1], h, t);
+        l[2] = dot3(R.c[0], t) * iD;
+    }
+}
+
 // Least-norm point of {c_j . f = b_j}.
 BODEX_FI void rows_point(const ContactRows& R, double* f) {
     f[0] = f[1] = f[2] = 0.0;
@@ -972,15 +1007,23 @@ BODEX_FI double sum_row_multiplier(const D& Dt, const ActiveSet<MM>& S, const V&
     return num / den;
 }
 
+// h = -grad_i(x) - up c_p (on the pending row's contact) + lg e_0: the
+// right-hand side whose row coefficients are contact i's multipliers.
 template <int MM, typename D, class V>
-BODEX_FI void contact_multipliers(const D& Dt, const ContactRows& R, const V& x, const double* r6, int i,
-                                  const PendingRow& p, double up, double lg, double* lam) {
-    double h[3];
+BODEX_FI void multiplier_rhs(const D& Dt, const V& x, const double* r6, int i, const PendingRow& p, double up,
+                             double lg, double* h) {
     contact_grad<MM>(Dt, i, r6, x, h);
     const bool on = pending_on(p, i);
 #pragma unroll
     for (int t = 0; t < 3; ++t) h[t] = -h[t] - (on ? up * p.c[t] : 0.0);
     h[0] += lg;
+}
+
+template <int MM, typename D, class V>
+BODEX_FI void contact_multipliers(const D& Dt, const ContactRows& R, const V& x, const double* r6, int i,
+                                  const PendingRow& p, double up, double lg, double* lam) {
+    double h[3];
+    multiplier_rhs<MM>(Dt, x, r6, i, p, up, lg, h);
     rows_coeffs(R, h, lam);
 }
 
@@ -1078,14 +1121,14 @@ struct PolishOut {
 //   reduced solve H v     108 m + 72   (two projections, G v, G^T w, 6x6 solves 72)
 //   equality solve        527 m + 144  (start point 36 m, two passes of gradient 78 m
 //                         + H v + update 3 m, multiplier check 113 m)
-//   one-row step          377 m + 77   (direction 31 m + H v, G z 36 m, ratio test
-//                         83 m and the multipliers at x 113 m, update 6 m)
+//   one-row step          381 m + 78   (direction 31 m + H v, G z 36 m, ratio test
+//                         87 m + 1 and the multipliers at x 113 m, update 6 m)
 //   violated-row search   54 m
 //   acceptance            227 m
 BODEX_FI double polish_flops(int m, const PolishOut& o) {
     const double dm = m;
     return 3.0 * 249.0 * dm + 227.0 * dm + (o.steps - o.updates) * (231.0 * dm + 100.0) + o.updates * 308.0 +
-           o.eqps * (527.0 * dm + 144.0) + o.moves * (377.0 * dm + 77.0) + o.picks * 54.0 * dm;
+           o.eqps * (527.0 * dm + 144.0) + o.moves * (381.0 * dm + 78.0) + o.picks * 54.0 * dm;
 }
 
 // The polish of one QP, as a resumable state machine: polish_begin sets the
@@ -1494,10 +1537,13 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
         }
         rg = num / den;
     }
-    double t1 = INFINITY;
+    // the smallest ratio lam_j / r_j over r_j > 0, kept as a fraction tn / td
+    // (compared by cross-multiplication, one division at the end)
+    double tn = INFINITY, td = 1.0;
     int lbit = -1;
     if (gam && rg > 0.0) {
-        t1 = *lg / rg;
+        tn = *lg;
+        td = rg;
         lbit = 9 * MM;
     }
     double r6x[6];
@@ -1514,16 +1560,19 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
 #pragma unroll
         for (int t = 0; t < 3; ++t) w[t] = (on ? p.c[t] : 0.0) - w[t];
         w[0] += rg;
-        rows_coeffs(R, w, r);
-        contact_multipliers<MM>(Dt, R, W.x, r6x, i, mp, mup, *lg, lam);
+        double h[3];
+        multiplier_rhs<MM>(Dt, W.x, r6x, i, mp, mup, *lg, h);
+        rows_coeffs2(R, w, h, r, lam);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            if (j < R.n && r[j] > 0.0 && lam[j] / r[j] < t1) {
-                t1 = lam[j] / r[j];
+            if (j < R.n && r[j] > 0.0 && lam[j] * td < tn * r[j]) {
+                tn = lam[j];
+                td = r[j];
                 lbit = 9 * i + R.id[j];
             }
         }
     }
+    const double t1 = tn / td;
     const double t2 = (dep || !(cz > 0.0)) ? INFINITY : sp / cz;
     const double st = t2 < t1 ? t2 : t1;
     if (!(st < INFINITY) || !(st >= 0.0)) {
