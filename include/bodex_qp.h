@@ -76,6 +76,8 @@ extern "C" {
 #define BODEX_F_GRAPH 0x10        /* capture launches in a hipGraph and replay */
                                   /* it while the batch shape is unchanged     */
 #define BODEX_F_TIMING 0x20       /* record HIP events around each kernel      */
+#define BODEX_F_SIGNED_DIST 0x40  /* E^c_d with the signed distance d_i (see   */
+                                  /* bodex_qp_pose_gradient)                   */
 
 /* Friction model (bodex_qp_params.friction_cone).
  * PYRAMID8: the 8-facet pyramid inscribed in the cone of Eq. 1, the
@@ -307,10 +309,13 @@ int bodex_qp_contact_query(bodex_qp_t *h, const bodex_hand *in, float *points,
 
 /* Gradient with respect to the hand pose of
  *     L = (the caller's loss through the contacts) + w_dist E^c_d,
- *     E^c_d = sum_i (d_i - radius - offset)^2
- * (the coarse distance energy of Sec. IV-C with the signed distance; radius
- * is the fingertip sphere's radius alpha, offset the pre-grasp distance
- * reduction of Sec. IV-D).  dL_dpoints, dL_dnormals: device [G][m][3], e.g.
+ *     E^c_d = sum_i (|c_i - p_i| - radius - offset)^2
+ * (the coarse distance energy of Sec. IV-C; radius is the fingertip sphere's
+ * radius alpha, offset the pre-grasp distance reduction of Sec. IV-D).  With
+ * BODEX_F_SIGNED_DIST in the handle's flags the signed distance d_i takes
+ * the place of |c_i - p_i|, so that a fingertip inside the object is pushed
+ * out rather than held at distance alpha inside the surface.  On the surface
+ * (d_i = 0) the unsigned form takes the outside branch of its derivative.  dL_dpoints, dL_dnormals: device [G][m][3], e.g.
  * from bodex_qp_backward; either may be NULL (no such term).  The contacts'
  * derivative is the exact Jacobian of the query (implicit function theorem;
  * zero where the nearest point is not unique).  Outputs (each optional):

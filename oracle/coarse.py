@@ -26,10 +26,13 @@ at the origin of the world frame.
   point has p_k = a_k^2 c_k / (a_k^2 - a0^2) off axis 0 and the p_0 >= 0 that
   puts it on the surface.  The centre of a sphere is the extreme case; there
   the query returns p = a0 e_0.
-* Coarse distance energy E^c_d = sum_i (d_i - alpha - delta)^2 (alpha the
-  fingertip sphere's radius, delta the distance reduction of the pre-grasp
-  stage, Sec. IV-D), with the signed distance in place of the unsigned norm
-  |c_{i,w} - p_i| so that a fingertip inside the object is pushed out.
+* Coarse distance energy E^c_d = sum_i (|c_{i,w} - p_i| - alpha - delta)^2
+  (Sec. IV-C; alpha the fingertip sphere's radius, delta the distance
+  reduction of the pre-grasp stage, Sec. IV-D).  Its derivative with respect
+  to c is u^T (I - dp/dc) with u = (c - p) / |c - p| (u = -n, the outward
+  normal, when c lies on the surface).  Option signed=True: the signed
+  distance d_i in place of |c_{i,w} - p_i| (a fingertip inside the object is
+  then pushed out instead of being held at distance alpha inside).
 * The derivative of the query: the paper approximates it by finite
   differences (its object is a mesh); on an analytic surface the exact
   Jacobian follows from the implicit function theorem applied to F(t, c) = 0:
@@ -41,7 +44,8 @@ at the origin of the world frame.
 * Upper-level loss L = w_qp sum_j Q_j + w_dist E^c_d (the QP energy of
   Eq. 3 plus the coarse distance energy; the robot-specific energies are not
   part of this path).  Per fingertip
-      g_i = (dp/dc)^T dL/dp_i + (dn/dc)^T dL/dn_i + w_dist 2 (d_i - alpha - delta) (dd/dc)^T,
+      g_i = (dp/dc)^T dL/dp_i + (dn/dc)^T dL/dn_i + w_dist 2 r_i (dr_i/dc)^T,
+  with r_i = |c_{i,w} - p_i| - alpha - delta (or d_i - alpha - delta),
   dL/dT = sum_i g_i and, for the rotation R(omega) = Exp(omega) R perturbed
   by a world-frame rotation vector, dL/domega = sum_i (R c_{i,l}) x g_i.
 * Descent step: T <- T - eta_T dL/dT, R <- Exp(-eta_R dL/domega) R, with Exp
@@ -186,7 +190,20 @@ def rodrigues(w):
     return np.eye(3) + np.sin(th) / th * K + (1.0 - np.cos(th)) / th ** 2 * (K @ K)
 
 
-def pose_gradient(R, T, cl, axes, dLdp=None, dLdn=None, w_dist=0.0, radius=0.0, offset=0.0, counts=None):
+def dist_term(c, p, n, d, Jp, signed=False):
+    """(distance, its gradient with respect to c) of one fingertip for E^c_d:
+    |c - p| and u^T (I - dp/dc) (the paper's form), or with signed=True the
+    signed distance d and dd/dc = -n."""
+    if signed:
+        return d, -np.asarray(n, np.float64)
+    v = np.asarray(c, np.float64) - np.asarray(p, np.float64)
+    nv = np.linalg.norm(v)
+    u = v / nv if nv > 0.0 else -np.asarray(n, np.float64)
+    return nv, (np.eye(3) - Jp).T @ u
+
+
+def pose_gradient(R, T, cl, axes, dLdp=None, dLdn=None, w_dist=0.0, radius=0.0, offset=0.0, counts=None,
+                  signed=False):
     """(E^c_d [G], dL/domega [G,3], dL/dT [G,3]) for
     L = (the caller's loss through p, n) + w_dist E^c_d."""
     R = np.asarray(R, np.float64)
@@ -200,11 +217,14 @@ def pose_gradient(R, T, cl, axes, dLdp=None, dLdn=None, w_dist=0.0, radius=0.0, 
     dT = np.zeros((G, 3))
     for g in range(G):
         for i in range(int(counts[g])):
-            _, _, d, _ = nearest_point(cw[g, i], ax[g])
+            p, n, d, _ = nearest_point(cw[g, i], ax[g])
             Jp, Jn, Jd = query_jacobian(cw[g, i], ax[g])
-            r = d - radius - offset
+            dist, Jdist = dist_term(cw[g, i], p, n, d, Jp, signed)
+            if not np.any(Jd):  # no derivative of the query here (ridge, centre)
+                Jdist = np.zeros(3)
+            r = dist - radius - offset
             E[g] += r * r
-            gi = 2.0 * w_dist * r * Jd
+            gi = 2.0 * w_dist * r * Jdist
             if dLdp is not None:
                 gi = gi + Jp.T @ np.asarray(dLdp[g, i], np.float64)
             if dLdn is not None:
@@ -233,18 +253,19 @@ def _solve_qps(counts, woff, P, N, mu, wrench, prm, cone):
 
 
 def loss(R, T, cl, axes, counts, woff, mu, wrench, w_qp=1.0, w_dist=0.0, radius=0.0, offset=0.0, prm=None,
-         cone=False):
+         cone=False, signed=False):
     """L per grasp at the pose (R, T), with the pyramid QP oracle (or the
     circular-cone one); also the contacts and the QP solution."""
     P, N, D = contact_query(R, T, cl, axes, counts)
     res = _solve_qps(counts, woff, P, N, mu, wrench, prm, cone)
     live = np.arange(P.shape[1])[None, :] < np.asarray(counts)[:, None]
-    Ec = np.sum(np.where(live, (D - radius - offset) ** 2, 0.0), axis=1)
+    dist = D if signed else np.linalg.norm(hand_points(R, T, cl) - P, axis=2)
+    Ec = np.sum(np.where(live, (dist - radius - offset) ** 2, 0.0), axis=1)
     return w_qp * res["energy"] + w_dist * Ec, P, N, res
 
 
 def descend(R, T, cl, axes, counts, woff, mu, wrench, iters, w_qp=1.0, w_dist=0.0, radius=0.0, offset=0.0,
-            step_rot=0.0, step_trans=0.0, prm=None, cone=False):
+            step_rot=0.0, step_trans=0.0, prm=None, cone=False, signed=False):
     """`iters` upper-level gradient steps; returns the final (R, T) and the
     loss [iters, G] at each pose before its step.  The QP gradient is
     Danskin's (a function of the optimal forces only), so the same chain rule
@@ -253,10 +274,11 @@ def descend(R, T, cl, axes, counts, woff, mu, wrench, iters, w_qp=1.0, w_dist=0.
     T = np.asarray(T, np.float64).copy()
     trace = []
     for _ in range(iters):
-        L, P, N, res = loss(R, T, cl, axes, counts, woff, mu, wrench, w_qp, w_dist, radius, offset, prm, cone)
+        L, P, N, res = loss(R, T, cl, axes, counts, woff, mu, wrench, w_qp, w_dist, radius, offset, prm, cone,
+                            signed)
         trace.append(L)
         G = P.shape[0]
         dP, dN = _qp.grad_batch(counts, woff, P, N, wrench, res["forces"], we=np.full(G, float(w_qp)), prm=prm)
-        _, dw, dT = pose_gradient(R, T, cl, axes, dP, dN, w_dist, radius, offset, counts)
+        _, dw, dT = pose_gradient(R, T, cl, axes, dP, dN, w_dist, radius, offset, counts, signed)
         R, T = descent_step(R, T, dw, dT, step_rot, step_trans)
     return R, T, np.array(trace)

@@ -22,6 +22,7 @@ OK, EINVAL, EHIP, EBUDGET, EINFEAS, EUNSUP, ENODEV = 0, -1, -2, -3, -4, -5, -6
 ST_CONVERGED, ST_MAX_ITER, ST_NONFINITE, ST_FP64_CHOL, ST_POLISH_REJ, ST_POLISHED = (
     0x01, 0x02, 0x04, 0x08, 0x10, 0x20)
 F_WARM_START, F_POLISH, F_ADAPTIVE_RHO, F_BATCHED, F_GRAPH, F_TIMING = 0x01, 0x02, 0x04, 0x08, 0x10, 0x20
+F_SIGNED_DIST = 0x40
 CONE_PYRAMID8, CONE_CIRCULAR = 0, 1
 
 

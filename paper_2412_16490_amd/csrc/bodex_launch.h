@@ -48,6 +48,7 @@ struct HandArgs {
     float *e_dist, *dLdrot, *dLdtrans, *trace;
     float step_rot, step_trans;
     int step, requery;
+    int signed_dist;  // E^c_d with the signed distance d_i instead of |c_i - p_i|
 };
 hipError_t launch_hand_query(const HandArgs& a, hipStream_t st);
 hipError_t launch_hand_step(const HandArgs& a, hipStream_t st);

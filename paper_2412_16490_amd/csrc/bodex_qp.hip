@@ -443,9 +443,10 @@ int validate_hand(bodex_qp* h, const bodex_hand* in) {
     return 0;
 }
 
-bodex::HandArgs hand_args(const bodex_hand* in) {
+bodex::HandArgs hand_args(const bodex_qp* h, const bodex_hand* in) {
     bodex::HandArgs a;
     std::memset(&a, 0, sizeof(a));
+    a.signed_dist = (h->prm.flags & BODEX_F_SIGNED_DIST) ? 1 : 0;
     a.G = in->n_grasps;
     a.M = in->m;
     a.counts = in->contact_count;
@@ -778,7 +779,7 @@ int bodex_qp_contact_query(bodex_qp_t* h, const bodex_hand* in, float* points, f
     if (!aligned4(points) || !aligned4(normals) || !aligned4(dist))
         return fail(h, BODEX_EINVAL, "outputs must be 4-byte aligned");
     HIP_TRY(h, hipSetDevice(h->device));
-    bodex::HandArgs a = hand_args(in);
+    bodex::HandArgs a = hand_args(h, in);
     a.points = points;
     a.normals = normals;
     a.dist = dist;
@@ -800,7 +801,7 @@ int bodex_qp_pose_gradient(bodex_qp_t* h, const bodex_hand* in, const float* dL_
     for (const void* p : all)
         if (!aligned4(p)) return fail(h, BODEX_EINVAL, "arrays must be 4-byte aligned");
     HIP_TRY(h, hipSetDevice(h->device));
-    bodex::HandArgs a = hand_args(in);
+    bodex::HandArgs a = hand_args(h, in);
     a.dLdp = dL_dpoints;
     a.dLdn = dL_dnormals;
     a.w_dist = w_dist;
@@ -906,7 +907,7 @@ int bodex_qp_descend(bodex_qp_t* h, const bodex_hand* hand, const bodex_batch* q
         KArgs ad = a;
         bind_desc(ad, desc, G, S);
         int* d_queue = desc + (n_ints - 4);
-        bodex::HandArgs ha = hand_args(hand);
+        bodex::HandArgs ha = hand_args(h, hand);
         ha.counts = ad.counts;  // the uploaded copy of qp->contact_count
         ha.points = P;
         ha.normals = N;

@@ -5,8 +5,10 @@
 //   c_i   = R c_{i,l} + T                                   fingertip centre
 //   p_i, n_i, d_i = nearest point of the ellipsoid surface sum (x_k/a_k)^2 = 1,
 //                   its inward unit normal and the signed distance (> 0 outside)
-//   E^c_d = sum_i (d_i - alpha - delta)^2                   coarse distance energy
-//   g_i   = (dp/dc)^T dL/dp_i + (dn/dc)^T dL/dn_i + 2 w_dist (d_i - alpha - delta) (dd/dc)^T
+//   E^c_d = sum_i (|c_i - p_i| - alpha - delta)^2           coarse distance energy
+//   g_i   = (dp/dc)^T dL/dp_i + (dn/dc)^T dL/dn_i + 2 w_dist (|d_i| - alpha - delta) sgn(d_i) (dd/dc)^T
+//   (|c_i - p_i| = |d_i|; sgn(0) = +1.  With signed_dist, d_i replaces |d_i|
+//   and sgn is dropped, so that a fingertip inside is pushed out.)
 //   dL/dT = sum_i g_i,   dL/domega = sum_i (R c_{i,l}) x g_i     (R(omega) = Exp(omega) R)
 //   T <- T - eta_T dL/dT,   R <- Exp(-eta_R dL/domega) R        (descent step)
 //
@@ -112,7 +114,9 @@ __global__ __launch_bounds__(kThreads) void hand_step_kernel(HandArgs a) {
         load_axes(a, s.g, ax);
         Near q;
         nearest(c, ax, q);
-        const double r = q.d - double(a.radius) - double(a.offset);
+        // |c - p| = |d| (the paper's form), or the signed distance itself
+        const double sg = (a.signed_dist || q.d >= 0.0) ? 1.0 : -1.0;
+        const double r = sg * q.d - double(a.radius) - double(a.offset);
         double gi[3] = {0.0, 0.0, 0.0};
         if (q.jac) {
             double vp[3], vn[3];
@@ -121,7 +125,7 @@ __global__ __launch_bounds__(kThreads) void hand_step_kernel(HandArgs a) {
             if (a.dLdn)
                 for (int k = 0; k < 3; ++k) vn[k] = a.dLdn[idx * 3 + k];
             chain(c, ax, q, a.dLdp ? vp : nullptr, a.dLdn ? vn : nullptr, gi);
-            for (int k = 0; k < 3; ++k) gi[k] += 2.0 * double(a.w_dist) * r * q.gh[k];
+            for (int k = 0; k < 3; ++k) gi[k] += 2.0 * double(a.w_dist) * r * sg * q.gh[k];
         }
         acc[0] = gi[0];
         acc[1] = gi[1];

@@ -335,7 +335,7 @@ class HandBatch:
 
 
 def hand_batch(seed, n_grasps, m=5, m_choices=None, s=16, shape="ellipsoid", radius=0.01,
-               standoff=(0.005, 0.02), shift=0.005, force_axis=False, mu_range=(0.3, 0.8)):
+               standoff=(0.005, 0.02), shift=0.005, force_axis=False, mu_range=(0.3, 0.8), inside=0.0):
     """Rigid hands placed around analytic objects.  The fingertips sit on a
     thumb-opposes-fingers pattern (the thumb at -y, the fingers spread along
     x at +y, all tilted towards +z) jittered per grasp, at a distance
@@ -343,7 +343,12 @@ def hand_batch(seed, n_grasps, m=5, m_choices=None, s=16, shape="ellipsoid", rad
     fingertip sphere starts outside the object; R is a uniform random
     rotation and T ~ U[-shift, shift]^3.  Objects: ellipsoids with semi-axes
     ~ U[0.02, 0.08] m, spheres with radius ~ U[0.03, 0.06] m, or a 50/50 mix.
-    Wrenches: s random unit directions per grasp, or the six force axes."""
+    Wrenches: s random unit directions per grasp, or the six force axes.
+    inside > 0: that fraction of the fingertips (drawn after everything else,
+    so the rest of the batch is unchanged) moves along its direction to a
+    distance U[0.1, 0.5] min(a) from the hand origin, which with
+    |T_k| <= shift <= 0.005 and min(a) >= 0.02 puts its centre inside the
+    object."""
     rng = np.random.Generator(np.random.PCG64(seed))
     if m_choices is None:
         counts = np.full(n_grasps, m, np.int32)
@@ -383,6 +388,14 @@ def hand_batch(seed, n_grasps, m=5, m_choices=None, s=16, shape="ellipsoid", rad
     else:
         woff = (s * np.arange(n_grasps + 1)).astype(np.int32)
         wrench = wrench_dirs(rng, n_grasps * s)
+    if inside > 0.0:
+        assert shift <= 0.005
+        flag = rng.random((n_grasps, m_max)) < inside
+        depth = rng.uniform(0.1, 0.5, size=(n_grasps, m_max))
+        for g in range(n_grasps):
+            for i in range(int(counts[g])):
+                if flag[g, i]:
+                    tips[g, i] *= depth[g, i] * axes[g].min() / np.linalg.norm(tips[g, i])
     f32 = lambda a: np.ascontiguousarray(a, np.float32)
     return HandBatch(f32(tips), f32(axes), f32(R), f32(T), counts, woff, mu, wrench,
                      "hand-%s-m%s-s%s" % (shape, m if m_choices is None else "".join(map(str, m_choices)),

@@ -103,27 +103,45 @@ def _tip_scales(hb, dLdp, dLdn, w_dist, radius, offset):
         for i in range(int(hb.counts[g])):
             _, _, d, _ = oc.nearest_point(cw[g, i], ax[g])
             Jp, Jn, Jd = oc.query_jacobian(cw[g, i], ax[g])
-            gi = np.abs(Jp.T @ dLdp[g, i]) + np.abs(Jn.T @ dLdn[g, i]) + np.abs(2 * w_dist * (d - radius - offset) * Jd)
+            gi = (np.abs(Jp.T @ dLdp[g, i]) + np.abs(Jn.T @ dLdn[g, i]) +
+                  np.abs(2 * w_dist * (abs(d) + radius + offset) * Jd))
             sT[g] += np.linalg.norm(gi)
             sw[g] += np.linalg.norm(cw[g, i] - T[g]) * np.linalg.norm(gi)
     return sT, sw
 
 
-@pytest.mark.parametrize("shape,mc", [("ellipsoid", None), ("mixed", (4, 5))])
-def test_pose_gradient_parity(solver, shape, mc):
+@pytest.fixture(scope="module")
+def solver_signed():
     import torch
-    hb = wl.hand_batch(21, 300, m_choices=mc, shape=shape)
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    s = api.Solver(api.default_params(m_max=5, s_max=16, flags_set=api.F_SIGNED_DIST))
+    yield s
+    s.close()
+
+
+@pytest.mark.parametrize("shape,mc,inside,signed", [("ellipsoid", None, 0.0, False), ("mixed", (4, 5), 0.0, False),
+                                                   ("ellipsoid", None, 0.4, False), ("mixed", (4, 5), 0.4, False),
+                                                   ("ellipsoid", None, 0.4, True), ("mixed", (4, 5), 0.4, True)])
+def test_pose_gradient_parity(solver, solver_signed, shape, mc, inside, signed):
+    import torch
+    hb = wl.hand_batch(21, 300, m_choices=mc, shape=shape, inside=inside)
+    print("pose gradient: 300 hands %s inside=%.1f signed=%d" % (shape, inside, signed), flush=True)
     rng = np.random.default_rng(3)
     dLdp = rng.standard_normal((hb.n_grasps, hb.m_max, 3)).astype(np.float32)
     dLdn = rng.standard_normal((hb.n_grasps, hb.m_max, 3)).astype(np.float32)
     w_dist, radius, offset = _f32(300.0), _f32(0.01), _f32(0.01)
     dh = api.DeviceHand(hb)
-    g = solver.pose_gradient(dh, torch.as_tensor(dLdp, device="cuda"), torch.as_tensor(dLdn, device="cuda"),
-                             w_dist, radius, offset)
+    sv = solver_signed if signed else solver
+    g = sv.pose_gradient(dh, torch.as_tensor(dLdp, device="cuda"), torch.as_tensor(dLdn, device="cuda"),
+                         w_dist, radius, offset)
     torch.cuda.synchronize()
     R, T, cl, ax = _f64(hb)
+    if inside:
+        _, _, D = oc.contact_query(R, T, cl, ax, hb.counts)
+        assert (D < 0).sum() >= 100
     E, dw, dT = oc.pose_gradient(R, T, cl, ax, dLdp.astype(np.float64), dLdn.astype(np.float64), w_dist, radius,
-                                 offset, hb.counts)
+                                 offset, hb.counts, signed=signed)
     sT, sw = _tip_scales(hb, dLdp.astype(np.float64), dLdn.astype(np.float64), w_dist, radius, offset)
     assert np.all(np.abs(_np(g["e_dist"]) - E) <= 4 * U * E + 1e-15)
     assert np.all(np.abs(_np(g["dL_dtrans"]) - dT).max(axis=1) <= 4 * U * sT + 1e-12)
@@ -141,9 +159,22 @@ def _descend(solver, hb, iters, **kw):
     return dh, res, _np(tr)
 
 
-def _oracle_descend(hb, iters, qps=None):
+def _oracle_descend(hb, iters, qps=None, signed=False):
     R, T, cl, ax = _f64(hb)
-    return oc.descend(R, T, cl, ax, hb.counts, hb.woff, hb.mu, hb.wrench, iters, **DESC)
+    return oc.descend(R, T, cl, ax, hb.counts, hb.woff, hb.mu, hb.wrench, iters, signed=signed, **DESC)
+
+
+@pytest.mark.parametrize("signed", [False, True])
+def test_descend_with_fingertips_inside(solver, solver_signed, signed):
+    # fingertips inside the object: the paper's |c - p| form holds them at
+    # distance alpha inside the surface, the signed form pushes them out
+    hb = wl.hand_batch(34, 48, m=5, s=16, inside=0.4)
+    K = 4
+    print("descend: 48 grasps, 40%% of the fingertips inside, signed=%d, %d steps" % (signed, K), flush=True)
+    dh, res, tr = _descend(solver_signed if signed else solver, hb, K)
+    R1, T1, trace = _oracle_descend(hb, K, signed=signed)
+    assert np.all(np.abs(tr - trace) <= 1e-3 * np.maximum(trace, 1e-2))
+    assert np.all(np.isfinite(_np(dh.rot))) and np.all(np.isfinite(_np(dh.trans)))
 
 
 def test_descend_one_step_matches_oracle(solver):

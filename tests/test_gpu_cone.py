@@ -16,6 +16,8 @@ from oracle import cone as oc
 from paper_2412_16490_amd import api
 from paper_2412_16490_amd import workload as wl
 
+import cone_certificate as cc
+
 pytestmark = pytest.mark.gpu
 
 
@@ -61,7 +63,14 @@ def _check(b, gpu, ref, qps=None, beta=1.0):
 
 
 def _oracle(b, gamma=0.0, beta=1.0, qps=None):
-    return oc.solve_batch(b.counts, b.woff, b.points, b.normals, b.mu, b.wrench, gamma=gamma, beta=beta, qps=qps)
+    """The cone oracle's answers, each certified optimal independently of the
+    barrier method: the projected-gradient fixed point with the closed-form
+    projection holds to 1e-7."""
+    ref = oc.solve_batch(b.counts, b.woff, b.points, b.normals, b.mu, b.wrench, gamma=gamma, beta=beta, qps=qps)
+    qlist = np.arange(b.n_qps) if qps is None else np.asarray(qps)
+    r1, = cc.certify_batch(oracle.grasp_matrix, b, ref["forces"], qlist, beta=beta, gamma=gamma)
+    assert r1 <= 1e-7, r1
+    return ref
 
 
 def test_cone_sphere_m4_s6_full():

@@ -138,42 +138,66 @@ def test_rodrigues_matches_scipy():
         np.testing.assert_allclose(oc.rodrigues(w), Rot.from_rotvec(w).as_matrix(), atol=1e-15)
 
 
-def _loss(hb, R, T, w_dist=200.0, radius=0.01, offset=0.005, cone=False):
+def _loss(hb, R, T, w_dist=200.0, radius=0.01, offset=0.005, cone=False, signed=False):
     L, _, _, _ = oc.loss(R, T, hb.tip_local, hb.semi_axes, hb.counts, hb.woff, hb.mu, hb.wrench,
-                         w_qp=1.0, w_dist=w_dist, radius=radius, offset=offset, cone=cone)
+                         w_qp=1.0, w_dist=w_dist, radius=radius, offset=offset, cone=cone, signed=signed)
     return L
 
 
-def _grad(hb, R, T, w_dist=200.0, radius=0.01, offset=0.005, drop_normals=False, cone=False):
+def _grad(hb, R, T, w_dist=200.0, radius=0.01, offset=0.005, drop_normals=False, cone=False, signed=False):
     L, P, N, res = oc.loss(R, T, hb.tip_local, hb.semi_axes, hb.counts, hb.woff, hb.mu, hb.wrench,
-                           w_qp=1.0, w_dist=w_dist, radius=radius, offset=offset, cone=cone)
+                           w_qp=1.0, w_dist=w_dist, radius=radius, offset=offset, cone=cone, signed=signed)
     dP, dN = oracle.grad_batch(hb.counts, hb.woff, P, N, hb.wrench, res["forces"], we=np.ones(hb.n_grasps))
     _, dw, dT = oc.pose_gradient(R, T, hb.tip_local, hb.semi_axes, dP, None if drop_normals else dN,
-                                 w_dist, radius, offset, hb.counts)
+                                 w_dist, radius, offset, hb.counts, signed=signed)
     return dw, dT
 
 
-def _fd_pose(hb, R, T, h=1e-6, cone=False):
+def _fd_pose(hb, R, T, h=1e-6, cone=False, signed=False):
     G = hb.n_grasps
     dw = np.zeros((G, 3))
     dT = np.zeros((G, 3))
+    kw = dict(cone=cone, signed=signed)
     for k in range(3):
         e = np.zeros(3)
         e[k] = h
         Tp, Tm = T + e, T - e
-        dT[:, k] = (_loss(hb, R, Tp, cone=cone) - _loss(hb, R, Tm, cone=cone)) / (2 * h)
+        dT[:, k] = (_loss(hb, R, Tp, **kw) - _loss(hb, R, Tm, **kw)) / (2 * h)
         Rp = np.stack([oc.rodrigues(e) @ R[g] for g in range(G)])
         Rm = np.stack([oc.rodrigues(-e) @ R[g] for g in range(G)])
-        dw[:, k] = (_loss(hb, Rp, T, cone=cone) - _loss(hb, Rm, T, cone=cone)) / (2 * h)
+        dw[:, k] = (_loss(hb, Rp, T, **kw) - _loss(hb, Rm, T, **kw)) / (2 * h)
     return dw, dT
 
 
-@pytest.mark.parametrize("shape,mc", [("ellipsoid", None), ("sphere", None), ("mixed", (4, 5))])
-def test_pose_gradient_matches_central_differences_through_the_qp(shape, mc):
-    hb = wl.hand_batch(11, 6, m_choices=mc, s=8, shape=shape)
+def test_distance_energy_closed_form_on_a_sphere():
+    # a fingertip at distance rho from the centre of a sphere of radius a:
+    # |c - p| = |a - rho| (Sec. IV-C), signed distance rho - a
+    a, alpha, delta = 0.05, 0.01, 0.002
+    R, T = np.eye(3)[None], np.zeros((1, 3))
+    for rho in (0.012, 0.04, 0.05, 0.07):
+        cl = np.array([[[0.0, rho, 0.0]]])
+        E, _, _ = oc.pose_gradient(R, T, cl, [[a, a, a]], w_dist=1.0, radius=alpha, offset=delta)
+        assert E[0] == pytest.approx((abs(a - rho) - alpha - delta) ** 2, rel=1e-12, abs=1e-18)
+        Es, _, _ = oc.pose_gradient(R, T, cl, [[a, a, a]], w_dist=1.0, radius=alpha, offset=delta, signed=True)
+        assert Es[0] == pytest.approx((rho - a - alpha - delta) ** 2, rel=1e-12, abs=1e-18)
+        # dE/dT along the radius: 2 r d|c-p|/drho with d|c-p|/drho = sign(rho - a)
+        _, _, dT = oc.pose_gradient(R, T, cl, [[a, a, a]], w_dist=1.0, radius=alpha, offset=delta)
+        sg = 1.0 if rho >= a else -1.0
+        assert dT[0, 1] == pytest.approx(2 * (abs(a - rho) - alpha - delta) * sg, rel=1e-10)
+
+
+@pytest.mark.parametrize("shape,mc,inside,signed", [("ellipsoid", None, 0.0, False), ("sphere", None, 0.0, False),
+                                                   ("mixed", (4, 5), 0.0, False),
+                                                   ("ellipsoid", None, 0.4, False), ("mixed", (4, 5), 0.4, False),
+                                                   ("ellipsoid", None, 0.4, True), ("sphere", None, 0.4, True)])
+def test_pose_gradient_matches_central_differences_through_the_qp(shape, mc, inside, signed):
+    hb = wl.hand_batch(11, 6, m_choices=mc, s=8, shape=shape, inside=inside)
     R, T = hb.rot.astype(np.float64), hb.trans.astype(np.float64)
-    dw, dT = _grad(hb, R, T)
-    fw, fT = _fd_pose(hb, R, T)
+    if inside:
+        _, _, D = oc.contact_query(R, T, hb.tip_local, hb.semi_axes, hb.counts)
+        assert (D < 0).sum() >= 3
+    dw, dT = _grad(hb, R, T, signed=signed)
+    fw, fT = _fd_pose(hb, R, T, signed=signed)
     for g in range(hb.n_grasps):
         assert np.linalg.norm(dT[g] - fT[g]) <= 1e-5 * max(np.linalg.norm(fT[g]), 1.0)
         assert np.linalg.norm(dw[g] - fw[g]) <= 1e-5 * max(np.linalg.norm(fw[g]), 1.0)
@@ -189,6 +213,20 @@ def test_pose_gradient_through_the_circular_cone_matches_central_differences():
     for g in range(hb.n_grasps):
         assert np.linalg.norm(dT[g] - fT[g]) <= 1e-5 * max(np.linalg.norm(fT[g]), 1.0)
         assert np.linalg.norm(dw[g] - fw[g]) <= 1e-5 * max(np.linalg.norm(fw[g]), 1.0)
+
+
+def test_the_two_distance_forms_differ_only_inside():
+    for inside in (0.0, 0.4):
+        hb = wl.hand_batch(15, 6, s=4, inside=inside)
+        R, T = hb.rot.astype(np.float64), hb.trans.astype(np.float64)
+        gu = _grad(hb, R, T)
+        gs = _grad(hb, R, T, signed=True)
+        scale = max(np.abs(gs[0]).max(), np.abs(gs[1]).max())
+        diff = max(np.abs(gu[0] - gs[0]).max(), np.abs(gu[1] - gs[1]).max()) / scale
+        if inside:
+            assert diff > 1e-2
+        else:
+            assert diff < 1e-12  # two routes to the same derivative outside
 
 
 def test_dropped_normal_jacobian_fails_the_difference_check():

@@ -25,33 +25,13 @@ import oracle
 from oracle import cone
 from paper_2412_16490_amd import workload as wl
 
+import cone_certificate as cc
+
 EPS = 1e-6
 C8 = np.cos(np.pi / 8)
 
 
-def _closest_on_segment(p, a, b):
-    d = b - a
-    s = np.clip((p - a) @ d / (d @ d), 0.0, 1.0)
-    return a + s * d
-
-
-def _triangle_projection(a, r, mu, fmax):
-    """Closest point to (a, r) in the triangle (0,0), (fmax, 0), (fmax, mu fmax)."""
-    p = np.array([a, r])
-    O, B, V = np.array([0.0, 0.0]), np.array([fmax, 0.0]), np.array([fmax, mu * fmax])
-    inside = r <= mu * a + 1e-300 and a <= fmax and r >= 0
-    if inside:
-        return p
-    cands = [_closest_on_segment(p, O, B), _closest_on_segment(p, B, V), _closest_on_segment(p, O, V)]
-    return min(cands, key=lambda c: np.sum((c - p) ** 2))
-
-
-def _project_contact(f, mu, fmax):
-    rt = np.hypot(f[1], f[2])
-    a2, r2 = _triangle_projection(f[0], rt, mu, fmax)
-    if rt > 0:
-        return np.array([a2, f[1] * r2 / rt, f[2] * r2 / rt])
-    return np.array([a2, 0.0, 0.0])
+_project_contact = cc.project_contact
 
 
 def _frame(n):
@@ -180,6 +160,58 @@ def test_projected_gradient_fixed_point():
         y = f - a * grad
         fp = np.concatenate([_project_contact(y[3 * i:3 * i + 3], mu[i], 1.0) for i in range(m)])
         assert np.abs(fp - f).max() <= 1e-7
+
+
+@pytest.mark.parametrize("gamma,beta", [(0.5, 1.0), (1.0, 0.0), (2.0, 1.0)])
+def test_projected_gradient_fixed_point_with_the_normal_sum_row(gamma, beta):
+    for G, mu, t in _grasps(4):
+        r = cone.solve(G, mu, t, gamma=gamma, beta=beta)
+        assert cc.fixed_point_residual(G, mu, t, r["f"], beta=beta, gamma=gamma) <= 1e-7
+        assert cc.fixed_point_residual(G, mu, t, r["f"], beta=beta, gamma=gamma, step=1e6) <= 1e-5
+
+
+def test_the_certificate_rejects_a_perturbed_point():
+    for G, mu, t in _grasps(2):
+        f = cone.solve(G, mu, t, gamma=0.5)["f"]
+        worst = max(cc.fixed_point_residual(G, mu, t, f + 1e-4 * np.eye(len(f))[k], gamma=0.5) for k in range(len(f)))
+        assert worst > 1e-6
+        # the sum row: dropping it from the certificate is noticed when it binds
+        f2 = cone.solve(G, mu, t, gamma=2.0, beta=0.0)["f"]
+        assert cc.fixed_point_residual(G, mu, t, f2, beta=0.0, gamma=2.0) <= 1e-7
+        assert cc.fixed_point_residual(G, mu, t, f2, beta=0.0, gamma=0.0, step=1e6) > 1e-3
+
+
+def test_unit_step_is_blind_to_internal_forces_and_fista_is_not():
+    # an error along an internal-force direction (G v = 0: only the 2 eps
+    # curvature sees it) passes the unit-step fixed point; the distance to
+    # the accelerated projected-gradient limit sees it
+    for G, mu, t in _grasps(2)[::3]:
+        f = cone.solve(G, mu, t)["f"]
+        v = np.linalg.svd(G)[2][-1]  # a null vector of G (3 m > 6)
+        fb = f + 1e-3 * v
+        if np.all(np.hypot(fb[1::3], fb[2::3]) < mu * fb[0::3]) and np.all(fb[0::3] < 1.0):
+            assert cc.fixed_point_residual(G, mu, t, fb) <= 1e-7
+        assert cc.fixed_point_residual(G, mu, t, fb, step=1e6) > 1e-4
+        assert np.abs(cc.fista(G, mu, t, iters=4000) - fb).max() > 5e-4
+
+
+@pytest.mark.parametrize("w,gamma,beta,iters,tol", [(503, 0.0, 1.0, 10000, 1e-7), (103, 0.0, 1.0, 10000, 1e-7),
+                                                    (285, 0.0, 1.0, 10000, 1e-7), (72, 0.0, 1.0, 60000, 1e-6),
+                                                    (45, 1.0, 1.0, 3000, 1e-7), (117, 1.0, 1.0, 3000, 1e-7)])
+def test_forces_match_the_projected_gradient_limit(w, gamma, beta, iters, tol):
+    # forces pinned by a method that shares nothing with the barrier, on the
+    # QPs of the uneven workload's first 40 grasps whose barrier points sit
+    # closest to a weakly active cone (largest large-step residual), a
+    # force-closure QP (Q* ~ eps |f|^2: the minimiser is fixed only by the
+    # 2 eps curvature, so the first-order method needs longer), and QPs whose
+    # normal-sum row binds
+    b = wl.config(3, 40)
+    g = int(np.searchsorted(b.woff, w, side="right") - 1)
+    m = int(b.counts[g])
+    G = oracle.grasp_matrix(b.points[g, :m].astype(float), b.normals[g, :m].astype(float), 20.0)
+    mu, t = b.mu[g, :m].astype(float), b.wrench[w].astype(float)
+    f = cone.solve(G, mu, t, gamma=gamma, beta=beta)["f"]
+    assert np.abs(f - cc.fista(G, mu, t, beta=beta, gamma=gamma, iters=iters)).max() <= tol
 
 
 def test_weak_duality_lower_bound():
