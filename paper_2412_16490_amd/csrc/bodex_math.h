@@ -1164,7 +1164,8 @@ enum PolishChange {
     kChgJoin = 1 << 9,
     kChgUsed = 1 << 10,
     kChgAllowed = 1 << 11,
-    kChgRetry = 1 << 12  // take the retry below even after an accepted check (tests)
+    kChgRetry = 1 << 12, // take the retry below even after an accepted check (tests)
+    kChgBreak = 1 << 13  // report one breakdown of the ratio test after a one-row change (tests)
 };
 
 // The pending set change in PS.chg: row 9 i + kk, joined or left.
@@ -1184,6 +1185,7 @@ struct PolishState {
     // it joined; flags: such changes were used, they are allowed, a retry
     // is forced
     int chg;
+    int step0;  // factorisations before the current attempt (the retry has its own cap)
     PolishOut out;
 };
 
@@ -1254,6 +1256,7 @@ BODEX_FI void polish_begin(const D& Dt, YP y0, PolishState<MM>& PS) {
     PS.need_mult = false;
     // no rank-one changes with the normal-sum row (its term involves every contact)
     PS.chg = kNoChange | (D::kGam ? 0 : int(kChgAllowed));
+    PS.step0 = 0;
 }
 
 // Acceptance: stationarity, dual and primal feasibility.  Sets the status
@@ -1332,7 +1335,7 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
     const PendingRow none = {-1, -1, {0.0, 0.0, 0.0}, 0.0};
     if (mode == kAccept) return true;
     if (refactor) {
-        if (++out.steps > max_steps) {
+        if (++out.steps - PS.step0 > max_steps) {
             out.status = 2;
             return true;
         }
@@ -1575,7 +1578,8 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
     const double t1 = tn / td;
     const double t2 = (dep || !(cz > 0.0)) ? INFINITY : sp / cz;
     const double st = t2 < t1 ? t2 : t1;
-    if (!(st < INFINITY) || !(st >= 0.0)) {
+    if (!(st < INFINITY) || !(st >= 0.0) || ((PS.chg & kChgBreak) && (PS.chg & kChgUsed))) {
+        PS.chg &= ~int(kChgBreak);
         out.status = 3;  // infeasible or broken down
         return true;
     }
@@ -1617,16 +1621,19 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
 
 // After polish_advance has returned true: the acceptance check of a QP
 // that reached it (others keep their failure status).  Returns false when
-// the QP is to be taken once more: rejected after one-row changes of the
-// factor, it restarts from its last set with fresh factorisations only
-// (equality solve, multiplier drops, steps).
+// the QP is to be taken once more: failed after one-row changes of the
+// factor (rejected by the check, out of steps, or broken down in the ratio
+// test), it restarts from its last set with fresh factorisations only
+// (equality solve, multiplier drops, steps) and a step cap of its own.
 template <int MM, typename D, class V>
 BODEX_FI bool polish_finish(const D& Dt, const PolishWork<V>& W, PolishState<MM>& PS) {
-    if (PS.mode != kAccept) return true;
-    polish_accept<MM>(Dt, W, PS);
-    if ((PS.out.status == 1 || (PS.chg & kChgRetry)) && (PS.chg & kChgUsed)) {
+    const bool reached = PS.mode == kAccept;
+    if (reached) polish_accept<MM>(Dt, W, PS);
+    const bool forced = reached && (PS.chg & kChgRetry);
+    if ((PS.out.status != 0 || forced) && (PS.chg & kChgUsed)) {
         PS.out.status = 0;
         PS.chg = kNoChange;
+        PS.step0 = PS.out.steps;
         PS.refactor = true;
         PS.phase = kWarm;
         PS.mode = kEqp0;

@@ -107,10 +107,13 @@ int host_matrix_change(int m, const double* p, const double* n, const double* mu
 // Solve s QPs of one grasp as host_polish_grasp does (beta = 1, fmax = 1,
 // gamma = 0), also reporting the polish's counts [s][4]: factorisations, of
 // which one-row changes, equality solves, one-row steps; x: [s][15].  With
-// force_retry every QP that used one-row changes is taken once more from its
-// final set on fresh factorisations, as after a failed acceptance check.
+// force_retry = 1 every QP that used one-row changes is taken once more from
+// its final set on fresh factorisations, as after a failed acceptance check;
+// 2: the first ratio test after a one-row change reports a breakdown; 3: the
+// first attempt gets a cap of first_cap factorisations (the retry 200).
 int host_polish_counts(int m, const double* p, const double* n, const double* mu, const double* t, int s,
-                       double kappa, double eps, const float* y0, int force_retry, int* counts, double* x) {
+                       double kappa, double eps, const float* y0, int force_retry, int* counts, double* x,
+                       int first_cap) {
     constexpr int MM = 5, NV = 15;
     double G[6 * NV] = {};
     double muc[MM] = {};
@@ -133,10 +136,13 @@ int host_polish_counts(int m, const double* p, const double* n, const double* mu
         PolishState<MM> PS;
         PS.S.pc = LaneVec{pcb, 1};
         polish_begin<MM>(D, y0 + 46 * j, PS);
-        if (force_retry) PS.chg |= kChgRetry;
+        if (force_retry == 1) PS.chg |= kChgRetry;
+        if (force_retry == 2) PS.chg |= kChgBreak;
+        int cap = force_retry == 3 ? first_cap : 200;
         do {
-            while (!polish_advance<MM>(D, 200, W, PS)) {
+            while (!polish_advance<MM>(D, cap, W, PS)) {
             }
+            cap = 200;
         } while (!polish_finish<MM>(D, W, PS));
         const PolishOut po = PS.out;
         for (int c = 0; c < NV; ++c) x[NV * j + c] = c < 3 * m ? xb[c] : 0.0;

@@ -39,7 +39,10 @@ def _rel(a, b):
 
 
 def test_backward_matches_oracle_gradient():
-    b = wl.config(2, 256)
+    # the differentiation workload at full size: every one of the 8192
+    # grasps' gradients against the oracle's
+    b = wl.config(2)
+    print("backward: 8192 grasps x 5 contacts x 16 wrenches, every grasp", flush=True)
     gp, gn, res = _gpu_grad(b, dE=np.ones(b.n_grasps))
     P0, N0 = b.points.astype(np.float64), b.normals.astype(np.float64)
     ref = oracle.solve_batch(b.counts, b.woff, P0, N0, b.mu, b.wrench)

@@ -157,7 +157,7 @@ def test_one_row_change_pin_fails_with_the_wrong_direction(host):
     assert np.abs((before - np.outer(v, v)) - after).max() <= 1e-12 * np.abs(after).max()
 
 
-def _counts(host, b, g, y0, force_retry):
+def _counts(host, b, g, y0, force_retry, first_cap=200):
     m = int(b.counts[g])
     s = int(b.woff[g + 1] - b.woff[g])
     p, pp = _d(b.points[g, :m])
@@ -170,7 +170,7 @@ def _counts(host, b, g, y0, force_retry):
     bad = host.host_polish_counts(m, pp, pn, pm, pt, s, ctypes.c_double(20.0), ctypes.c_double(1e-6),
                                   y.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), int(force_retry),
                                   cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
-                                  x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                                  x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(first_cap))
     return bad, cnt, x[:, :3 * m]
 
 
@@ -212,4 +212,33 @@ def test_retry_on_fresh_factorisations_reaches_the_minimiser(host):
         assert np.all(c1[used, 0] > c0[used, 0]) and np.all(c1[used, 1] == c0[used, 1])
         assert np.all(c1[~used] == c0[~used])
         retried += int(used.sum())
+    assert retried > 0
+
+
+@pytest.mark.parametrize("mode", ["breakdown", "step cap"])
+def test_retry_after_a_failed_attempt_reaches_the_minimiser(host, mode):
+    # a QP whose attempt with one-row changes ends in a ratio-test breakdown
+    # (forced once) or runs out of steps (a first-attempt cap of 4
+    # factorisations) is taken once more from its last set with fresh
+    # factorisations and a cap of its own, and ends at the oracle's minimiser
+    b = wl.config(1, 16)
+    ref = oracle.solve_batch(b.counts, b.woff, b.points, b.normals, b.mu, b.wrench, oracle.params())
+    rng = np.random.default_rng(19)
+    retried = 0
+    for g in range(b.n_grasps):
+        s = int(b.woff[g + 1] - b.woff[g])
+        m = int(b.counts[g])
+        y0 = np.where(rng.random((s, 46)) < 0.3, rng.random((s, 46)), 0.0)
+        bad0, c0, x0 = _counts(host, b, g, y0, 0)
+        if mode == "breakdown":
+            bad1, c1, x1 = _counts(host, b, g, y0, 2)
+            hit = c0[:, 1] > 0  # QPs that made a one-row change: the forced breakdown hits them
+        else:
+            bad1, c1, x1 = _counts(host, b, g, y0, 3, first_cap=4)
+            hit = (c0[:, 0] > 4) & (c0[:, 1] > 0)
+        assert bad0 == 0 and bad1 == 0
+        fr = ref["forces"][b.woff[g]:b.woff[g + 1], :3 * m]
+        assert np.abs(x1 - fr).max() <= 1e-8, (g, np.abs(x1 - fr).max())
+        assert np.all(c1[~hit] == c0[~hit])
+        retried += int(hit.sum())
     assert retried > 0
