@@ -198,6 +198,27 @@ int bodex_qp_set_stream(bodex_qp_t *h, void *hip_stream);
  * non-finite), EUNSUP, EINFEAS, EBUDGET (workspace above budget), EHIP. */
 int bodex_qp_solve(bodex_qp_t *h, const bodex_batch *in, bodex_result *out);
 
+/* Descriptor ints the allocation-free solve can hold: 3 G + (tiles) + 6
+ * <= 2^20 (a tile holds at least one grasp, so every batch of up to
+ * 262,142 grasps fits). */
+#define BODEX_STATIC_SCRATCH_INTS (1 << 20)
+
+/* bodex_qp_solve without allocation, for callers that cannot allocate
+ * device or pinned host memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same kernels and results as
+ * bodex_qp_solve in the plain form; the batch descriptor (contact counts,
+ * wrench offsets, tile schedule) lives in a static device array of
+ * BODEX_STATIC_SCRATCH_INTS ints (4 MiB per GPU, held until the process
+ * ends; its address is taken per device at bodex_qp_create), staged through
+ * a static pageable host buffer.  The caller passes the state (out->state:
+ * x, z, y, rho all non-NULL; r optional); no library workspace is used.
+ * Every call on one GPU shares that GPU's array and keeps the last call's
+ * contents: calls that overlap on one GPU (other streams, other threads)
+ * race, so serialise them.  Calls no hipMalloc, hipFree or hipHostMalloc.
+ * Errors: EINVAL (as bodex_qp_solve, or a NULL state pointer), EUNSUP
+ * (BODEX_F_BATCHED or BODEX_F_GRAPH set; a batch beyond the scratch), EHIP. */
+int bodex_qp_solve_static(bodex_qp_t *h, const bodex_batch *in, bodex_result *out);
+
 /* Gradient of L = sum_g dL_dE[g] E_g + sum_w dL_dQ[w] Q_w with respect to
  * points and normals (Danskin's theorem: the feasible set does not depend on
  * p or n, so dQ/dG = 2 (G f* - beta t) f*^T, chained through Eq. 2 and the

@@ -121,6 +121,8 @@ def lib():
         L.bodex_qp_set_stream.restype = ctypes.c_int
         L.bodex_qp_solve.argtypes = [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Result)]
         L.bodex_qp_solve.restype = ctypes.c_int
+        L.bodex_qp_solve_static.argtypes = [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(Result)]
+        L.bodex_qp_solve_static.restype = ctypes.c_int
         L.bodex_qp_backward.argtypes = [ctypes.c_void_p, ctypes.POINTER(Batch), ctypes.POINTER(State),
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_int]
@@ -153,7 +155,7 @@ def lib():
 
 
 EXPORTED = ("bodex_qp_default_params", "bodex_qp_create", "bodex_qp_set_stream",
-            "bodex_qp_solve", "bodex_qp_backward", "bodex_qp_destroy",
+            "bodex_qp_solve", "bodex_qp_solve_static", "bodex_qp_backward", "bodex_qp_destroy",
             "bodex_qp_last_error", "bodex_qp_state_bytes", "bodex_qp_last_stats",
             "bodex_qp_kernel_times", "bodex_qp_detach_energy", "bodex_qp_contact_query",
             "bodex_qp_pose_gradient", "bodex_qp_descend")
@@ -286,7 +288,7 @@ def _c_result(result: dict, state: dict | None) -> Result:
     return r
 
 
-def bodex_qp_solve(h, batch: DeviceBatch, result: dict, state: dict | None = None) -> None:
+def _c_result(result: dict, state: dict | None):
     r = Result()
     r.forces = _ptr(result["forces"])
     r.qp_obj = _ptr(result["qp_obj"])
@@ -296,8 +298,21 @@ def bodex_qp_solve(h, batch: DeviceBatch, result: dict, state: dict | None = Non
     r.status = _ptr(result["status"])
     r.state = _c_state(state)
     r.polish_flops = _ptr(result["polish_flops"]) if result.get("polish_flops") is not None else None
+    return r
+
+
+def bodex_qp_solve(h, batch: DeviceBatch, result: dict, state: dict | None = None) -> None:
+    r = _c_result(result, state)
     b = batch.c_batch()
     _check(lib().bodex_qp_solve(h, ctypes.byref(b), ctypes.byref(r)), h)
+
+
+def bodex_qp_solve_static(h, batch: DeviceBatch, result: dict, state: dict) -> None:
+    """The allocation-free solve: descriptor in the library's static device
+    scratch, state from the caller."""
+    r = _c_result(result, state)
+    b = batch.c_batch()
+    _check(lib().bodex_qp_solve_static(h, ctypes.byref(b), ctypes.byref(r)), h)
 
 
 def bodex_qp_backward(h, batch: DeviceBatch, state: dict, dL_dE=None, dL_dQ=None,

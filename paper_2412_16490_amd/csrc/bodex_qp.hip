@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -20,6 +21,13 @@
 #include "bodex_launch.h"
 
 using bodex::KArgs;
+
+// Scratch of the allocation-free solve (bodex_qp_solve_static): the batch
+// descriptor the kernels read (contact counts, wrench offsets, tile order,
+// tile starts, queue counters).  One copy per GPU, held until the process
+// ends.  In host code this name stands for no device address: the device
+// address of each GPU's copy comes from hipGetSymbolAddress (static_scratch).
+static __device__ __align__(256) int scratch[BODEX_STATIC_SCRATCH_INTS];
 
 namespace {
 
@@ -101,6 +109,29 @@ int hip_fail(bodex_qp* h, hipError_t e, const char* what) {
     } while (0)
 
 bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
+
+// Device address of `scratch` on each GPU (taken once per device with that
+// device current), and the pageable host buffer the descriptor is staged in.
+constexpr int kStaticMaxDevices = 64;
+std::mutex g_static_mu;
+int* g_static_dev[kStaticMaxDevices] = {};
+int g_static_host[BODEX_STATIC_SCRATCH_INTS];
+
+// With h->device current: this device's address of `scratch`.
+int static_scratch(bodex_qp* h, int device, int** out) {
+    if (device < 0 || device >= kStaticMaxDevices)
+        return fail(h, BODEX_EUNSUP, "device %d: the static scratch covers devices 0..%d", device,
+                    kStaticMaxDevices - 1);
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_dev[device]) {
+        void* ptr = nullptr;
+        HIP_TRY(h, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(h, BODEX_EHIP, "hipGetSymbolAddress returned NULL for the static scratch");
+        g_static_dev[device] = static_cast<int*>(ptr);
+    }
+    *out = g_static_dev[device];
+    return 0;
+}
 
 // Contact counts the kernels are compiled for.  A batch with m_max contacts
 // per grasp runs on the smallest compiled size >= m_max (array strides stay
@@ -524,6 +555,14 @@ int bodex_qp_create(const bodex_qp_params* p, int device, void* hip_stream, size
         delete h;
         return fail(nullptr, BODEX_EHIP, "hipEventCreate: %s", hipGetErrorString(e));
     }
+    // the static scratch's address on this device (bodex_qp_solve_static)
+    int* sp = nullptr;
+    if (static_scratch(h, device, &sp) != 0) {
+        g_create_error = h->err;
+        (void)hipEventDestroy(h->desc_ev);
+        delete h;
+        return BODEX_EHIP;
+    }
     *out = h;
     return 0;
 }
@@ -666,6 +705,104 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
     if (timing) HIP_TRY(h, hipEventRecord(h->tev[1], h->stream));
     h->t_admm = timing;
     h->last_launches = 1;
+    return 0;
+}
+
+int bodex_qp_solve_static(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
+    if (!h) return BODEX_EINVAL;
+    int rc = validate_batch(h, in);
+    if (rc) return rc;
+    h->last_launches = 0;
+    h->last_replays = 0;
+    h->last_tiles = 0;
+    if (h->prm.flags & (BODEX_F_BATCHED | BODEX_F_GRAPH))
+        return fail(h, BODEX_EUNSUP, "bodex_qp_solve_static runs the plain form only (no BATCHED or GRAPH flag)");
+    const int G = in->n_grasps;
+    if (G == 0) return 0;
+    if (!out->forces || !out->qp_obj || !out->energy || !out->kkt_rel || !out->iters || !out->status)
+        return fail(h, BODEX_EINVAL, "an output pointer is NULL");
+    const bodex_state& st = out->state;
+    if (!(st.x && st.z && st.y && st.rho))
+        return fail(h, BODEX_EINVAL, "bodex_qp_solve_static needs the caller's state (x, z, y, rho)");
+    // the plain schedule (consecutive grasps, at most kWave QPs and
+    // kMaxSlots grasps per tile), built straight into the staging buffer
+    const int* counts = in->contact_count;
+    const int* woff = in->wrench_offset;
+    int n_tiles = 0, slots = 1, cur_q = 0, cur_n = 0;
+    for (int g = 0; g < G; ++g) {
+        const int sg = woff[g + 1] - woff[g];
+        if (cur_n > 0 && (cur_q + sg > bodex::kWave || cur_n >= bodex::kMaxSlots)) {
+            ++n_tiles;
+            slots = std::max(slots, cur_n);
+            cur_q = cur_n = 0;
+        }
+        cur_q += sg;
+        ++cur_n;
+    }
+    ++n_tiles;
+    slots = std::max(slots, cur_n);
+    const size_t n_ints = size_t(G) * 3 + 1 + size_t(n_tiles) + 1 + 4;
+    if (n_ints > size_t(BODEX_STATIC_SCRATCH_INTS))
+        return fail(h, BODEX_EUNSUP,
+                    "batch needs %zu descriptor ints, beyond the static scratch of %d (every batch of up to %d "
+                    "grasps fits)", n_ints, BODEX_STATIC_SCRATCH_INTS, (BODEX_STATIC_SCRATCH_INTS - 6) / 4);
+    HIP_TRY(h, hipSetDevice(h->device));
+    int* d = nullptr;
+    rc = static_scratch(h, h->device, &d);
+    if (rc) return rc;
+
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    int* p = g_static_host;
+    std::memcpy(p, counts, sizeof(int) * G);
+    std::memcpy(p + G, woff, sizeof(int) * (G + 1));
+    int* perm = p + 2 * G + 1;
+    int* ts = p + 3 * G + 1;
+    for (int g = 0; g < G; ++g) perm[g] = g;
+    int t = 0;
+    ts[0] = 0;
+    cur_q = cur_n = 0;
+    for (int g = 0; g < G; ++g) {
+        const int sg = woff[g + 1] - woff[g];
+        if (cur_n > 0 && (cur_q + sg > bodex::kWave || cur_n >= bodex::kMaxSlots)) {
+            ts[++t] = g;
+            cur_q = cur_n = 0;
+        }
+        cur_q += sg;
+        ++cur_n;
+    }
+    ts[n_tiles] = G;
+    std::memset(ts + n_tiles + 1, 0, sizeof(int) * 4);
+    // pageable source: the copy has consumed the staging buffer when it returns
+    HIP_TRY(h, hipMemcpyAsync(d, p, n_ints * sizeof(int), hipMemcpyHostToDevice, h->stream));
+
+    const int mm = kernel_mm(h->prm.m_max);
+    const bool cone = h->prm.friction_cone == BODEX_CONE_CIRCULAR;
+    KArgs a = make_args(h, in);
+    a.x = st.x;
+    a.z = st.z;
+    a.y = st.y;
+    a.rho = st.rho;
+    a.resid = st.r;
+    a.forces = out->forces;
+    a.qobj = out->qp_obj;
+    a.energy = out->energy;
+    a.kkt = out->kkt_rel;
+    a.iters = out->iters;
+    a.status = out->status;
+    a.pflops = out->polish_flops;
+    a.counts = d;
+    a.woff = d + G;
+    a.perm = d + 2 * G + 1;
+    a.tile_start = d + 3 * G + 1;
+    a.n_tiles = n_tiles;
+    a.slots = slots;
+    a.queue = nullptr;
+    const size_t lds_a = admm_lds(mm, slots);
+    const size_t lds_f = cone ? bodex::cone_fin_lds(mm, slots, h->prm.gamma > 0.f) : fin_lds(mm, slots, false);
+    HIP_TRY(h, launch(Kind::Admm, mm, a, n_tiles, lds_a, h->stream, h->prm.admm_waves));
+    HIP_TRY(h, launch(Kind::Fin, mm, a, n_tiles, lds_f, h->stream));
+    h->last_launches = 2;
+    h->last_tiles = n_tiles;
     return 0;
 }
 
