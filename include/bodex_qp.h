@@ -112,7 +112,13 @@ typedef struct {
     float rho_hysteresis; /* refactor only when rho changes by this factor    */
     float fp64_cond;      /* factor K in FP64 when cond estimate exceeds this */
     int polish_steps;     /* cap on active-set corrections in the polish      */
-    int iters_per_chunk;  /* batched form: iterations between queue checks    */
+    int polish_chunk;     /* factorisations a QP takes in the one-lane FP64   */
+                          /* polish before it is handed to the contact-       */
+                          /* parallel polish (a group of lanes, one per       */
+                          /* contact); 0 = every polish ends in the one-lane  */
+                          /* kernel; -1 = chosen by the number of QPs (1 up   */
+                          /* to 40,960, 12 up to 98,304, else 20).  Used with */
+                          /* BODEX_F_POLISH, the pyramid and gamma = 0.       */
     unsigned flags;       /* BODEX_F_*                                        */
     int admm_waves;       /* ADMM kernel register budget as resident waves   */
                           /* per SIMD: 1, 2, 3 or 4 (0 = library default)     */
@@ -174,7 +180,7 @@ typedef struct bodex_qp bodex_qp_t;
 /* Fill *p with the defaults: m_max 5, s_max 32, fmax 1, gamma 0, beta 1,
  * eps 1e-6, torque_scale 20, tol 1e-5, 500 iterations, rho0 0.3, alpha 1.6,
  * check every 10, rho in [1e-4, 1e4], hysteresis 5, fp64_cond 1e4, 128 polish
- * steps, 20 iterations per chunk, flags POLISH | ADAPTIVE_RHO, admm_waves 0,
+ * steps, polish_chunk -1, flags POLISH | ADAPTIVE_RHO, admm_waves 0,
  * admm_tol 0 (the model's default; with the polish on, ADMM only has to find the active set
  * roughly; the polish then solves each QP exactly). */
 void bodex_qp_default_params(bodex_qp_params *p);
@@ -205,8 +211,10 @@ int bodex_qp_solve(bodex_qp_t *h, const bodex_batch *in, bodex_result *out);
 
 /* bodex_qp_solve without allocation, for callers that cannot allocate
  * device or pinned host memory (code under HIP graph capture, tight serving
- * loops, harnesses that forbid hipMalloc).  Same kernels and results as
- * bodex_qp_solve in the plain form; the batch descriptor (contact counts,
+ * loops, harnesses that forbid hipMalloc).  The plain form's kernels with
+ * the one-lane FP64 polish run to the end (polish_chunk is not used: the
+ * contact-parallel polish needs workspace), so the results equal
+ * bodex_qp_solve's with polish_chunk 0; the batch descriptor (contact counts,
  * wrench offsets, tile schedule) lives in a static device array of
  * BODEX_STATIC_SCRATCH_INTS ints (4 MiB per GPU, held until the process
  * ends; its address is taken per device at bodex_qp_create), staged through

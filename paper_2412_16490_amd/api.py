@@ -42,7 +42,7 @@ class Params(ctypes.Structure):
         ("alpha", ctypes.c_float), ("check_every", ctypes.c_int),
         ("rho_min", ctypes.c_float), ("rho_max", ctypes.c_float),
         ("rho_hysteresis", ctypes.c_float), ("fp64_cond", ctypes.c_float),
-        ("polish_steps", ctypes.c_int), ("iters_per_chunk", ctypes.c_int),
+        ("polish_steps", ctypes.c_int), ("polish_chunk", ctypes.c_int),
         ("flags", ctypes.c_uint), ("admm_waves", ctypes.c_int),
         ("admm_tol", ctypes.c_float), ("friction_cone", ctypes.c_int),
     ]

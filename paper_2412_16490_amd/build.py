@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 UNITS = ["bodex_qp.hip", "k_admm.hip", "k_finalize.hip", "k_finalize_sum.hip", "k_backward.hip",
          "k_backward_sum.hip", "k_detach.hip", "k_admm_cone.hip", "k_finalize_cone.hip",
-         "k_backward_cone.hip", "k_hand.hip"]
+         "k_backward_cone.hip", "k_hand.hip", "k_gpolish.hip", "k_finalize_chunk.hip"]
 LIB = os.path.join(HERE, "libbodex_qp.so")
 OBJDIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

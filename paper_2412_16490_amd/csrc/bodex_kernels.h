@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include "bodex_cone.h"
+#include "bodex_gpolish.h"
 #include "bodex_math.h"
 
 namespace bodex {
@@ -79,6 +80,15 @@ struct KArgs {
     float kappa, beta, eps, fmax, gamma, tol, admm_tol, rho0, alpha, rho_min, rho_max, hyst, fp64_cond;
     int max_iters, check_every, warm, adaptive, polish, polish_steps;
     int cone;  // 1: exact circular cone (state rows 3 m + 1), 0: 8-facet pyramid
+    // chunked polish (finalize_kernel): fin_mode 0 runs every polish to the
+    // end; 1 suspends a polish after polish_budget factorisations and hands it
+    // to the contact-parallel polish through the spill records (spill_idx[w]:
+    // the record of QP w, -1 for none; spill_count: records taken); 2 forms
+    // the outputs of the QPs whose records that polish finished
+    int fin_mode, polish_budget;
+    SpillPtrs spill;
+    int* spill_count;
+    int* spill_idx;
 };
 
 struct SlotInfo {
@@ -699,13 +709,18 @@ __device__ inline LdsPolishData<MM, GAM> polish_data(const KArgs& a, const FinPt
 #define BODEX_FIN_WAVES 2
 #endif
 
-template <int MM, bool GAM>
+template <int MM, bool GAM, int MODE>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BODEX_FIN_WAVES))) finalize_kernel(const KArgs a) {
     constexpr int NG = 6 * 3 * MM;
     extern __shared__ __align__(16) unsigned char smem[];
     const FinPtrs<MM> P = fin_carve<MM>(smem, a.slots, false);
     const int lane = threadIdx.x;
     const PolishWork<LaneVec> W = polish_work<MM>(P, lane);
+    // chunked polish (gamma = 0 only; MODE is KArgs::fin_mode): 1 = hand
+    // unfinished polishes on, 2 = outputs of the QPs the contact-parallel
+    // polish finished
+    static_assert(MODE == 0 || !GAM, "the chunked polish has no normal-sum row");
+    constexpr int mode = MODE;
     __shared__ int sTile;
     for (int t = fetch_tile(a, &sTile, -1); t < a.n_tiles; t = fetch_tile(a, &sTile, t)) {
         int nsl;
@@ -715,9 +730,13 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BODEX_F
         const bool act = slot >= 0;
         SlotInfo si = {0, 0, 1, 0};
         if (act) si = P.info[slot];
-        const bool good = fin_setup<MM>(a, P, nsl, slot, j, si);
         const int w = si.w0 + j;
+        // this lane's spill record (-1: none)
+        int kspill = (act && mode == 2) ? a.spill_idx[w] : -1;
+        if (mode == 2 && !__syncthreads_or(kspill >= 0)) continue;  // nothing handed on in this tile
+        const bool good = fin_setup<MM>(a, P, nsl, slot, j, si);
         double Q = 0.0;
+        bool skip = false;  // no outputs from this lane in this pass
         if (act) {
             const double* Gs = P.G + size_t(slot) * NG;
             const double* muc = P.muc + slot * 8;
@@ -728,119 +747,230 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BODEX_F
             unsigned char st = a.status[w];
             bool polished = false;
             const bool finite_in = good && !(st & kStNonfinite);
-            if (finite_in && a.polish) {
-                const LdsPolishData<MM, GAM> D = polish_data<MM, GAM>(a, P, slot, si, bt);
+            const LdsPolishData<MM, GAM> D = polish_data<MM, GAM>(a, P, slot, si, bt);
+            // the polish's result: point in W.x, active set, normal-sum multiplier, counts
+            ActiveSet<MM> S;
+            S.pc = projector_cache<MM>(P, lane);
+            double lg = 0.0;
+            PolishOut po;
+            bool ran = false;
+            if constexpr (mode == 2) {
+                skip = kspill < 0;
+                if (!skip) {
+                    // the finished polish from the record
+#pragma unroll 1
+                    for (int c = 0; c < 3 * si.m; ++c) W.x[c] = a.spill.dv(c, kspill);
+                    unsigned mw[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) mw[q] = unsigned(a.spill.iv(kSpMask0 + q, kspill));
+                    S.mask = mask_from_words<RowMask<MM>>(mw);
+                    S.gam = false;
+                    po.status = a.spill.iv(kSpStatus, kspill);
+                    po.steps = a.spill.iv(kSpSteps, kspill);
+                    po.updates = a.spill.iv(kSpUpdates, kspill);
+                    po.eqps = a.spill.iv(kSpEqps, kspill);
+                    po.moves = a.spill.iv(kSpMoves, kspill);
+                    po.picks = a.spill.iv(kSpPicks, kspill);
+                    ran = true;
+                }
+            } else if (finite_in && a.polish) {
                 PolishState<MM> PS;
-                PS.S.pc = projector_cache<MM>(P, lane);
+                PS.S.pc = S.pc;
                 const StridedY<MM> y0{a.y + w, W_, a.ms};
-                const PolishOut po = polish_qp<MM>(D, y0, a.polish_steps, W, PS);
-                const ActiveSet<MM>& S = PS.S;
-                const double lg = PS.lg;
-                if (a.pflops) a.pflops[w] = float(polish_flops(si.m, po));
-                if (po.status == 0) {
-                    polished = true;
-                    st |= kStPolished;
-                    st &= ~kStPolishRej;
-                    // ADMM-form state of the polished point: z = A x projected
-                    // on [l, u] (the bound itself on active rows), y = the
-                    // multipliers of the active rows
-                    double s1 = 0.0, r6[6];
-                    g_times<MM>(D, W.x, true, r6);
-                    const PendingRow none = {-1, -1, {0.0, 0.0, 0.0}, 0.0};
-#pragma unroll 1
-                    for (int i = 0; i < a.ms; ++i) {
-                        const bool live = i < si.m;
-                        const double f[3] = {live ? W.x[3 * i] : 0.0, live ? W.x[3 * i + 1] : 0.0,
-                                             live ? W.x[3 * i + 2] : 0.0};
-                        const unsigned mk = live ? contact_mask(S.mask, i) : 0u;
-                        double lam[3] = {0.0, 0.0, 0.0};
-                        if (live) {
-                            ContactRows R;
-                            contact_rows(mk, muc[i], D.fmax, R);
-                            contact_multipliers<MM>(D, R, W.x, r6, i, none, 0.0, lg, lam);
-                        }
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) a.x[size_t(3 * i + c) * W_ + w] = float(f[c]);
-#pragma unroll
-                        for (int kk = 0; kk < 9; ++kk) {
-                            const double zz = (kk < 8) ? facet_cos<double>(kk) * f[1] + facet_sin<double>(kk) * f[2] -
-                                                             muc[i] * f[0]
-                                                       : f[0];
-                            const bool on = (mk >> kk) & 1u;
-                            const int jr = __builtin_popcount(mk & ((1u << kk) - 1u));
-                            const float zv = on ? (kk == 8 ? a.fmax : 0.f)
-                                                : row_proj(9 * i + kk, MM, float(zz), a.fmax, a.gamma);
-                            const float yv = on ? float(jr == 0 ? lam[0] : (jr == 1 ? lam[1] : lam[2])) : 0.f;
-                            a.z[size_t(9 * i + kk) * W_ + w] = zv;
-                            a.y[size_t(9 * i + kk) * W_ + w] = yv;
-                        }
-                        s1 += f[0];
-                    }
-                    const bool gam = GAM && S.gam;
-                    a.z[size_t(9 * a.ms) * W_ + w] = gam ? a.gamma : fmaxf(float(s1), a.gamma);
-                    a.y[size_t(9 * a.ms) * W_ + w] = gam ? float(-lg) : 0.f;
+                if constexpr (mode == 0) {
+                    polish_qp<MM>(D, y0, a.polish_steps, W, PS);
                 } else {
-                    st |= kStPolishRej;
-                    st &= ~kStPolished;
-                }
-            }
-            // objective and forces from the returned point (FP64: the polished
-            // point, else the ADMM iterate)
-            auto xval = [&](int c) -> double {
-                return polished ? (c < 3 * si.m ? W.x[c] : 0.0) : double(a.x[size_t(c) * W_ + w]);
-            };
-            double r6[6];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) r6[k] = -bt[k];
-            double ff = 0.0;
+                    polish_begin<MM>(D, y0, PS);
+                    PS.budget = a.polish_budget;
 #pragma unroll 1
-            for (int c = 0; c < 3 * a.ms; ++c) {
-                const double xc = xval(c);
-                if (c < 3 * si.m) {
-#pragma unroll
-                    for (int k = 0; k < 6; ++k) r6[k] += Gs[k * 3 * MM + c] * xc;
+                    for (;;) {
+#pragma unroll 1
+                        do {
+#pragma unroll 1
+                            while (!polish_advance<MM, LdsPolishData<MM, GAM>, LaneVec, true>(D, a.polish_steps, W,
+                                                                                              PS)) {
+                            }
+                        } while (!polish_finish<MM>(D, W, PS));
+                        if (PS.out.status != kPolishSuspended) break;
+                        // hand it on if a record is free, else finish it here
+                        const int k = atomicAdd(a.spill_count, 1);
+                        if (k < a.spill.K) {
+                            polish_save<MM>(PS, W.x, si.m, a.spill, k, w, si.g);
+                            kspill = k;
+                            break;
+                        }
+                        PS.out.status = 0;
+                        PS.budget = 0x7fffffff;
+                    }
                 }
-                ff += xc * xc;
-                a.forces[size_t(w) * 3 * a.ms + c] = finite_in ? float(xc) : NAN;
+                skip = kspill >= 0;
+                ran = !skip;
+                S.mask = PS.S.mask;
+                S.gam = PS.S.gam;
+                lg = PS.lg;
+                po = PS.out;
             }
-            double rr2 = 0.0;
+            if (mode == 1) a.spill_idx[w] = kspill;
+            if (!skip) {
+                if (ran) {
+                    if (a.pflops) a.pflops[w] = float(polish_flops(si.m, po));
+                    if (po.status == 0) {
+                        polished = true;
+                        st |= kStPolished;
+                        st &= ~kStPolishRej;
+                        // ADMM-form state of the polished point: z = A x projected
+                        // on [l, u] (the bound itself on active rows), y = the
+                        // multipliers of the active rows
+                        double s1 = 0.0, r6[6];
+                        g_times<MM>(D, W.x, true, r6);
+                        const PendingRow none = {-1, -1, {0.0, 0.0, 0.0}, 0.0};
+#pragma unroll 1
+                        for (int i = 0; i < a.ms; ++i) {
+                            const bool live = i < si.m;
+                            const double f[3] = {live ? W.x[3 * i] : 0.0, live ? W.x[3 * i + 1] : 0.0,
+                                                 live ? W.x[3 * i + 2] : 0.0};
+                            const unsigned mk = live ? contact_mask(S.mask, i) : 0u;
+                            double lam[3] = {0.0, 0.0, 0.0};
+                            if (live) {
+                                ContactRows R;
+                                contact_rows(mk, muc[i], D.fmax, R);
+                                contact_multipliers<MM>(D, R, W.x, r6, i, none, 0.0, lg, lam);
+                            }
 #pragma unroll
-            for (int k = 0; k < 6; ++k) rr2 += r6[k] * r6[k];
-            Q = rr2 + double(a.eps) * ff;
-            if (a.resid) {
+                            for (int c = 0; c < 3; ++c) a.x[size_t(3 * i + c) * W_ + w] = float(f[c]);
 #pragma unroll
-                for (int k = 0; k < 6; ++k) a.resid[size_t(k) * W_ + w] = finite_in ? float(r6[k]) : NAN;
+                            for (int kk = 0; kk < 9; ++kk) {
+                                const double zz = (kk < 8) ? facet_cos<double>(kk) * f[1] +
+                                                                 facet_sin<double>(kk) * f[2] - muc[i] * f[0]
+                                                           : f[0];
+                                const bool on = (mk >> kk) & 1u;
+                                const int jr = __builtin_popcount(mk & ((1u << kk) - 1u));
+                                const float zv = on ? (kk == 8 ? a.fmax : 0.f)
+                                                    : row_proj(9 * i + kk, MM, float(zz), a.fmax, a.gamma);
+                                const float yv = on ? float(jr == 0 ? lam[0] : (jr == 1 ? lam[1] : lam[2])) : 0.f;
+                                a.z[size_t(9 * i + kk) * W_ + w] = zv;
+                                a.y[size_t(9 * i + kk) * W_ + w] = yv;
+                            }
+                            s1 += f[0];
+                        }
+                        const bool gam = GAM && S.gam;
+                        a.z[size_t(9 * a.ms) * W_ + w] = gam ? a.gamma : fmaxf(float(s1), a.gamma);
+                        a.y[size_t(9 * a.ms) * W_ + w] = gam ? float(-lg) : 0.f;
+                    } else {
+                        st |= kStPolishRej;
+                        st &= ~kStPolished;
+                    }
+                }
+                // objective and forces from the returned point (FP64: the polished
+                // point, else the ADMM iterate)
+                auto xval = [&](int c) -> double {
+                    return polished ? (c < 3 * si.m ? W.x[c] : 0.0) : double(a.x[size_t(c) * W_ + w]);
+                };
+                double r6[6];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) r6[k] = -bt[k];
+                double ff = 0.0;
+#pragma unroll 1
+                for (int c = 0; c < 3 * a.ms; ++c) {
+                    const double xc = xval(c);
+                    if (c < 3 * si.m) {
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) r6[k] += Gs[k * 3 * MM + c] * xc;
+                    }
+                    ff += xc * xc;
+                    a.forces[size_t(w) * 3 * a.ms + c] = finite_in ? float(xc) : NAN;
+                }
+                double rr2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) rr2 += r6[k] * r6[k];
+                Q = rr2 + double(a.eps) * ff;
+                if (a.resid) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) a.resid[size_t(k) * W_ + w] = finite_in ? float(r6[k]) : NAN;
+                }
+                double rel = NAN;
+                if (finite_in) {
+                    const float* xs = a.x + w;
+                    const float* zs = a.z + w;
+                    const float* ys = a.y + w;
+                    rel = rel_kkt64<MM>(
+                        Gs, muc, bt, si.m, double(a.eps), [&](int c) { return double(xs[size_t(c) * W_]); },
+                        [&](int r) { return double(zs[size_t(r) * W_]); },
+                        [&](int r) { return double(ys[size_t(r) * W_]); }, double(zs[size_t(9 * a.ms) * W_]),
+                        double(ys[size_t(9 * a.ms) * W_]));
+                }
+                if (rel <= double(a.tol))
+                    st |= kStConverged;
+                else
+                    st &= ~kStConverged;
+                if (!finite_in) {
+                    st |= kStNonfinite;
+                    Q = NAN;
+                }
+                a.status[w] = st;
+                a.kkt[w] = float(rel);
+                a.qobj[w] = float(Q);
+            } else if (mode == 2) {
+                Q = double(a.qobj[w]);  // finished in the first pass
             }
-            double rel = NAN;
-            if (finite_in) {
-                const float* xs = a.x + w;
-                const float* zs = a.z + w;
-                const float* ys = a.y + w;
-                rel = rel_kkt64<MM>(
-                    Gs, muc, bt, si.m, double(a.eps), [&](int c) { return double(xs[size_t(c) * W_]); },
-                    [&](int r) { return double(zs[size_t(r) * W_]); }, [&](int r) { return double(ys[size_t(r) * W_]); },
-                    double(zs[size_t(9 * a.ms) * W_]), double(ys[size_t(9 * a.ms) * W_]));
-            }
-            if (rel <= double(a.tol))
-                st |= kStConverged;
-            else
-                st &= ~kStConverged;
-            if (!finite_in) {
-                st |= kStNonfinite;
-                Q = NAN;
-            }
-            a.status[w] = st;
-            a.kkt[w] = float(rel);
-            a.qobj[w] = float(Q);
+            if (kspill >= 0) atomicOr(&P.flag[slot], 8);
         }
         P.red[lane] = Q;
         __syncthreads();
-        if (act && j == 0) {
+        // energies: in the first pass of grasps with nothing handed on, in
+        // the second of the others
+        const bool handed = act && (P.flag[slot] & 8);
+        if (act && j == 0 && (mode == 0 || (mode == 1 && !handed) || (mode == 2 && handed))) {
             double E = 0.0;
             for (int l = lane; l < lane + si.s; ++l) E += P.red[l];
             a.energy[si.g] = float(E);
         }
         __syncthreads();
+    }
+}
+
+// Contact-parallel polish of the handed-on QPs (see bodex_gpolish.h): a
+// group of GS lanes per record, one lane per contact; all groups of the
+// grid stride over the records taken by the first pass.
+#ifndef BODEX_GPOLISH_WAVES
+#define BODEX_GPOLISH_WAVES 1
+#endif
+template <int MM, int GS>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BODEX_GPOLISH_WAVES))) gpolish_kernel(const KArgs a) {
+    constexpr int GPW = kWave / GS;
+    const int lane = threadIdx.x, sub = lane % GS, grp = lane / GS;
+    const int count = min(*a.spill_count, a.spill.K);
+    const ShflTeam<GS> team{sub};
+    for (int base = int(blockIdx.x) * GPW; base < count; base += int(gridDim.x) * GPW) {
+        const int k = base + grp;
+        if (k < count) {
+            const int w = a.spill.iv(kSpW, k), g = a.spill.iv(kSpG, k);
+            const int m = a.counts[g];
+            double p3[3] = {0.0, 0.0, 0.0}, n3[3] = {0.0, 0.0, 1.0}, mu = 0.5;
+            if (sub < m) {
+                const size_t base3 = (size_t(g) * a.ms + sub) * 3;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    p3[q] = a.points[base3 + q];
+                    n3[q] = a.normals[base3 + q];
+                }
+                mu = a.mu[size_t(g) * a.ms + sub];
+            }
+            double bt[6];
+#pragma unroll
+            for (int r = 0; r < 6; ++r) bt[r] = double(a.beta) * double(a.wrench[size_t(w) * 6 + r]);
+            GQP<MM> Q;
+            Q.sub = sub;
+            gpolish_load<MM>(team, Q, a.spill, k, m, p3, n3, mu, double(a.kappa), bt, double(a.fmax),
+                             double(a.eps));
+#pragma unroll 1
+            do {
+#pragma unroll 1
+                while (!gpolish_advance<MM>(team, Q, a.polish_steps)) {
+                }
+            } while (!gpolish_finish<MM>(team, Q));
+            gpolish_store<MM>(team, Q, a.spill, k);
+        }
     }
 }
 

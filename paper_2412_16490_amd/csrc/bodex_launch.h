@@ -10,6 +10,10 @@ hipError_t launch_admm(int mm, int occ, const KArgs& a, int grid, size_t lds, hi
 hipError_t launch_finalize(int mm, const KArgs& a, int grid, size_t lds, hipStream_t st);
 hipError_t launch_backward(int mm, const KArgs& a, int grid, size_t lds, hipStream_t st);
 hipError_t launch_reset(int* q, int n, hipStream_t st);
+// Contact-parallel polish of the records the first finalize pass handed on
+// (KArgs::spill); group size (lanes per QP) for a kernel size.
+hipError_t launch_gpolish(int mm, const KArgs& a, int grid, hipStream_t st);
+int gpolish_group(int mm);
 // Circular-cone form (KArgs::cone set).
 hipError_t launch_admm_cone(int mm, int occ, const KArgs& a, int grid, size_t lds, hipStream_t st);
 hipError_t launch_finalize_cone(int mm, const KArgs& a, int grid, size_t lds, hipStream_t st);

@@ -1185,9 +1185,14 @@ struct PolishState {
     // it joined; flags: such changes were used, they are allowed, a retry
     // is forced
     int chg;
-    int step0;  // factorisations before the current attempt (the retry has its own cap)
+    int step0;   // factorisations before the current attempt (the retry has its own cap)
+    int budget;  // factorisations after which the polish suspends (status 4) before the next one
     PolishOut out;
 };
+
+// Status of a polish that stopped at its budget with a factorisation due:
+// its state can be saved (polish_save) and continued elsewhere.
+constexpr int kPolishSuspended = 4;
 
 template <int MM, typename YP, typename D>
 BODEX_FI void polish_begin(const D& Dt, YP y0, PolishState<MM>& PS) {
@@ -1257,6 +1262,7 @@ BODEX_FI void polish_begin(const D& Dt, YP y0, PolishState<MM>& PS) {
     // no rank-one changes with the normal-sum row (its term involves every contact)
     PS.chg = kNoChange | (D::kGam ? 0 : int(kChgAllowed));
     PS.step0 = 0;
+    PS.budget = 0x7fffffff;
 }
 
 // Acceptance: stationarity, dual and primal feasibility.  Sets the status
@@ -1315,7 +1321,8 @@ BODEX_FI bool polish_accept(const D& Dt, const PolishWork<V>& W, PolishState<MM>
 }
 
 
-template <int MM, typename D, class V>
+// BUDGET: compile the check of PS.budget in (the chunked first pass).
+template <int MM, typename D, class V, bool BUDGET = false>
 BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W, PolishState<MM>& PS) {
     ActiveSet<MM>& S = PS.S;
     PolishOut& out = PS.out;
@@ -1335,6 +1342,10 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
     const PendingRow none = {-1, -1, {0.0, 0.0, 0.0}, 0.0};
     if (mode == kAccept) return true;
     if (refactor) {
+        if (BUDGET && out.steps >= PS.budget) {
+            out.status = kPolishSuspended;
+            return true;
+        }
         if (++out.steps - PS.step0 > max_steps) {
             out.status = 2;
             return true;
@@ -1627,6 +1638,7 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
 // (equality solve, multiplier drops, steps) and a step cap of its own.
 template <int MM, typename D, class V>
 BODEX_FI bool polish_finish(const D& Dt, const PolishWork<V>& W, PolishState<MM>& PS) {
+    if (PS.out.status == kPolishSuspended) return true;
     const bool reached = PS.mode == kAccept;
     if (reached) polish_accept<MM>(Dt, W, PS);
     const bool forced = reached && (PS.chg & kChgRetry);

@@ -72,6 +72,9 @@ struct bodex_qp {
     // descent workspace: contacts, their gradients, distances, loss weights
     float* d_hand = nullptr;
     size_t d_hand_cap = 0;
+    // chunked polish: spill records (doubles, then ints) and the record of each QP
+    void* d_spill = nullptr;
+    size_t d_spill_cap = 0;
     // graphs
     std::vector<GraphEntry> graphs;
     uint64_t graph_clock = 0;
@@ -315,6 +318,14 @@ int graph_entry(bodex_qp* h, uint64_t key, size_t n_ints, GraphEntry** out) {
 enum class Kind { Admm, Fin, Bwd };
 
 constexpr int kDefaultAdmmWaves = 2;
+// polish_chunk -1 (the default): the chunk by batch size.  Measured at 16
+// to 8192 grasps x 16 wrenches (5 contacts): the contact-parallel polish
+// alone (chunk 1) is ~2.8x faster than the one-lane polish up to 256 grasps
+// and 1.4x at 2048, where its latency wins; at 8192 the one-lane pass is
+// needed for throughput and a budget of 20 factorisations leaves the
+// contact-parallel kernel only the slowest QPs (0.97x the one-lane time).
+constexpr int kDefaultPolishChunk = -1;
+int auto_polish_chunk(int n_qps) { return n_qps <= 40960 ? 1 : (n_qps <= 98304 ? 12 : 20); }
 // ADMM stopping tolerances with the polish on, per friction model (admm_tol 0)
 constexpr float kAdmmTolPyramid = 1e-1f, kAdmmTolCone = 1e-2f;
 
@@ -344,6 +355,7 @@ int validate_params(const bodex_qp_params* p, bodex_qp* h) {
     if (p->check_every < 1) return fail(h, BODEX_EINVAL, "check_every must be >= 1");
     if (!(p->rho_min > 0.f) || !(p->rho_max >= p->rho_min))
         return fail(h, BODEX_EINVAL, "need 0 < rho_min <= rho_max");
+    if (p->polish_chunk < -1) return fail(h, BODEX_EINVAL, "polish_chunk must be >= -1");
     if (!(p->rho_hysteresis >= 1.f)) return fail(h, BODEX_EINVAL, "rho_hysteresis must be >= 1");
     if (!(p->fp64_cond > 0.f)) return fail(h, BODEX_EINVAL, "fp64_cond must be positive");
     if (p->polish_steps < 0) return fail(h, BODEX_EINVAL, "polish_steps must be >= 0");
@@ -516,7 +528,7 @@ void bodex_qp_default_params(bodex_qp_params* p) {
     p->rho_hysteresis = 5.0f;
     p->fp64_cond = 1e4f;
     p->polish_steps = 128;
-    p->iters_per_chunk = 20;
+    p->polish_chunk = kDefaultPolishChunk;
     p->flags = BODEX_F_POLISH | BODEX_F_ADAPTIVE_RHO;
     p->admm_waves = 0;
     p->admm_tol = 0.0f;
@@ -626,6 +638,27 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
     a.status = out->status;
     a.pflops = out->polish_flops;
 
+    // chunked polish: the one-lane pass hands QPs that need more than
+    // polish_chunk factorisations to the contact-parallel polish (records
+    // for every QP of the batch, so none is ever finished in the first pass
+    // for want of room)
+    const int chunk = h->prm.polish_chunk < 0 ? auto_polish_chunk(W) : h->prm.polish_chunk;
+    const bool chunked = (h->prm.flags & BODEX_F_POLISH) && !cone && h->prm.gamma == 0.f && chunk > 0;
+    int grid_g = 0;
+    if (chunked) {
+        const size_t K = size_t(W);
+        const size_t nd = size_t(3 * mm + 3) * K, ni = size_t(bodex::kSpInts) * K + size_t(W);
+        rc = ensure_device(h, &h->d_spill, &h->d_spill_cap, nd * sizeof(double) + ni * sizeof(int));
+        if (rc) return rc;
+        a.spill.d = static_cast<double*>(h->d_spill);
+        a.spill.i = reinterpret_cast<int*>(a.spill.d + nd);
+        a.spill.K = int(K);
+        a.spill_idx = a.spill.i + size_t(bodex::kSpInts) * K;
+        a.polish_budget = chunk;
+        const int gpw = bodex::kWave / bodex::gpolish_group(mm);
+        grid_g = int((K + gpw - 1) / gpw);
+    }
+
     const size_t n_ints = size_t(G) * 3 + 1 + S.n_tiles + 1 + 4;
     const bool timing = (h->prm.flags & BODEX_F_TIMING) != 0;
     const bool graph = (h->prm.flags & BODEX_F_GRAPH) != 0 && h->stream != nullptr;
@@ -650,7 +683,19 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
         KArgs f = a;
         f.queue = nullptr;
         if (with_events) HIP_TRY(h, hipEventRecord(h->tev[2], h->stream));
-        HIP_TRY(h, launch(Kind::Fin, mm, f, grid_f, lds_f, h->stream));
+        if (chunked) {
+            // first pass (budgeted), contact-parallel polish of what it
+            // handed on, outputs of those QPs; the record counter is the
+            // second queue word, cleared with the others above
+            f.spill_count = d_queue + 1;
+            f.fin_mode = 1;
+            HIP_TRY(h, launch(Kind::Fin, mm, f, grid_f, lds_f, h->stream));
+            HIP_TRY(h, bodex::launch_gpolish(mm, f, grid_g, h->stream));
+            f.fin_mode = 2;
+            HIP_TRY(h, launch(Kind::Fin, mm, f, grid_f, lds_f, h->stream));
+        } else {
+            HIP_TRY(h, launch(Kind::Fin, mm, f, grid_f, lds_f, h->stream));
+        }
         if (with_events) HIP_TRY(h, hipEventRecord(h->tev[3], h->stream));
         return 0;
     };
@@ -668,7 +713,7 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
         if (rc) return rc;
         rc = enqueue(h->d_desc, timing);
         if (rc) return rc;
-        h->last_launches = 3;
+        h->last_launches = chunked ? 5 : 3;
         h->t_admm = h->t_fin = timing;
         return 0;
     }
@@ -865,6 +910,7 @@ int bodex_qp_destroy(bodex_qp_t* h) {
     if (h->d_desc) (void)hipFree(h->d_desc);
     if (h->d_state) (void)hipFree(h->d_state);
     if (h->d_hand) (void)hipFree(h->d_hand);
+    if (h->d_spill) (void)hipFree(h->d_spill);
     if (h->h_desc) (void)hipHostFree(h->h_desc);
     if (h->desc_ev) (void)hipEventDestroy(h->desc_ev);
     for (auto& e : h->tev)

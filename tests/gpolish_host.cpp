@@ -1,0 +1,222 @@
+// Host build of the chunked FP64 polish (the headers the GPU kernels use),
+// for CPU tests: the one-lane polish runs a budget of factorisations and
+// saves its state into a spill record, then the contact-parallel polish
+// continues from the record with GS threads standing in for the GS lanes of
+// a group (each group operation is a barrier plus a reduction in lane order,
+// the same value in every thread).
+#include <condition_variable>
+#include <cstring>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "../paper_2412_16490_amd/csrc/bodex_gpolish.h"
+
+using namespace bodex;
+
+namespace {
+
+// GS threads of one group: shared slots, a barrier with a generation count.
+struct Shared {
+    int n;
+    std::mutex mu;
+    std::condition_variable cv;
+    int waiting = 0;
+    long gen = 0;
+    double d[8][32];
+    int i[8][4];
+    explicit Shared(int n_) : n(n_) {}
+    void barrier() {
+        std::unique_lock<std::mutex> lk(mu);
+        const long g = gen;
+        if (++waiting == n) {
+            waiting = 0;
+            ++gen;
+            cv.notify_all();
+        } else {
+            cv.wait(lk, [&] { return gen != g; });
+        }
+    }
+};
+
+template <int GS>
+struct HostTeam {
+    int sub;
+    Shared* S;
+    double sum(double v) const {
+        S->d[sub][0] = v;
+        S->barrier();
+        double r = 0.0;
+        for (int l = 0; l < GS; ++l) r += S->d[l][0];
+        S->barrier();
+        return r;
+    }
+    template <int N>
+    void sum(double (&v)[N]) const {
+        static_assert(N <= 32, "slot size");
+        for (int j = 0; j < N; ++j) S->d[sub][j] = v[j];
+        S->barrier();
+        for (int j = 0; j < N; ++j) {
+            double r = 0.0;
+            for (int l = 0; l < GS; ++l) r += S->d[l][j];
+            v[j] = r;
+        }
+        S->barrier();
+    }
+    double max(double v) const {
+        S->d[sub][0] = v;
+        S->barrier();
+        double r = S->d[0][0];
+        for (int l = 1; l < GS; ++l) r = fmax(r, S->d[l][0]);
+        S->barrier();
+        return r;
+    }
+    void argmax(double& v, int& idx) const {
+        S->d[sub][0] = v;
+        S->i[sub][0] = idx;
+        S->barrier();
+        for (int l = 0; l < GS; ++l) {
+            const double ov = S->d[l][0];
+            const int oi = S->i[l][0];
+            if (ov > v || (ov == v && unsigned(oi) < unsigned(idx))) {
+                v = ov;
+                idx = oi;
+            }
+        }
+        S->barrier();
+    }
+    void argmin_frac(double& tn, double& td, int& idx) const {
+        S->d[sub][0] = tn;
+        S->d[sub][1] = td;
+        S->i[sub][0] = idx;
+        S->barrier();
+        for (int l = 0; l < GS; ++l) {
+            const double on = S->d[l][0], od = S->d[l][1];
+            const int oi = S->i[l][0];
+            const double a = on * td, b = tn * od;
+            if (a < b || (a == b && unsigned(oi) < unsigned(idx))) {
+                tn = on;
+                td = od;
+                idx = oi;
+            }
+        }
+        S->barrier();
+    }
+    double bcast(double v, int src) const {
+        S->d[sub][0] = v;
+        S->barrier();
+        const double r = S->d[src][0];
+        S->barrier();
+        return r;
+    }
+    int bcast(int v, int src) const {
+        S->i[sub][0] = v;
+        S->barrier();
+        const int r = S->i[src][0];
+        S->barrier();
+        return r;
+    }
+    unsigned bor(unsigned v) const {
+        S->i[sub][0] = int(v);
+        S->barrier();
+        unsigned r = 0u;
+        for (int l = 0; l < GS; ++l) r |= unsigned(S->i[l][0]);
+        S->barrier();
+        return r;
+    }
+};
+
+constexpr int MM = 5, NV = 15, GS = 8;
+
+}  // namespace
+
+extern "C" {
+
+// Chunked polish of the s QPs of one grasp with m <= 5 contacts (beta = 1,
+// fmax = 1, gamma = 0): the one-lane polish from the ADMM-form dual guess
+// y0 [s][46] with a budget of `budget` factorisations; a QP not finished by
+// then is saved to a record and finished by the contact-parallel polish.
+// Outputs x [s][15], status [s], handed [s] (1 if the group finished it),
+// counts [s][4] (factorisations, of which one-row changes, equality solves,
+// one-row steps).  Returns the number of QPs whose polish was not accepted.
+int host_chunked_polish(int m, const double* p, const double* n, const double* mu, const double* t, int s,
+                        double kappa, double eps, const float* y0, int budget, double* x, int* status,
+                        int* handed, int* counts) {
+    double G[6 * NV] = {};
+    double muc[MM] = {};
+    for (int i = 0; i < m; ++i) {
+        grasp_columns<double, NV>(p + 3 * i, n + 3 * i, kappa, i, G);
+        muc[i] = mu[i] * kC8;
+    }
+    int bad = 0;
+    std::vector<double> dsp((3 * MM + 3) * 1);
+    std::vector<int> isp(kSpInts * 1);
+    SpillPtrs sp{dsp.data(), isp.data(), 1};
+    for (int j = 0; j < s; ++j) {
+        PolishData<MM, const double*, false> D;
+        D.G = G;
+        D.muc = muc;
+        for (int r = 0; r < 6; ++r) D.bt[r] = t[6 * j + r];
+        D.m = m;
+        D.fmax = 1.0;
+        D.gamma = 0.0;
+        D.eps = eps;
+        double xb[NV] = {}, zb[NV] = {};
+        PolishWork<LaneVec> W{{xb, 1}, {zb, 1}};
+        PolishState<MM> PS;
+        PS.S.pc = LaneVec{nullptr, 1};
+        polish_begin<MM>(D, y0 + 46 * j, PS);
+        PS.budget = budget;
+        do {
+            while (!polish_advance<MM, decltype(D), LaneVec, true>(D, 200, W, PS)) {
+            }
+        } while (!polish_finish<MM>(D, W, PS));
+        PolishOut po = PS.out;
+        handed[j] = po.status == kPolishSuspended;
+        if (handed[j]) {
+            polish_save<MM>(PS, W.x, m, sp, 0, j, 0);
+            Shared sh(GS);
+            std::vector<std::thread> th;
+            for (int l = 0; l < GS; ++l) {
+                th.emplace_back([&, l] {
+                    HostTeam<GS> team{l, &sh};
+                    GQP<MM> Q;
+                    Q.sub = l;
+                    double p3[3] = {0.0, 0.0, 0.0}, n3[3] = {0.0, 0.0, 1.0}, mu1 = 0.5;
+                    if (l < m) {
+                        for (int q = 0; q < 3; ++q) {
+                            p3[q] = p[3 * l + q];
+                            n3[q] = n[3 * l + q];
+                        }
+                        mu1 = mu[l];
+                    }
+                    gpolish_load<MM>(team, Q, sp, 0, m, p3, n3, mu1, kappa, t + 6 * j, 1.0, eps);
+                    do {
+                        while (!gpolish_advance<MM>(team, Q, 200)) {
+                        }
+                    } while (!gpolish_finish<MM>(team, Q));
+                    gpolish_store<MM>(team, Q, sp, 0);
+                });
+            }
+            for (auto& h : th) h.join();
+            for (int c = 0; c < NV; ++c) xb[c] = c < 3 * m ? sp.dv(c, 0) : 0.0;
+            po.status = sp.iv(kSpStatus, 0);
+            po.steps = sp.iv(kSpSteps, 0);
+            po.updates = sp.iv(kSpUpdates, 0);
+            po.eqps = sp.iv(kSpEqps, 0);
+            po.moves = sp.iv(kSpMoves, 0);
+            // the saved active set, reassembled by the group, equals each
+            // contact's rows at the end
+        }
+        for (int c = 0; c < NV; ++c) x[NV * j + c] = c < 3 * m ? xb[c] : 0.0;
+        status[j] = po.status;
+        counts[4 * j] = po.steps;
+        counts[4 * j + 1] = po.updates;
+        counts[4 * j + 2] = po.eqps;
+        counts[4 * j + 3] = po.moves;
+        bad += po.status != 0;
+    }
+    return bad;
+}
+
+}  // extern "C"

@@ -261,3 +261,19 @@ def test_kernel_timing_flag():
     kt = s.kernel_times()
     assert kt["admm_ms"] > 0 and kt["finalize_ms"] > 0 and kt["backward_ms"] > 0
     s.close()
+
+
+@pytest.mark.parametrize("chunk", [0, 1, 3, 12, 40])
+@pytest.mark.parametrize("cfg,ng", [(1, 300), (3, 300), (0, 64)])
+def test_chunked_polish_budgets(chunk, cfg, ng):
+    # the one-lane polish with a budget of `chunk` factorisations, the
+    # contact-parallel polish for the QPs it hands on (0: none handed on,
+    # 1: nearly all, 40: none needs it), the outputs of those QPs formed by
+    # the second finalize pass: the same minimiser either way
+    b = wl.config(cfg, ng)
+    print("chunked polish: %s, %d grasps, chunk %d" % (b.name, ng, chunk), flush=True)
+    gpu = run_gpu(b, polish_chunk=chunk, tol_rel=1e-6 if cfg == 0 else 1e-5)
+    ref = _ref(b)
+    print("chunk %d:" % chunk, check_forward(b, gpu, ref))
+    check_energy(b, gpu, ref)
+    check_state_kkt(b, gpu, 1e-6 if cfg == 0 else 1e-5, range(0, b.n_qps, 7))

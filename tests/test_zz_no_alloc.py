@@ -1,8 +1,12 @@
 """The allocation-free solve (bodex_qp_solve_static) against bodex_qp_solve,
 through the C ABI: two calls in a row on one handle, the second with a
 smaller batch, each compared element by element with the allocating entry
-point on the same inputs (same kernels and tiles, so the results are
-identical); also a cone handle, the size limit and the rejected flags."""
+point on the same inputs.  The static solve runs the one-lane polish to the
+end (the contact-parallel polish needs workspace), so against bodex_qp_solve
+with polish_chunk = 0 (same kernels and tiles) the results are identical,
+and against the default chunked polish they agree to the parity bar (both
+reach the minimiser); also a cone handle, the size limit and the rejected
+flags."""
 import numpy as np
 import pytest
 
@@ -35,18 +39,35 @@ def _same(a, b, sa, sb):
         np.testing.assert_array_equal(sa[k], sb[k], err_msg="state " + k)
 
 
+def _close(a, b, batch):
+    # the parity bar: objective 1e-5 relative (floor 1e-2 |t|^2), forces 1e-4
+    # fmax, energy 1e-5 relative (floor 1e-2 s)
+    tn = np.sum(batch.wrench.astype(np.float64) ** 2, axis=1)
+    q = np.abs(a["qp_obj"] - b["qp_obj"]) / np.maximum(np.abs(a["qp_obj"]), 1e-2 * tn)
+    assert q.max() <= 1e-5
+    assert np.abs(a["forces"] - b["forces"]).max() <= 1e-4
+    s = np.diff(batch.woff)
+    e = np.abs(a["energy"] - b["energy"]) / np.maximum(np.abs(a["energy"]), 1e-2 * s)
+    assert e.max() <= 1e-5
+    np.testing.assert_array_equal(a["status"] & api.ST_CONVERGED, b["status"] & api.ST_CONVERGED)
+
+
 def test_static_solve_matches_the_allocating_solve_twice():
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+    s0 = api.Solver(api.default_params(m_max=5, s_max=32, polish_chunk=0))
     s = api.Solver(api.default_params(m_max=5, s_max=32))
     print("static solve: 2000 grasps uneven, then 150 grasps", flush=True)
     big = wl.config(3, 2000)
     small = wl.config(1, 150)
     for b in (big, small):
-        a, c, sa, sc = _both(s, b)
+        a, c, sa, sc = _both(s0, b)
         _same(a, c, sa, sc)
         assert np.all(c["status"] & api.ST_CONVERGED)
+        a2, c2, _, _ = _both(s, b)
+        _close(a2, c2, b)
+    s0.close()
     s.close()
 
 
@@ -54,7 +75,7 @@ def test_static_solve_circular_cone():
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    p = api.default_params(m_max=5, s_max=16)
+    p = api.default_params(m_max=5, s_max=16, polish_chunk=0)
     p.friction_cone = api.CONE_CIRCULAR
     s = api.Solver(p)
     print("static solve: circular cone, 64 grasps", flush=True)
