@@ -81,8 +81,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the extra forms")
-    ap.add_argument("--serve-seconds", type=float, default=0.5,
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="length of the Poisson arrival window of the served form")
+    ap.add_argument("--fifo-seconds", type=float, default=1.0,
+                    help="window of the stream that both the served form and the FIFO baseline run")
+    ap.add_argument("--served-only", action="store_true",
+                    help="only run the served form and its FIFO baseline and print their JSON")
     ap.add_argument("--admm-waves", type=int, default=0, help="ADMM register budget (0 = default)")
     ap.add_argument("--cone-only", action="store_true",
                     help="only run the circular-cone form and print its JSON")
@@ -133,6 +137,9 @@ def main():
     if args.descent_only:
         print(json.dumps({"coarse_descent": descent_form(torch, api, wl)}), flush=True)
         return
+    if args.served_only:
+        print(json.dumps(served(torch, wl, args.serve_seconds, args.fifo_seconds)), flush=True)
+        return
 
     batch = wl.config(1)
     db = api.DeviceBatch(batch)
@@ -168,13 +175,14 @@ def main():
 
     admm_avg = float(np.mean(admm_ms))
     fin_avg = float(np.mean(fin_ms))
+    dev_ms = np.asarray(admm_ms) + np.asarray(fin_ms)  # device time of each step's launches
     flops_a = admm_flops(5, iters, p.check_every)
     flops_f = float(np.sum(res["polish_flops"].double().cpu().numpy()))
     kernels = {
         "admm": {"bound": "alu", "kernel": "admm_kernel<5>", "dtype": "f32", "peak": PEAK_FP32_TFLOPS,
                  "ms": admm_avg, "flops": flops_a},
-        "finalize": {"bound": "alu", "kernel": "finalize_kernel<5>", "dtype": "f64",
-                     "peak": PEAK_FP64_TFLOPS, "ms": fin_avg, "flops": flops_f},
+        "finalize": {"bound": "alu", "kernel": "FP64 polish: finalize_kernel<5> passes + gpolish_kernel<5,8>",
+                     "dtype": "f64", "peak": PEAK_FP64_TFLOPS, "ms": fin_avg, "flops": flops_f},
     }
 
     def roof(name):
@@ -207,7 +215,10 @@ def main():
                    "polish": "fp64", "converged": converged,
                    "kkt_rel_max": float(np.max(kkt)),
                    "iters_mean": float(np.mean(iters)), "iters_p99": float(np.percentile(iters, 99)),
-                   "finalize_ms": round(float(np.mean(fin_ms)), 4)},
+                   "finalize_ms": round(float(np.mean(fin_ms)), 4),
+                   "polish_chunk": "auto (%d for %d QPs)" % (20 if db.n_qps > 98304 else 12, db.n_qps),
+                   "step_device_ms_median": round(float(np.median(dev_ms)), 4),
+                   "step_device_ms_p99": round(float(np.percentile(dev_ms, 99)), 4)},
         "roofline": roofline,
         "roofline_other_kernel": other,
     }
@@ -216,7 +227,8 @@ def main():
     if not args.no_forms:
         out["forms"] = forms(torch, api, wl)
         out["forms"]["tuning"] = tuning(torch, api, db)
-        out["forms"].update(served(torch, wl, args.serve_seconds))
+        out["forms"]["sphere_m4_s6"] = small_form(torch, api, wl)
+        out["forms"].update(served(torch, wl, args.serve_seconds, args.fifo_seconds))
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(batch)
@@ -227,14 +239,22 @@ def main():
 def forms(torch, api, wl):
     """Uneven batch: persistent graph launch vs per-(m, s) plain launches; and
     forward + backward on the differentiation workload."""
+    from paper_2412_16490_amd import autotune
     res = {}
     b3 = wl.config(3)
     db3 = api.DeviceBatch(b3)
     s_max = int(np.max(np.diff(b3.woff)))
     side = torch.cuda.Stream()
+    # the autotuner's choice for this shape: polish chunk (one-lane budget
+    # before the contact-parallel polish), ADMM register budget, persistent
+    # cost-sorted launch or not; cached per shape class
+    base = api.default_params(m_max=5, s_max=s_max)
+    t0 = time.perf_counter()
+    knobs, table = autotune.tune(db3, base=base, reps=2)
+    tune_s = time.perf_counter() - t0
     with torch.cuda.stream(side):
-        pb = api.default_params(m_max=5, s_max=s_max)
-        pb.flags |= api.F_BATCHED | api.F_GRAPH
+        pb = autotune.apply(base, knobs)
+        pb.flags |= api.F_GRAPH
         sb = api.Solver(pb, stream=side.cuda_stream)
         st3 = api.new_state(db3.n_grasps, db3.n_qps, 5)
         r3 = api.new_result(db3.n_grasps, db3.n_qps, 5)
@@ -248,9 +268,14 @@ def forms(torch, api, wl):
         side.synchronize()
         tb = (time.perf_counter() - t0) / n
         conv = int(np.sum((r3["status"].cpu().numpy() & api.ST_CONVERGED) != 0))
+        dflt = [t for t in table if t["knobs"] == {"polish_chunk": 20, "admm_waves": 2, "batched": 1}]
         res["batched"] = {"workload": "ellipsoid-m45-s6to32 (50,000 grasps, %d QPs)" % db3.n_qps,
                           "ms": round(tb * 1e3, 3), "qps_per_s": round(conv / tb, 1),
-                          "converged": conv, "graph_replays": sb.stats()["graph_replays"]}
+                          "converged": conv, "graph_replays": sb.stats()["graph_replays"],
+                          "knobs": knobs, "knobs_from": "autotune cache (%d configurations, %.1f s)" % (
+                              len(table), tune_s),
+                          "tuning_best_ms": min(t["ms"] for t in table),
+                          "tuning_chunk20_batched_ms": dflt[0]["ms"] if dflt else None}
         sb.close()
         # per-(m, s) plain launches of the same grasps
         groups = {}
@@ -587,41 +612,106 @@ def tuning(torch, api, db):
     return res
 
 
-def served(torch, wl, seconds):
-    """Continuous batching vs FIFO plain launches on the same Poisson stream
-    (200 requests/s, 50 steps each, sizes log-U[16, 4096] grasps)."""
+def served(torch, wl, seconds, fifo_seconds):
+    """Continuous batching vs FIFO plain launches on one Poisson stream (200
+    requests/s, 50 forward+backward steps each, sizes log-U[16, 4096] grasps).
+    The served form runs the first `seconds` of the stream; both forms run the
+    same requests, those of the first `fifo_seconds` (the FIFO baseline
+    serves about a tenth of the offered load, so the full window would take
+    it many times longer).  Only converged QP solves are counted."""
     from paper_2412_16490_amd.serve import Server, serve_fifo_plain
     reqs = list(wl.request_stream(rate=200.0, duration=seconds))
-    srv = Server(m_max=5, s_max=32, budget_bytes=4 << 30)
-    st = srv.run(reqs, realtime=True)
-    srv.close()
-    fifo = serve_fifo_plain(reqs[: max(1, len(reqs) // 4)], m_max=5, s_max=32, realtime=True)
-    return {"served": {"stream": "%d requests over %.2f s, 50 steps" % (len(reqs), seconds),
-                       "qp_solves_per_s": round(st["qps_per_s"], 1),
-                       "latency_p50_s": st["latency_p50_s"], "latency_p99_s": st["latency_p99_s"],
-                       "wall_s": round(st["wall_s"], 3), "ticks": st["ticks"],
-                       "peak_device_bytes": st["peak_device_bytes"]},
-            "fifo_plain": {"stream": "first %d of the same requests" % fifo["requests"],
-                           "qp_solves_per_s": round(fifo["qps_per_s"], 1),
-                           "latency_p50_s": fifo["latency_p50_s"], "latency_p99_s": fifo["latency_p99_s"],
-                           "wall_s": round(fifo["wall_s"], 3)}}
+    window = [r for r in reqs if r.arrival <= fifo_seconds]
+
+    def run_served(rs):
+        srv = Server(m_max=5, s_max=32, budget_bytes=4 << 30)
+        srv.progress_every = 10.0
+        st = srv.run(rs, realtime=True)
+        srv.close()
+        return {"qp_solves_per_s": round(st["qps_per_s"], 1), "converged": st["qp_solves_converged"],
+                "qp_solves": st["qp_solves"], "offered_qp_solves_per_s": round(st["offered_qp_solves_per_s"], 1),
+                "keeps_up": st["keeps_up"], "latency_p50_s": round(st["latency_p50_s"], 4),
+                "latency_p99_s": round(st["latency_p99_s"], 4), "wall_s": round(st["wall_s"], 3),
+                "ticks": st["ticks"], "queue_waiting_max": st["queue_waiting_max"],
+                "queue_waiting_at": st["queue_waiting_at"],
+                "around_solve_fraction": round(st["around_solve_fraction"], 4),
+                "peak_device_bytes": st["peak_device_bytes"]}
+
+    out = {}
+    if seconds > fifo_seconds:
+        out["served_full"] = {"stream": "%d requests over %.1f s, 50 steps" % (len(reqs), seconds),
+                              **run_served(reqs)}
+    out["served"] = {"stream": "%d requests over %.1f s, 50 steps (the window both forms run)" % (
+        len(window), fifo_seconds), **run_served(window)}
+    fifo = serve_fifo_plain(window, m_max=5, s_max=32, realtime=True)
+    out["fifo_plain"] = {"stream": "the same %d requests" % fifo["requests"],
+                         "qp_solves_per_s": round(fifo["qps_per_s"], 1), "converged": fifo["qp_solves_converged"],
+                         "latency_p50_s": round(fifo["latency_p50_s"], 4),
+                         "latency_p99_s": round(fifo["latency_p99_s"], 4), "wall_s": round(fifo["wall_s"], 3)}
+    return out
+
+
+def small_form(torch, api, wl, reps=20):
+    """The 4-contact sphere workload (64 grasps x 6 wrenches = 384 QPs, tol
+    1e-6): median and p99 of the device time of one solve's launches."""
+    b = wl.config(0)
+    db = api.DeviceBatch(b)
+    p = api.default_params(m_max=4, s_max=6)
+    p.flags |= api.F_TIMING
+    p.tol_rel = 1e-6
+    s = api.Solver(p)
+    st = api.new_state(db.n_grasps, db.n_qps, 4)
+    r = api.new_result(db.n_grasps, db.n_qps, 4)
+    for _ in range(3):
+        s.solve(db, state=st, result=r)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        s.solve(db, state=st, result=r)
+        kt = s.kernel_times()
+        ts.append(kt["admm_ms"] + kt["finalize_ms"])
+    conv = int(np.sum((r["status"].cpu().numpy() & api.ST_CONVERGED) != 0))
+    s.close()
+    med = float(np.median(ts))
+    return {"workload": "sphere-m4-s6 (64 grasps x 4 contacts x 6 wrenches, seed 16490, tol 1e-6)",
+            "qps": int(db.n_qps), "converged": conv, "device_ms_median": round(med, 4),
+            "device_ms_p99": round(float(np.percentile(ts, 99)), 4), "qps_per_s": round(conv / (med / 1e3), 1)}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(batch):
-    """The FP64 oracle (as it stands) on the host cores over the same QPs."""
+    """The FP64 oracle (as it stands) on the host: the cores this process is
+    given (its CPU affinity, at most the 16-core share a GPU's job gets on a
+    shared host), and one thread, over the same QPs."""
     import oracle
     try:
-        threads = len(os.sched_getaffinity(0))
+        affinity = len(os.sched_getaffinity(0))
     except AttributeError:
-        threads = os.cpu_count() or 1
-    threads = max(1, min(threads, 16))
+        affinity = os.cpu_count() or 1
+    threads = max(1, min(affinity, 16))
     t0 = time.perf_counter()
     oracle.solve_batch(batch.counts, batch.woff, batch.points, batch.normals, batch.mu,
                        batch.wrench, nthreads=threads)
     dt = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.solve_batch(batch.counts, batch.woff, batch.points, batch.normals, batch.mu,
+                       batch.wrench, nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": round(batch.n_qps / dt, 1), "unit": "QPs/s", "cores": threads, "kind": "oracle",
-            "sample": "all %d QPs of the 8192-grasp workload, %.1f s wall on %d threads"
-                      % (batch.n_qps, dt, threads)}
+            "cpu_model": _cpu_model(), "logical_cpus_on_host": os.cpu_count(), "cpu_affinity": affinity,
+            "value_1_thread": round(batch.n_qps / dt1, 1),
+            "sample": "all %d QPs of the 8192-grasp workload: %.2f s wall on %d threads, %.2f s on 1 thread"
+                      % (batch.n_qps, dt, threads, dt1)}
 
 
 if __name__ == "__main__":

@@ -159,6 +159,20 @@ typedef struct {
                 /* its digits to cancellation when it is small).  NULL: not */
                 /* written; the backward then recovers f* in FP64 (pyramid: */
                 /* one more polish) or uses the FP32 forces (cone).         */
+    /* Layout of the arrays above.  By default (stride 0, offsets NULL) a  */
+    /* batch's QP w is column w of arrays with W columns and grasp g's rho */
+    /* is rho[g].  A caller that keeps several requests' states in one     */
+    /* pool (a serving loop) sets stride = the pool's column count and,    */
+    /* per grasp of the batch, qp_offset[g] = the pool column of its first */
+    /* QP (its s_g QPs follow) and grasp_offset[g] = its index in rho (of  */
+    /* rho_len); columns of different grasps must not overlap.  The solve, */
+    /* the backward and the descent then read and write the state in place */
+    /* (no gather or scatter).  qp_offset and grasp_offset are HOST arrays, */
+    /* read during the call; both or neither.                              */
+    int stride;
+    int rho_len;
+    const int *qp_offset;
+    const int *grasp_offset;
 } bodex_state;
 
 typedef struct {

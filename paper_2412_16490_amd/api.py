@@ -87,7 +87,8 @@ class Descent(ctypes.Structure):
 class State(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("z", ctypes.c_void_p),
                 ("y", ctypes.c_void_p), ("rho", ctypes.c_void_p),
-                ("r", ctypes.c_void_p)]
+                ("r", ctypes.c_void_p), ("stride", ctypes.c_int), ("rho_len", ctypes.c_int),
+                ("qp_offset", ctypes.POINTER(ctypes.c_int)), ("grasp_offset", ctypes.POINTER(ctypes.c_int))]
 
 
 class Result(ctypes.Structure):
@@ -268,10 +269,21 @@ def new_result(n_grasps, n_qps, m_max, device="cuda", polish_flops=False):
 
 
 def _c_state(st) -> State:
+    """A state dict (x, z, y, rho[, r]) or a pooled view of one (the same plus
+    'qp_offset' and 'grasp_offset' host int32 arrays for the batch's grasps;
+    the pool's column count and rho length are taken from the arrays)."""
     s = State()
     if st is not None:
         s.x, s.z, s.y, s.rho = _ptr(st["x"]), _ptr(st["z"]), _ptr(st["y"]), _ptr(st["rho"])
         s.r = _ptr(st["r"]) if st.get("r") is not None else None
+        if st.get("qp_offset") is not None:
+            qo = np.ascontiguousarray(st["qp_offset"], np.int32)
+            go = np.ascontiguousarray(st["grasp_offset"], np.int32)
+            st["_keep"] = (qo, go)  # alive for the call
+            s.stride = int(st["x"].shape[1])
+            s.rho_len = int(st["rho"].shape[0])
+            s.qp_offset = qo.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+            s.grasp_offset = go.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
     return s
 
 

@@ -3,6 +3,12 @@
 For a batch shape it times the full solve (ADMM + polish) over a small grid of
 knobs and keeps the fastest configuration whose results are all converged:
 
+* ``polish_chunk`` the iteration-chunk schedule of the FP64 polish: the
+                   factorisations a QP takes in the one-lane polish (group
+                   shape: one lane per QP, 64 QPs per wavefront) before it is
+                   handed to the contact-parallel polish (group shape: one
+                   lane per contact, 8 or 16 QPs per wavefront); 0 keeps every
+                   QP in the one-lane polish, 1 hands nearly all on;
 * ``admm_waves``   register budget of the ADMM kernel as resident waves per
                    SIMD (1 = no cap, 2, 3, 4): trades spills for occupancy;
 * ``check_every``  iterations between residual checks / rho updates;
@@ -25,6 +31,7 @@ import numpy as np
 from . import api
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "bodex_qp_autotune.json")
+DEFAULT_GRID = {"polish_chunk": [0, 1, 4, 8, 12, 16, 20, 24], "admm_waves": [2, 3], "batched": [0, 1]}
 
 
 def shape_key(device_name: str, batch: api.DeviceBatch) -> str:
@@ -67,7 +74,7 @@ def tune(batch: api.DeviceBatch, base: api.Params | None = None, reps: int = 3,
             cache = {}
     if key in cache and not force:
         return cache[key]["best"], cache[key]["table"]
-    grid = grid or {"admm_waves": [1, 2, 3, 4], "check_every": [5, 10, 20], "batched": [0, 1]}
+    grid = grid or DEFAULT_GRID
     s_max = int(np.max(np.diff(batch.woff)))
     stream = torch.cuda.Stream()
     table = []
@@ -77,12 +84,7 @@ def tune(batch: api.DeviceBatch, base: api.Params | None = None, reps: int = 3,
         p = api.Params.from_buffer_copy(bytes(base)) if base is not None else api.default_params()
         p.m_max = batch.m_max
         p.s_max = max(p.s_max, s_max)
-        p.admm_waves = int(knobs.get("admm_waves", 0))
-        p.check_every = int(knobs.get("check_every", p.check_every))
-        if knobs.get("batched"):
-            p.flags |= api.F_BATCHED
-        else:
-            p.flags &= ~api.F_BATCHED
+        p = apply(p, knobs)
         ms, ok = _time_solve(p, batch, reps, stream)
         table.append({"knobs": knobs, "ms": round(ms * 1e3, 4), "converged": ok})
     good = [t for t in table if t["converged"]] or table
@@ -99,6 +101,8 @@ def tune(batch: api.DeviceBatch, base: api.Params | None = None, reps: int = 3,
 
 def apply(params: api.Params, knobs: dict) -> api.Params:
     p = api.Params.from_buffer_copy(bytes(params))
+    if "polish_chunk" in knobs:
+        p.polish_chunk = int(knobs["polish_chunk"])
     if "admm_waves" in knobs:
         p.admm_waves = int(knobs["admm_waves"])
     if "check_every" in knobs:

@@ -70,6 +70,11 @@ struct KArgs {
     unsigned char* status;
     float* pflops;  // optional: polish flops per QP
     float* resid;   // optional state: [6][W] wrench residual G f - beta t of the returned forces (FP64, rounded)
+    // state layout: column stride of x, z, y, resid; per grasp the column
+    // of its first QP (null: its wrench offset) and its rho index (null: g)
+    int sW;
+    const int* sq;
+    const int* sg;
     // backward
     const float* dLdE;
     const float* dLdQ;
@@ -125,6 +130,12 @@ __device__ inline void lane_slot(const SlotInfo* info, int nsl, int lane, int& s
         acc += s;
     }
 }
+
+// State column of QP j of a slot's grasp, and the grasp's rho index.
+__device__ inline unsigned state_col(const KArgs& a, const SlotInfo& si, int j) {
+    return unsigned((a.sq ? a.sq[si.g] : si.w0) + j);
+}
+__device__ inline int rho_index(const KArgs& a, int g) { return a.sg ? a.sg[g] : g; }
 
 __device__ inline int fetch_tile(const KArgs& a, int* sTile, int prev) {
     if (a.queue == nullptr) return prev < 0 ? int(blockIdx.x) : a.n_tiles;
@@ -239,7 +250,7 @@ __device__ __forceinline__ void write_admm_x(const KArgs& a, unsigned w, const f
     asm volatile("" : "+v"(w));
 #pragma unroll
     for (int c = 0; c < NV; ++c)
-        if (c < 3 * a.ms) (a.x + size_t(c) * a.W)[w] = xv[c];
+        if (c < 3 * a.ms) (a.x + size_t(c) * a.sW)[w] = xv[c];
 }
 
 template <int MM, bool CONE>
@@ -256,8 +267,8 @@ __device__ __forceinline__ void write_admm_zy(const KArgs& a, unsigned w, const 
         for (int r = 0; r < NR; ++r) {
             const int sr = cone_state_row<MM>(r, a.ms);
             if (sr >= 0) {
-                (a.z + size_t(sr) * a.W)[w] = zv[r];
-                (a.y + size_t(sr) * a.W)[w] = rho * (wv[r] - zv[r]);
+                (a.z + size_t(sr) * a.sW)[w] = zv[r];
+                (a.y + size_t(sr) * a.sW)[w] = rho * (wv[r] - zv[r]);
             }
         }
     } else {
@@ -268,8 +279,8 @@ __device__ __forceinline__ void write_admm_zy(const KArgs& a, unsigned w, const 
             const int sr = state_row<MM>(r, a.ms);
             const float zr = row_proj(r, MM, wv[r], a.fmax, a.gamma);
             if (sr >= 0) {
-                (a.z + size_t(sr) * a.W)[w] = zr;
-                (a.y + size_t(sr) * a.W)[w] = rho * (wv[r] - zr);
+                (a.z + size_t(sr) * a.sW)[w] = zr;
+                (a.y + size_t(sr) * a.sW)[w] = rho * (wv[r] - zr);
             }
         }
     }
@@ -370,6 +381,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) 
         if (act) si = sInfo[slot];
         const int m = si.m;
         const int w = si.w0 + j;
+        const unsigned sw = state_col(a, si, j);  // this QP's state column
 
         // --- grasp matrix, friction terms, initial rho -----------------------
         for (int e = lane; e < nsl * NG; e += kWave) sG[e] = 0.f;
@@ -389,7 +401,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) 
             if (j == 0) {
                 float r0 = a.rho0;
                 if (a.warm) {
-                    const float rw = a.rho[si.g];
+                    const float rw = a.rho[rho_index(a, si.g)];
                     if (rw > 0.f && isfinite(rw)) r0 = rw;
                 }
                 sRho[slot] = fminf(fmaxf(r0, a.rho_min), a.rho_max);
@@ -427,7 +439,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) 
             float v = 0.f;
             const int sr = CONE ? cone_state_row<MM>(r, a.ms) : state_row<MM>(r, a.ms);
             if (act && a.warm && sr >= 0) {
-                const float zr = (a.z + size_t(sr) * a.W)[wl], yr = (a.y + size_t(sr) * a.W)[wl];
+                const float zr = (a.z + size_t(sr) * a.sW)[sw], yr = (a.y + size_t(sr) * a.sW)[sw];
                 v = zr + yr / rho;
             }
             wv[r] = isfinite(v) ? v : 0.f;
@@ -484,7 +496,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) 
                     stbits |= kStConverged;
                     it_done = it;
                     rho_frz = rho;
-                    write_admm_x<MM>(a, wl, xv);
+                    write_admm_x<MM>(a, sw, xv);
                 } else {
                     rpn = R.rp_n;
                     rdn = R.rd_n;
@@ -553,7 +565,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) 
             stbits |= kStMaxIter;
             it_done = a.max_iters;
             rho_frz = rho;
-            write_admm_x<MM>(a, wl, xv);
+            write_admm_x<MM>(a, sw, xv);
         }
         if (act && (stbits & kStNonfinite)) {
 #pragma unroll
@@ -561,14 +573,14 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) 
 #pragma unroll
             for (int r = 0; r < NR; ++r) wv[r] = NAN;
             rel_last = NAN;
-            write_admm_x<MM>(a, wl, xv);
+            write_admm_x<MM>(a, sw, xv);
         }
-        if (act) write_admm_zy<MM, CONE>(a, wl, wv, muc, rho_frz);
+        if (act) write_admm_zy<MM, CONE>(a, sw, wv, muc, rho_frz);
         if (act) {
             a.iters[w] = it_done;
             a.status[w] = stbits;
             a.kkt[w] = rel_last;
-            if (j == 0) a.rho[si.g] = rho;
+            if (j == 0) a.rho[rho_index(a, si.g)] = rho;
         }
     }
 }
@@ -740,7 +752,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BODEX_F
         if (act) {
             const double* Gs = P.G + size_t(slot) * NG;
             const double* muc = P.muc + slot * 8;
-            const size_t W_ = size_t(a.W);
+            const size_t W_ = size_t(a.sW);  // state stride
+            const size_t sw = state_col(a, si, j);
             double bt[6];
 #pragma unroll
             for (int r = 0; r < 6; ++r) bt[r] = double(a.beta) * double(a.wrench[size_t(w) * 6 + r]);
@@ -776,7 +789,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BODEX_F
             } else if (finite_in && a.polish) {
                 PolishState<MM> PS;
                 PS.S.pc = S.pc;
-                const StridedY<MM> y0{a.y + w, W_, a.ms};
+                const StridedY<MM> y0{a.y + sw, W_, a.ms};
                 if constexpr (mode == 0) {
                     polish_qp<MM>(D, y0, a.polish_steps, W, PS);
                 } else {
@@ -837,7 +850,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BODEX_F
                                 contact_multipliers<MM>(D, R, W.x, r6, i, none, 0.0, lg, lam);
                             }
 #pragma unroll
-                            for (int c = 0; c < 3; ++c) a.x[size_t(3 * i + c) * W_ + w] = float(f[c]);
+                            for (int c = 0; c < 3; ++c) a.x[size_t(3 * i + c) * W_ + sw] = float(f[c]);
 #pragma unroll
                             for (int kk = 0; kk < 9; ++kk) {
                                 const double zz = (kk < 8) ? facet_cos<double>(kk) * f[1] +
@@ -848,14 +861,14 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BODEX_F
                                 const float zv = on ? (kk == 8 ? a.fmax : 0.f)
                                                     : row_proj(9 * i + kk, MM, float(zz), a.fmax, a.gamma);
                                 const float yv = on ? float(jr == 0 ? lam[0] : (jr == 1 ? lam[1] : lam[2])) : 0.f;
-                                a.z[size_t(9 * i + kk) * W_ + w] = zv;
-                                a.y[size_t(9 * i + kk) * W_ + w] = yv;
+                                a.z[size_t(9 * i + kk) * W_ + sw] = zv;
+                                a.y[size_t(9 * i + kk) * W_ + sw] = yv;
                             }
                             s1 += f[0];
                         }
                         const bool gam = GAM && S.gam;
-                        a.z[size_t(9 * a.ms) * W_ + w] = gam ? a.gamma : fmaxf(float(s1), a.gamma);
-                        a.y[size_t(9 * a.ms) * W_ + w] = gam ? float(-lg) : 0.f;
+                        a.z[size_t(9 * a.ms) * W_ + sw] = gam ? a.gamma : fmaxf(float(s1), a.gamma);
+                        a.y[size_t(9 * a.ms) * W_ + sw] = gam ? float(-lg) : 0.f;
                     } else {
                         st |= kStPolishRej;
                         st &= ~kStPolished;
@@ -864,7 +877,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BODEX_F
                 // objective and forces from the returned point (FP64: the polished
                 // point, else the ADMM iterate)
                 auto xval = [&](int c) -> double {
-                    return polished ? (c < 3 * si.m ? W.x[c] : 0.0) : double(a.x[size_t(c) * W_ + w]);
+                    return polished ? (c < 3 * si.m ? W.x[c] : 0.0) : double(a.x[size_t(c) * W_ + sw]);
                 };
                 double r6[6];
 #pragma unroll
@@ -886,13 +899,13 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BODEX_F
                 Q = rr2 + double(a.eps) * ff;
                 if (a.resid) {
 #pragma unroll
-                    for (int k = 0; k < 6; ++k) a.resid[size_t(k) * W_ + w] = finite_in ? float(r6[k]) : NAN;
+                    for (int k = 0; k < 6; ++k) a.resid[size_t(k) * W_ + sw] = finite_in ? float(r6[k]) : NAN;
                 }
                 double rel = NAN;
                 if (finite_in) {
-                    const float* xs = a.x + w;
-                    const float* zs = a.z + w;
-                    const float* ys = a.y + w;
+                    const float* xs = a.x + sw;
+                    const float* zs = a.z + sw;
+                    const float* ys = a.y + sw;
                     rel = rel_kkt64<MM>(
                         Gs, muc, bt, si.m, double(a.eps), [&](int c) { return double(xs[size_t(c) * W_]); },
                         [&](int r) { return double(zs[size_t(r) * W_]); },
@@ -1034,7 +1047,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) co
         double Q = 0.0;
         if (act) {
             const double* Gs = P.G + size_t(slot) * NG;
-            const size_t W_ = size_t(a.W);
+            const size_t W_ = size_t(a.sW);  // state stride
+            const size_t sw = state_col(a, si, j);
             ConeData<MM, const double*, GAM> D;
             D.G = Gs;
             D.mu = P.muc + slot * 8;
@@ -1047,7 +1061,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) co
             bool polished = false;
             const bool finite_in = good && !(st & kStNonfinite);
             if (finite_in && a.polish) {
-                const float* zs = a.z + w;
+                const float* zs = a.z + sw;
                 cone_start<MM>(D, [&](int r) { return double(zs[size_t(r) * W_]); }, kConePull, W);
                 ConePolishOut po = cone_polish<MM>(D, kConeT0, kConeGap, kConeGrowth, kConeLoose, a.polish_steps, W);
                 if (po.status != 0) {
@@ -1083,20 +1097,20 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) co
 #pragma unroll
                         for (int c = 0; c < 3; ++c) {
                             const double fv = live ? W.f[3 * i + c] : 0.0;
-                            a.x[size_t(3 * i + c) * W_ + w] = float(fv);
-                            a.z[size_t(3 * i + c) * W_ + w] = float(fv);
-                            a.y[size_t(3 * i + c) * W_ + w] = live ? float(-g[c] - (c == 0 ? yg : 0.0)) : 0.f;
+                            a.x[size_t(3 * i + c) * W_ + sw] = float(fv);
+                            a.z[size_t(3 * i + c) * W_ + sw] = float(fv);
+                            a.y[size_t(3 * i + c) * W_ + sw] = live ? float(-g[c] - (c == 0 ? yg : 0.0)) : 0.f;
                         }
                     }
-                    a.z[size_t(3 * a.ms) * W_ + w] = fmaxf(float(s1), a.gamma);
-                    a.y[size_t(3 * a.ms) * W_ + w] = float(yg);
+                    a.z[size_t(3 * a.ms) * W_ + sw] = fmaxf(float(s1), a.gamma);
+                    a.y[size_t(3 * a.ms) * W_ + sw] = float(yg);
                 } else {
                     st |= kStPolishRej;
                     st &= ~kStPolished;
                 }
             }
             auto xval = [&](int c) -> double {
-                return polished ? (c < 3 * si.m ? W.f[c] : 0.0) : double(a.x[size_t(c) * W_ + w]);
+                return polished ? (c < 3 * si.m ? W.f[c] : 0.0) : double(a.x[size_t(c) * W_ + sw]);
             };
             double r6[6];
 #pragma unroll
@@ -1118,13 +1132,13 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) co
             Q = rr2 + double(a.eps) * ff;
             if (a.resid) {
 #pragma unroll
-                for (int k = 0; k < 6; ++k) a.resid[size_t(k) * W_ + w] = finite_in ? float(r6[k]) : NAN;
+                for (int k = 0; k < 6; ++k) a.resid[size_t(k) * W_ + sw] = finite_in ? float(r6[k]) : NAN;
             }
             double rel = NAN;
             if (finite_in) {
-                const float* xs = a.x + w;
-                const float* zs = a.z + w;
-                const float* ys = a.y + w;
+                const float* xs = a.x + sw;
+                const float* zs = a.z + sw;
+                const float* ys = a.y + sw;
                 rel = cone_rel_kkt64<MM>(
                     Gs, D.bt, si.m, double(a.eps), [&](int c) { return double(xs[size_t(c) * W_]); },
                     [&](int r) { return double(zs[size_t(r) * W_]); }, [&](int r) { return double(ys[size_t(r) * W_]); },
@@ -1188,7 +1202,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) ba
 #pragma unroll
             for (int r = 0; r < 6; ++r) tw[r] = a.wrench[size_t(w) * 6 + r];
 #pragma unroll
-            for (int c = 0; c < NV; ++c) f[c] = (c < 3 * a.ms) ? a.x[size_t(c) * a.W + w] : 0.0;
+            for (int c = 0; c < NV; ++c) f[c] = (c < 3 * a.ms) ? a.x[size_t(c) * a.sW + state_col(a, si, j)] : 0.0;
             double bt[6];
 #pragma unroll
             for (int r = 0; r < 6; ++r) bt[r] = double(a.beta) * tw[r];
@@ -1196,7 +1210,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) ba
                 const LdsPolishData<MM, GAM> D = polish_data<MM, GAM>(a, P, slot, si, bt);
                 PolishState<MM> PS;
                 PS.S.pc = projector_cache<MM>(P, lane);
-                const StridedY<MM> y0{a.y + w, size_t(a.W), a.ms};
+                const StridedY<MM> y0{a.y + state_col(a, si, j), size_t(a.sW), a.ms};
                 const PolishOut po = polish_qp<MM>(D, y0, a.polish_steps, W, PS);
                 if (po.status == 0) {
 #pragma unroll
@@ -1217,7 +1231,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) ba
                 for (int c = 0; c < NV; ++c) v += Gs[r * NV + c] * f[c];
                 // the stored residual carries the digits that G f - beta t
                 // loses to cancellation when formed from FP32 forces
-                if (a.resid) v = a.resid[size_t(r) * a.W + w];
+                if (a.resid) v = a.resid[size_t(r) * a.sW + state_col(a, si, j)];
                 rw[r] = 2.0 * om * v;
             }
 #pragma unroll

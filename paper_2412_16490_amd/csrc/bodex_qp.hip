@@ -375,6 +375,7 @@ KArgs make_args(const bodex_qp* h, const bodex_batch* in) {
     a.mu = in->mu;
     a.wrench = in->wrench_dir;
     a.W = in->n_qps;
+    a.sW = in->n_qps;
     a.ms = p.m_max;
     a.kappa = p.torque_scale;
     a.beta = p.beta;
@@ -434,11 +435,42 @@ int validate_batch(bodex_qp* h, const bodex_batch* in) {
     return 0;
 }
 
-// Upload counts | woff | perm | tile_start | queue(4) to `dst` via the pinned
-// staging buffer.  Returns 0 or an error.
-int upload_desc(bodex_qp* h, const bodex_batch* in, const Schedule& S, int* dst, size_t* n_ints_out) {
+// Descriptor ints: counts | woff | perm | tile_start | [qp_offset |
+// grasp_offset: with a pooled state layout] | queue(4).
+size_t desc_ints(int G, const Schedule& S, bool lay) {
+    return size_t(G) + (G + 1) + G + (S.n_tiles + 1) + (lay ? 2 * size_t(G) : 0) + 4;
+}
+
+// Whether st asks for a pooled state layout, and its validation (host
+// arrays, before any device work).
+int state_layout(bodex_qp* h, const bodex_batch* in, const bodex_state* st, bool* lay) {
+    *lay = false;
+    if (!st) return 0;
+    if (!st->qp_offset && !st->grasp_offset) return 0;
+    if (!st->qp_offset || !st->grasp_offset)
+        return fail(h, BODEX_EINVAL, "state qp_offset and grasp_offset must both be set or both NULL");
+    if (st->stride < 1 || st->rho_len < 1)
+        return fail(h, BODEX_EINVAL, "a pooled state needs stride >= 1 and rho_len >= 1");
+    for (int g = 0; g < in->n_grasps; ++g) {
+        const int s = in->wrench_offset[g + 1] - in->wrench_offset[g];
+        const long q = st->qp_offset[g];
+        if (q < 0 || q + s > st->stride)
+            return fail(h, BODEX_EINVAL, "state qp_offset[%d] = %ld with %d QPs outside [0, %d)", g, q, s,
+                        st->stride);
+        if (st->grasp_offset[g] < 0 || st->grasp_offset[g] >= st->rho_len)
+            return fail(h, BODEX_EINVAL, "state grasp_offset[%d] = %d outside [0, %d)", g, st->grasp_offset[g],
+                        st->rho_len);
+    }
+    *lay = true;
+    return 0;
+}
+
+// Upload the descriptor (desc_ints) to `dst` via the pinned staging buffer;
+// st: the pooled state layout or NULL.  Returns 0 or an error.
+int upload_desc(bodex_qp* h, const bodex_batch* in, const Schedule& S, int* dst, size_t* n_ints_out,
+                const bodex_state* st = nullptr) {
     const int G = in->n_grasps;
-    const size_t n = size_t(G) + (G + 1) + G + (S.n_tiles + 1) + 4;
+    const size_t n = desc_ints(G, S, st != nullptr);
     if (h->desc_pending) {
         HIP_TRY(h, hipEventSynchronize(h->desc_ev));
         h->desc_pending = false;
@@ -454,7 +486,11 @@ int upload_desc(bodex_qp* h, const bodex_batch* in, const Schedule& S, int* dst,
     std::memcpy(p + G, in->wrench_offset, sizeof(int) * (G + 1));
     std::memcpy(p + 2 * G + 1, S.perm.data(), sizeof(int) * G);
     std::memcpy(p + 3 * G + 1, S.tile_start.data(), sizeof(int) * (S.n_tiles + 1));
-    std::memset(p + 3 * G + 2 + S.n_tiles, 0, sizeof(int) * 4);
+    if (st) {
+        std::memcpy(p + 3 * G + 2 + S.n_tiles, st->qp_offset, sizeof(int) * G);
+        std::memcpy(p + 4 * G + 2 + S.n_tiles, st->grasp_offset, sizeof(int) * G);
+    }
+    std::memset(p + n - 4, 0, sizeof(int) * 4);
     HIP_TRY(h, hipMemcpyAsync(dst, p, n * sizeof(int), hipMemcpyHostToDevice, h->stream));
     HIP_TRY(h, hipEventRecord(h->desc_ev, h->stream));
     h->desc_pending = true;
@@ -462,13 +498,15 @@ int upload_desc(bodex_qp* h, const bodex_batch* in, const Schedule& S, int* dst,
     return 0;
 }
 
-void bind_desc(KArgs& a, const int* d, int G, const Schedule& S) {
+void bind_desc(KArgs& a, const int* d, int G, const Schedule& S, bool lay = false) {
     a.counts = d;
     a.woff = d + G;
     a.perm = d + 2 * G + 1;
     a.tile_start = d + 3 * G + 1;
     a.n_tiles = S.n_tiles;
     a.slots = S.slots;
+    a.sq = lay ? d + 3 * G + 2 + S.n_tiles : nullptr;
+    a.sg = lay ? a.sq + G : nullptr;
 }
 
 // Validate a hand batch (pointers only; device contents are not read).
@@ -604,6 +642,10 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
         return fail(h, BODEX_EINVAL, "state pointers must be all set or all NULL");
     if ((h->prm.flags & BODEX_F_WARM_START) && !have_state)
         return fail(h, BODEX_EINVAL, "warm start needs the caller's state");
+    bool lay = false;
+    rc = state_layout(h, in, &st, &lay);
+    if (rc) return rc;
+    if (lay && !have_state) return fail(h, BODEX_EINVAL, "a pooled state layout needs the state pointers");
     HIP_TRY(h, hipSetDevice(h->device));
 
     const int mm = kernel_mm(h->prm.m_max);
@@ -621,6 +663,7 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
         a.y = st.y;
         a.rho = st.rho;
         a.resid = st.r;
+        if (lay) a.sW = st.stride;
     } else {
         const size_t need = (size_t(W) * (nv + 2 * nr) + size_t(G)) * sizeof(float);
         rc = ensure_device(h, reinterpret_cast<void**>(&h->d_state), &h->d_state_cap, need);
@@ -659,7 +702,7 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
         grid_g = int((K + gpw - 1) / gpw);
     }
 
-    const size_t n_ints = size_t(G) * 3 + 1 + S.n_tiles + 1 + 4;
+    const size_t n_ints = desc_ints(G, S, lay);
     const bool timing = (h->prm.flags & BODEX_F_TIMING) != 0;
     const bool graph = (h->prm.flags & BODEX_F_GRAPH) != 0 && h->stream != nullptr;
     const size_t lds_a = admm_lds(mm, S.slots);
@@ -672,7 +715,7 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
     // Enqueue the launch sequence (reset counters, ADMM, finalize) for the
     // descriptors at d.
     auto enqueue = [&](int* d, bool with_events) -> int {
-        bind_desc(a, d, G, S);
+        bind_desc(a, d, G, S, lay);
         int* d_queue = d + (n_ints - 4);
         HIP_TRY(h, bodex::launch_reset(d_queue, 4, h->stream));
         KArgs aa = a;
@@ -709,7 +752,7 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
         rc = ensure_device(h, reinterpret_cast<void**>(&h->d_desc), &h->d_desc_cap, n_ints * sizeof(int));
         if (rc) return rc;
         size_t up = 0;
-        rc = upload_desc(h, in, S, h->d_desc, &up);
+        rc = upload_desc(h, in, S, h->d_desc, &up, lay ? &st : nullptr);
         if (rc) return rc;
         rc = enqueue(h->d_desc, timing);
         if (rc) return rc;
@@ -723,6 +766,10 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
     key = fnv1a(key, &G, sizeof(G));
     key = fnv1a(key, in->contact_count, sizeof(int) * G);
     key = fnv1a(key, in->wrench_offset, sizeof(int) * (G + 1));
+    if (lay) {
+        key = fnv1a(key, st.qp_offset, sizeof(int) * G);
+        key = fnv1a(key, st.grasp_offset, sizeof(int) * G);
+    }
     key = fnv1a(key, &a, sizeof(a));
     key = fnv1a(key, &h->prm, sizeof(h->prm));
     GraphEntry* hit = nullptr;
@@ -730,7 +777,7 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
     if (rc) return rc;
     if (!hit->exec) {
         size_t up = 0;
-        rc = upload_desc(h, in, S, hit->d_desc, &up);
+        rc = upload_desc(h, in, S, hit->d_desc, &up, lay ? &st : nullptr);
         if (rc) return rc;
         hipGraph_t gr = nullptr;
         HIP_TRY(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
@@ -769,6 +816,8 @@ int bodex_qp_solve_static(bodex_qp_t* h, const bodex_batch* in, bodex_result* ou
     const bodex_state& st = out->state;
     if (!(st.x && st.z && st.y && st.rho))
         return fail(h, BODEX_EINVAL, "bodex_qp_solve_static needs the caller's state (x, z, y, rho)");
+    if (st.qp_offset || st.grasp_offset)
+        return fail(h, BODEX_EUNSUP, "bodex_qp_solve_static takes the plain state layout only");
     // the plain schedule (consecutive grasps, at most kWave QPs and
     // kMaxSlots grasps per tile), built straight into the staging buffer
     const int* counts = in->contact_count;
@@ -861,6 +910,9 @@ int bodex_qp_backward(bodex_qp_t* h, const bodex_batch* in, const bodex_state* s
     if (!st || !st->x || !st->z || !st->y)
         return fail(h, BODEX_EINVAL, "backward needs the state written by a solve");
     if (!dL_dpoints || !dL_dnormals) return fail(h, BODEX_EINVAL, "gradient outputs are NULL");
+    bool lay = false;
+    rc = state_layout(h, in, st, &lay);
+    if (rc) return rc;
     HIP_TRY(h, hipSetDevice(h->device));
     const int mm = kernel_mm(h->prm.m_max);
     Schedule S;
@@ -871,18 +923,19 @@ int bodex_qp_backward(bodex_qp_t* h, const bodex_batch* in, const bodex_state* s
     a.y = st->y;
     a.rho = st->rho;
     a.resid = st->r;
+    if (lay) a.sW = st->stride;
     a.dLdE = dL_dE;
     a.dLdQ = dL_dQ;
     a.dP = dL_dpoints;
     a.dN = dL_dnormals;
     a.accumulate = accumulate ? 1 : 0;
-    const size_t n_ints = size_t(G) * 3 + 1 + S.n_tiles + 1 + 4;
+    const size_t n_ints = desc_ints(G, S, lay);
     rc = ensure_device(h, reinterpret_cast<void**>(&h->d_desc), &h->d_desc_cap, n_ints * sizeof(int));
     if (rc) return rc;
     size_t up = 0;
-    rc = upload_desc(h, in, S, h->d_desc, &up);
+    rc = upload_desc(h, in, S, h->d_desc, &up, lay ? st : nullptr);
     if (rc) return rc;
-    bind_desc(a, h->d_desc, G, S);
+    bind_desc(a, h->d_desc, G, S, lay);
     const size_t lds_b = fin_lds(mm, S.slots, true);
     a.queue = nullptr;
     const int grid_b = S.n_tiles;
@@ -1010,6 +1063,8 @@ int bodex_qp_descend(bodex_qp_t* h, const bodex_hand* hand, const bodex_batch* q
     if (qp->n_grasps != hand->n_grasps)
         return fail(h, BODEX_EINVAL, "qp->n_grasps %d != hand->n_grasps %d", qp->n_grasps, hand->n_grasps);
     if (d->iters < 0) return fail(h, BODEX_EINVAL, "iters %d < 0", d->iters);
+    if (out->state.qp_offset || out->state.grasp_offset)
+        return fail(h, BODEX_EUNSUP, "bodex_qp_descend takes the plain state layout only");
     const float fp[] = {d->w_qp, d->w_dist, d->radius, d->offset, d->step_rot, d->step_trans};
     for (float v : fp)
         if (!std::isfinite(v)) return fail(h, BODEX_EINVAL, "descent parameters must be finite");
@@ -1076,7 +1131,7 @@ int bodex_qp_descend(bodex_qp_t* h, const bodex_hand* hand, const bodex_batch* q
     a.iters = out->iters;
     a.status = out->status;
     a.pflops = out->polish_flops;
-    const size_t n_ints = size_t(G) * 3 + 1 + S.n_tiles + 1 + 4;
+    const size_t n_ints = desc_ints(G, S, false);
     const size_t lds_a = admm_lds(mm, S.slots);
     const size_t lds_f = cone ? bodex::cone_fin_lds(mm, S.slots, h->prm.gamma > 0.f) : fin_lds(mm, S.slots, false);
     const size_t lds_b = fin_lds(mm, S.slots, true);

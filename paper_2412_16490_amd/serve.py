@@ -11,11 +11,19 @@ seeded random walk of the synthetic stream).  The server
 * every tick gathers the next step of *all* active requests into one batch and
   launches one solve and one backward for it, so requests that arrived while
   others were on the GPU share the device with them;
-* keeps each request's ADMM state (x, z, y, rho) on the device between steps
-  and warm-starts the next step from it;
+* keeps each request's ADMM state (x, z, y, rho, and the wrench residual the
+  backward reads) on the device between steps, in a pool of columns the
+  request holds from admission to completion, and warm-starts the next step
+  from it: the tick passes the pool with per-grasp column offsets to the
+  solve and the backward, which read and write the state in place;
 * enqueues tick t+1 while tick t runs (stream order carries the dependency) and
   records each request's latency from arrival to the completion of its last
   step.
+
+Throughput counts only QP solves that end converged (relative KKT residual
+<= tol_rel).  The run also reports the offered load, the queue over time and
+the device time of each tick spent around its solve and backward (gathering
+the requests' inputs, moving their contact points).
 
 The solve of a grasp depends only on that grasp's inputs and state, so a
 request's results are the same alone and in a mix (tested).
@@ -32,6 +40,72 @@ import torch
 from . import api
 
 
+class _Ranges:
+    """First-fit allocator of contiguous index ranges in [0, n)."""
+
+    def __init__(self, n: int):
+        self.free = [(0, n)]
+
+    def take(self, k: int):
+        for i, (a, ln) in enumerate(self.free):
+            if ln >= k:
+                if ln == k:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (a + k, ln - k)
+                return a
+        return None
+
+    def give(self, a: int, k: int):
+        self.free.append((a, k))
+        self.free.sort()
+        merged = []
+        for b, ln in self.free:
+            if merged and merged[-1][0] + merged[-1][1] == b:
+                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
+            else:
+                merged.append((b, ln))
+        self.free = merged
+
+
+class _StatePool:
+    """The state of every active request in one set of device arrays: x [3 m][cap],
+    z, y [9 m + 1][cap], r [6][cap] (columns = QPs) and rho [cap_g]."""
+
+    def __init__(self, cap_q: int, cap_g: int, m_max: int, device):
+        nr = 9 * m_max + 1
+        f = dict(dtype=torch.float32, device=device)
+        self.x = torch.zeros((3 * m_max, cap_q), **f)
+        self.z = torch.zeros((nr, cap_q), **f)
+        self.y = torch.zeros((nr, cap_q), **f)
+        self.r = torch.zeros((6, cap_q), **f)
+        self.rho = torch.zeros((cap_g,), **f)
+        self.cols = _Ranges(cap_q)
+        self.slots = _Ranges(cap_g)
+
+    @staticmethod
+    def bytes_per(m_max: int):
+        """(bytes per QP column, bytes per grasp slot)."""
+        return (3 * m_max + 2 * (9 * m_max + 1) + 6) * 4, 4
+
+    def take(self, nq: int, ng: int):
+        q0 = self.cols.take(nq)
+        if q0 is None:
+            return None
+        g0 = self.slots.take(ng)
+        if g0 is None:
+            self.cols.give(q0, nq)
+            return None
+        for t in (self.x, self.z, self.y, self.r):
+            t[:, q0:q0 + nq].zero_()
+        self.rho[g0:g0 + ng].zero_()  # rho 0: the first step starts from rho0
+        return q0, g0
+
+    def give(self, q0: int, nq: int, g0: int, ng: int):
+        self.cols.give(q0, nq)
+        self.slots.give(g0, ng)
+
+
 @dataclasses.dataclass
 class _Active:
     rid: int
@@ -44,7 +118,8 @@ class _Active:
     normals: torch.Tensor
     mu: torch.Tensor
     wrench: torch.Tensor
-    state: dict
+    q0: int        # first state column in the pool
+    g0: int        # first rho slot in the pool
     walk: torch.Tensor | None
     nbytes: int
     energy: torch.Tensor | None = None
@@ -55,12 +130,17 @@ class _Active:
 
 
 def request_bytes(n_grasps: int, n_qps: int, m_max: int) -> int:
-    """Device bytes a request holds while active (inputs, state, outputs,
-    and its share of the gathered tick batch)."""
+    """Device bytes a request holds while active outside the state pool
+    (inputs and its share of the gathered tick batch: inputs, outputs,
+    gradients); its state columns come from the pool."""
     inputs = n_grasps * m_max * 7 * 4 + n_qps * 6 * 4
-    state = api.bodex_qp_state_bytes(n_grasps, n_qps, m_max)
     outputs = n_qps * (3 * m_max + 4) * 4 + n_grasps * 4 + 2 * n_grasps * m_max * 3 * 4
-    return 2 * (inputs + state + outputs)
+    return 2 * inputs + outputs
+
+
+# share of the HBM budget given to the state pool (a QP's state columns take
+# about three times the bytes of its inputs, outputs and tick buffers)
+POOL_SHARE = 0.75
 
 
 class Server:
@@ -72,7 +152,11 @@ class Server:
         p.flags |= api.F_WARM_START
         self.m_max = p.m_max
         self.solver = api.Solver(p, device=device, stream=self.stream.cuda_stream)
-        self.budget = int(budget_bytes)
+        bq, bg = _StatePool.bytes_per(self.m_max)
+        pool_bytes = int(POOL_SHARE * budget_bytes)
+        cap_q = max(64, pool_bytes // (bq + bg // 4))
+        self.pool = _StatePool(cap_q, max(16, cap_q // 4), self.m_max, self.device)
+        self.budget = int(budget_bytes) - pool_bytes
         self.in_use = 0
         self.max_inflight = max_inflight_ticks
         self.waiting: deque = deque()
@@ -84,6 +168,11 @@ class Server:
         self.ticks = 0
         self.peak_in_use = 0
         self.keep_results = False
+        self._conv = []         # per tick: converged QPs (device scalars)
+        self._copy_ev = []      # per tick: events before/after the gather, after the backward, at the end
+        self.queue_trace = []   # (time, waiting, active, bytes in use) per tick
+        self.progress_every = 0.0
+        self._ones = torch.ones(1, device=self.device)
 
     # -- admission -----------------------------------------------------------
     def submit(self, req, now: float | None = None, keep_walk=True):
@@ -95,10 +184,15 @@ class Server:
             req, keep_walk = self.waiting[0]
             b = req.batch
             nb = request_bytes(b.n_grasps, b.n_qps, self.m_max)
-            if nb > self.budget:
-                raise ValueError("request %d needs %d bytes, budget is %d" % (req.rid, nb, self.budget))
+            if nb > self.budget or b.n_qps > self.pool.x.shape[1] or b.n_grasps > self.pool.rho.shape[0]:
+                raise ValueError("request %d needs %d bytes and %d state columns; budget %d bytes, pool %d columns"
+                                 % (req.rid, nb, b.n_qps, self.budget, self.pool.x.shape[1]))
             if self.in_use + nb > self.budget:
                 return
+            with torch.cuda.stream(self.stream):
+                got = self.pool.take(b.n_qps, b.n_grasps)
+            if got is None:
+                return  # waits for state columns to free up
             self.waiting.popleft()
             with torch.cuda.stream(self.stream):
                 dev = self.device
@@ -110,7 +204,7 @@ class Server:
                     normals=torch.as_tensor(b.normals, device=dev),
                     mu=torch.as_tensor(b.mu, device=dev),
                     wrench=torch.as_tensor(b.wrench, device=dev),
-                    state=api.new_state(b.n_grasps, b.n_qps, self.m_max, device=dev),
+                    q0=got[0], g0=got[1],
                     walk=torch.as_tensor(req.walk, device=dev) if keep_walk and req.walk is not None else None,
                     nbytes=nb)
             self.in_use += nb
@@ -123,6 +217,8 @@ class Server:
         if not acts:
             return
         with torch.cuda.stream(self.stream):
+            evs = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            evs[0].record(self.stream)
             counts = np.concatenate([a.counts for a in acts])
             woffs = [0]
             for a in acts:
@@ -132,26 +228,33 @@ class Server:
             nrm = torch.cat([a.normals for a in acts])
             mu = torch.cat([a.mu for a in acts])
             wr = torch.cat([a.wrench for a in acts])
-            st = {k: torch.cat([a.state[k] for a in acts], dim=(0 if k == "rho" else 1)).contiguous()
-                  for k in ("x", "z", "y", "rho")}
+            # the pool with each grasp's state columns (its requests' ranges)
+            qoff = np.concatenate([a.q0 + a.woff[:-1] for a in acts]).astype(np.int32)
+            goff = np.concatenate([a.g0 + np.arange(a.counts.shape[0]) for a in acts]).astype(np.int32)
+            P = self.pool
+            st = {"x": P.x, "z": P.z, "y": P.y, "rho": P.rho, "r": P.r, "qp_offset": qoff, "grasp_offset": goff}
             tb = _Batch(pts, nrm, mu, wr, counts, woff)
             res = api.new_result(tb.n_grasps, tb.n_qps, self.m_max, device=self.device)
+            evs[1].record(self.stream)
             self.solver.solve(tb, state=st, result=res)
-            gp = torch.zeros_like(pts)
-            gn = torch.zeros_like(nrm)
-            ones = torch.ones(tb.n_grasps, device=self.device)
-            self.solver.backward(tb, st, dL_dE=ones, out=(gp, gn))
-            # scatter state and advance every request by one step
+            # the backward overwrites every entry of its outputs
+            gp = torch.empty_like(pts)
+            gn = torch.empty_like(nrm)
+            if self._ones.shape[0] < tb.n_grasps:
+                self._ones = torch.ones(2 * tb.n_grasps, device=self.device)
+            self.solver.backward(tb, st, dL_dE=self._ones[:tb.n_grasps], out=(gp, gn))
+            self._conv.append(((res["status"] & api.ST_CONVERGED) != 0).sum())
+            evs[2].record(self.stream)
+            # advance every request by one step: the random walk of its
+            # contact points (one multi-tensor add for all of them)
+            walkers = [a for a in acts if a.walk is not None and a.done_steps < a.walk.shape[0]]
+            if walkers:
+                torch._foreach_add_([a.points for a in walkers], [a.walk[a.done_steps] for a in walkers])
             g0 = 0
             w0 = 0
             finishing = []
             for a in acts:
                 G, W = a.counts.shape[0], int(a.woff[-1])
-                for k in ("x", "z", "y"):
-                    a.state[k].copy_(st[k][:, w0:w0 + W])
-                a.state["rho"].copy_(st["rho"][g0:g0 + G])
-                if a.walk is not None and a.done_steps < a.walk.shape[0]:
-                    a.points.add_(a.walk[a.done_steps])
                 a.done_steps += 1
                 if a.done_steps == a.steps:
                     if self.keep_results:
@@ -162,10 +265,13 @@ class Server:
                     finishing.append(a)
                 g0 += G
                 w0 += W
+            evs[3].record(self.stream)
             ev = torch.cuda.Event()
             ev.record(self.stream)
+        self._copy_ev.append(evs)
         self.qp_solves += tb.n_qps
         self.ticks += 1
+        self.queue_trace.append((time.perf_counter() - self._t0, len(self.waiting), len(self.active), self.in_use))
         self.inflight.append((ev, finishing))
         for a in finishing:
             self.active.remove(a)
@@ -181,6 +287,7 @@ class Server:
             for a in finishing:
                 self.latency[a.rid] = t - a.arrival
                 self.in_use -= a.nbytes
+                self.pool.give(a.q0, int(a.woff[-1]), a.g0, int(a.counts.shape[0]))
                 if self.keep_results:
                     self.results[a.rid] = {"energy": a.energy.cpu().numpy(), "qp_obj": a.qobj.cpu().numpy(),
                                            "forces": a.forces.cpu().numpy(),
@@ -191,9 +298,16 @@ class Server:
         """Serve an iterable of requests sorted by arrival.  With realtime the
         arrivals follow the wall clock from the start of the run."""
         reqs = deque(requests)
+        offered = sum(r.batch.n_qps * r.steps for r in reqs)
+        span = reqs[-1].arrival if reqs else 0.0
         self._t0 = time.perf_counter()
+        next_note = self.progress_every
         while reqs or self.waiting or self.active or self.inflight:
             now = time.perf_counter() - self._t0
+            if self.progress_every and now >= next_note:
+                print("serve: t=%.0f s, %d finished, %d waiting, %d active, %d ticks" % (
+                    now, len(self.latency), len(self.waiting), len(self.active), self.ticks), flush=True)
+                next_note += self.progress_every
             while reqs and (not realtime or reqs[0].arrival <= now):
                 self.submit(reqs.popleft())
             self._reap(block=False)
@@ -205,15 +319,35 @@ class Server:
             elif reqs and realtime:
                 time.sleep(max(0.0, min(0.001, reqs[0].arrival - now)))
         wall = time.perf_counter() - self._t0
+        torch.cuda.synchronize(self.device)
+        conv = int(sum(int(c.item()) for c in self._conv))
+        copy_ms = sum(e[0].elapsed_time(e[1]) + e[2].elapsed_time(e[3]) for e in self._copy_ev)
+        tick_ms = sum(e[0].elapsed_time(e[3]) for e in self._copy_ev)
         lat = np.array([self.latency[k] for k in sorted(self.latency)])
-        return {"requests": len(lat), "wall_s": wall, "qp_solves": self.qp_solves, "ticks": self.ticks,
-                "qps_per_s": self.qp_solves / wall,
+        qt = np.array(self.queue_trace) if self.queue_trace else np.zeros((0, 4))
+        return {"requests": len(lat), "wall_s": wall, "arrival_span_s": span, "qp_solves": self.qp_solves,
+                "qp_solves_converged": conv, "ticks": self.ticks,
+                "qps_per_s": conv / wall, "offered_qp_solves_per_s": offered / max(span, 1e-9),
+                "keeps_up": bool(conv / wall >= 0.95 * offered / max(span, 1e-9)),
                 "latency_p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
                 "latency_p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
+                "around_solve_ms": copy_ms, "tick_device_ms": tick_ms,
+                "around_solve_fraction": copy_ms / max(tick_ms, 1e-9),
+                "queue_waiting_max": int(qt[:, 1].max()) if len(qt) else 0,
+                "queue_waiting_at": _queue_samples(qt),
                 "peak_device_bytes": self.peak_in_use}
 
     def close(self):
         self.solver.close()
+
+
+def _queue_samples(qt, n=8):
+    """Waiting requests at n evenly spaced times of the run."""
+    if len(qt) == 0:
+        return []
+    times = np.linspace(qt[0, 0], qt[-1, 0], n)
+    idx = np.searchsorted(qt[:, 0], times, side="right") - 1
+    return [[round(float(t), 2), int(qt[max(i, 0), 1])] for t, i in zip(times, idx)]
 
 
 class _Batch(api.DeviceBatch):
@@ -240,6 +374,7 @@ def serve_fifo_plain(requests, m_max=5, s_max=32, realtime=True):
     t0 = time.perf_counter()
     lat = []
     solves = 0
+    conv = []
     while reqs:
         r = reqs.popleft()
         now = time.perf_counter() - t0
@@ -256,6 +391,7 @@ def serve_fifo_plain(requests, m_max=5, s_max=32, realtime=True):
             for k in range(r.steps):
                 res = solver.solve(db, state=st)
                 solver.backward(db, st, dL_dE=ones, out=(gp, gn))
+                conv.append(((res["status"] & api.ST_CONVERGED) != 0).sum())
                 if walk is not None:
                     db.points.add_(walk[k])
                 solves += db.n_qps
@@ -264,5 +400,7 @@ def serve_fifo_plain(requests, m_max=5, s_max=32, realtime=True):
     wall = time.perf_counter() - t0
     solver.close()
     lat = np.asarray(lat)
-    return {"requests": len(lat), "wall_s": wall, "qp_solves": solves, "qps_per_s": solves / wall,
+    nconv = int(sum(int(c.item()) for c in conv))
+    return {"requests": len(lat), "wall_s": wall, "qp_solves": solves, "qp_solves_converged": nconv,
+            "qps_per_s": nconv / wall,
             "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99))}

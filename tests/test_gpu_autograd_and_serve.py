@@ -85,14 +85,61 @@ def test_served_step_matches_oracle_after_random_walk():
 
 
 def test_budget_admission_queues_instead_of_failing():
-    from paper_2412_16490_amd.serve import Server, request_bytes
+    from paper_2412_16490_amd.serve import POOL_SHARE, Server, _StatePool, request_bytes
     reqs = _stream(5, steps=2, seed=11)
     biggest = max(request_bytes(r.batch.n_grasps, r.batch.n_qps, 5) for r in reqs)
-    srv = Server(m_max=5, s_max=32, budget_bytes=biggest)      # room for about one at a time
+    most_qps = max(r.batch.n_qps for r in reqs)
+    bq, bg = _StatePool.bytes_per(5)
+    # room for about one request at a time, in the per-request budget and in
+    # the state pool
+    budget = int(1.05 * max(biggest / (1 - POOL_SHARE), (bq + bg / 4) * most_qps / POOL_SHARE))
+    srv = Server(m_max=5, s_max=32, budget_bytes=budget)
     stats = srv.run(reqs, realtime=False)
     assert stats["requests"] == 5
-    assert stats["peak_device_bytes"] <= biggest
+    assert stats["peak_device_bytes"] <= budget - int(POOL_SHARE * budget)
     srv.close()
+
+
+def test_state_pool_layout_equals_the_plain_state():
+    # the solve and the backward on a state pool (per-grasp column offsets,
+    # grasps scattered over the pool in another order) give the same bits as
+    # on a plain state, warm-started the same way
+    import torch
+    b = wl.config(3, 120)
+    db = api.DeviceBatch(b)
+    G, W = db.n_grasps, db.n_qps
+    s = api.Solver(api.default_params(m_max=5, s_max=32))
+    sw = api.Solver(api.default_params(m_max=5, s_max=32, flags_set=api.F_WARM_START))
+    plain = api.new_state(G, W, 5)
+    cap_q, cap_g = 3 * W, 3 * G
+    pool = api.new_state(cap_g, cap_q, 5)
+    rng = np.random.default_rng(5)
+    order = rng.permutation(G)
+    s_of = np.diff(b.woff)
+    qoff = np.zeros(G, np.int32)
+    col = 7
+    for g in order:             # grasps placed in a shuffled order with gaps
+        qoff[g] = col
+        col += int(s_of[g]) + int(rng.integers(0, 4))
+    assert col <= cap_q
+    goff = (2 * rng.permutation(G) + 1).astype(np.int32)
+    pooled = dict(pool, qp_offset=qoff, grasp_offset=goff)
+    outs = []
+    for st, solver_cold in ((plain, s), (pooled, s)):
+        r1 = solver_cold.solve(db, state=st)
+        r2 = sw.solve(db, state=st)            # a warm-started second step
+        gp, gn = sw.backward(db, st, dL_dE=torch.ones(G, device="cuda"))
+        torch.cuda.synchronize()
+        outs.append([t.cpu().numpy() for t in (r1["forces"], r2["forces"], r2["qp_obj"], r2["iters"],
+                                               r2["status"], gp, gn)])
+    for a_, b_ in zip(*outs):
+        np.testing.assert_array_equal(a_, b_)
+    # the pooled columns hold the plain state's columns
+    cols = np.concatenate([qoff[g] + np.arange(s_of[g]) for g in range(G)])
+    np.testing.assert_array_equal(pool["x"][:, cols].cpu().numpy(), plain["x"].cpu().numpy())
+    np.testing.assert_array_equal(pool["rho"][goff].cpu().numpy(), plain["rho"].cpu().numpy())
+    s.close()
+    sw.close()
 
 
 def test_autotuner_picks_a_converged_configuration(tmp_path):
