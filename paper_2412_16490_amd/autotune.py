@@ -31,7 +31,7 @@ import numpy as np
 from . import api
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "bodex_qp_autotune.json")
-DEFAULT_GRID = {"polish_chunk": [0, 1, 4, 8, 12, 16, 20, 24], "admm_waves": [2, 3], "batched": [0, 1]}
+DEFAULT_GRID = {"polish_chunk": [0, 1, 4, 8, 12, 16, 20, 24], "admm_waves": [1, 2, 3], "batched": [0, 1]}
 
 
 def shape_key(device_name: str, batch: api.DeviceBatch) -> str:

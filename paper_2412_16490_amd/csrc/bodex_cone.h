@@ -7,10 +7,12 @@
 // has 3 MM + 1 rows: rows 3i..3i+2 contact i's force, row 3 MM the
 // normal-sum row.  The projection onto the constraint set is per contact
 // onto the truncated cone (closed form, below) and a clamp for the sum row.
-// The FP64 polish is a Newton (SQP) iteration on the contacts' identified
-// state (free, on the cone surface, on the normal bound, on the rim where
-// both meet, or at the apex), corrected one contact at a time until the KKT
-// conditions hold.
+// The FP64 polish is a primal log-barrier method warm-started from the ADMM
+// point: per barrier weight t, damped Newton steps on t Q(f) + phi(f) with
+// phi = -sum_i log(mu_i^2 f_i1^2 - |f_it|^2) - sum_i log(fmax - f_i1)
+// [- log(sum_i f_i1 - gamma)], each solving the dense 3m x 3m system
+// t 2 (G^T G + eps I) + Hess(phi) (scaled symmetrically by its diagonal, then
+// Cholesky), until the duality-gap bound nu / t is below the target.
 #pragma once
 
 #include "bodex_math.h"

@@ -29,8 +29,8 @@ CSRC = os.path.join(HERE, "csrc")
 # figure is reported only while these files are unchanged.
 KERNEL_FILES = {
     "admm": ("bodex_math.h", "bodex_cone.h", "bodex_kernels.h", "k_admm.hip", "bodex_qp.hip"),
-    "finalize": ("bodex_math.h", "bodex_cone.h", "bodex_kernels.h", "k_finalize.hip", "k_finalize_sum.hip",
-                 "bodex_qp.hip"),
+    "finalize": ("bodex_math.h", "bodex_cone.h", "bodex_gpolish.h", "bodex_kernels.h", "k_finalize.hip",
+                 "k_finalize_sum.hip", "k_finalize_chunk.hip", "k_gpolish.hip", "bodex_qp.hip"),
     "cone_finalize": ("bodex_math.h", "bodex_cone.h", "bodex_kernels.h", "k_finalize_cone.hip", "bodex_qp.hip"),
     "detach": ("bodex_launch.h", "k_detach.hip"),
 }
@@ -80,23 +80,29 @@ def _counter(db, counter, substr):
 
 
 def traffic(a):
-    f = _counter(a.fetch, "FETCH_SIZE", a.kernel)
-    w = _counter(a.write, "WRITE_SIZE", a.kernel)
+    # --kernel may list several name substrings separated by '+': the launches
+    # that together make one unit (their per-dispatch medians add)
+    subs = [k.strip() for k in a.kernel.split("+") if k.strip()]
+    fs = [_counter(a.fetch, "FETCH_SIZE", k) for k in subs]
+    ws = [_counter(a.write, "WRITE_SIZE", k) for k in subs]
     cf = _counter(a.copy_fetch, "FETCH_SIZE", a.copy_kernel)
     cw = _counter(a.copy_write, "WRITE_SIZE", a.copy_kernel)
     kib = 1024.0
     sf = a.copy_bytes / (statistics.median(cf) * kib)
     sw = a.copy_bytes / (statistics.median(cw) * kib)
-    fetch_b = statistics.median(f) * kib * sf
-    write_b = statistics.median(w) * kib * sw
+    f_kib = sum(statistics.median(v) for v in fs)
+    w_kib = sum(statistics.median(v) for v in ws)
+    fetch_b = f_kib * kib * sf
+    write_b = w_kib * kib * sw
     print("# HBM traffic of %s (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE)" % a.kernel)
     print("# command: %s" % a.command)
     print("# counters are KiB per dispatch; scaled by a %d-byte device copy (%s)" % (a.copy_bytes, a.copy_kernel))
     print("kernel: %s" % a.kernel)
-    print("dispatches_fetch: %d" % len(f))
-    print("dispatches_write: %d" % len(w))
-    print("fetch_kib_median: %.1f" % statistics.median(f))
-    print("write_kib_median: %.1f" % statistics.median(w))
+    for k, fv, wv in zip(subs, fs, ws):
+        print("part: %s  dispatches %d/%d  fetch_kib_median %.1f  write_kib_median %.1f" % (
+            k, len(fv), len(wv), statistics.median(fv), statistics.median(wv)))
+    print("fetch_kib_median: %.1f" % f_kib)
+    print("write_kib_median: %.1f" % w_kib)
     print("copy_fetch_scale: %.4f" % sf)
     print("copy_write_scale: %.4f" % sw)
     print("fetch_bytes_per_launch: %.0f" % fetch_b)
