@@ -28,7 +28,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB names another library path and ORACLE_CFLAGS adds compiler
+# flags (a sanitizer build of the same source, kept apart from the default)
+_LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
+_EXTRA = os.environ.get("ORACLE_CFLAGS", "").split()
 _lock = threading.Lock()
 _lib = None
 
@@ -42,7 +45,7 @@ def build(force: bool = True) -> str:
     tmp = _LIB_PATH + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-D_GNU_SOURCE",
            "-ffp-contract=off", "-Wall", "-Wextra", "-Wno-unused-parameter",
-           _SRC, "-o", tmp, "-lm", "-lpthread"]
+           *_EXTRA, _SRC, "-o", tmp, "-lm", "-lpthread"]
     subprocess.check_call(cmd)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH

@@ -8,11 +8,11 @@ GPU kernels use) against independent references:
 """
 import ctypes
 import os
-import subprocess
 
 import numpy as np
 import pytest
 
+import host_build
 from oracle import cone as oc
 import oracle
 from paper_2412_16490_amd import workload as wl
@@ -25,8 +25,7 @@ _D = ctypes.POINTER(ctypes.c_double)
 @pytest.fixture(scope="module")
 def host(tmp_path_factory):
     out = str(tmp_path_factory.mktemp("cone_host") / "libcone_host.so")
-    subprocess.check_call(["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
-                           os.path.join(HERE, "cone_host.cpp"), "-o", out])
+    host_build.build(os.path.join(HERE, "cone_host.cpp"), out)
     return ctypes.CDLL(out)
 
 

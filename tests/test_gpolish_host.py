@@ -7,11 +7,11 @@ result must be the oracle's minimiser, and a QP the group finishes keeps the
 counts of its first part."""
 import ctypes
 import os
-import subprocess
 
 import numpy as np
 import pytest
 
+import host_build
 import oracle
 from paper_2412_16490_amd import workload as wl
 
@@ -21,8 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 @pytest.fixture(scope="module")
 def host(tmp_path_factory):
     out = str(tmp_path_factory.mktemp("gpolish_host") / "libgpolish_host.so")
-    subprocess.check_call(["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-ffp-contract=off", "-pthread",
-                           os.path.join(HERE, "gpolish_host.cpp"), "-o", out])
+    host_build.build(os.path.join(HERE, "gpolish_host.cpp"), out, extra=["-pthread"])
     return ctypes.CDLL(out)
 
 

@@ -5,10 +5,11 @@ Jacobian-transposed products against the oracle's implicit-function Jacobians,
 the medial ridge and the centre, and the Rodrigues exponential."""
 import ctypes
 import os
-import subprocess
 
 import numpy as np
 import pytest
+
+import host_build
 
 from oracle import coarse as oc
 
@@ -19,8 +20,7 @@ _D = ctypes.POINTER(ctypes.c_double)
 @pytest.fixture(scope="module")
 def host(tmp_path_factory):
     out = str(tmp_path_factory.mktemp("hand_host") / "libhand_host.so")
-    subprocess.check_call(["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
-                           os.path.join(HERE, "hand_host.cpp"), "-o", out])
+    host_build.build(os.path.join(HERE, "hand_host.cpp"), out)
     L = ctypes.CDLL(out)
     L.host_nearest.restype = ctypes.c_int
     return L

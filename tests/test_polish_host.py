@@ -4,11 +4,11 @@ deliberately poor warm guess it must reach the oracle's minimiser, and the
 run-time facet coefficients must equal cos/sin of (2k+1) pi / 8."""
 import ctypes
 import os
-import subprocess
 
 import numpy as np
 import pytest
 
+import host_build
 import oracle
 from paper_2412_16490_amd import workload as wl
 
@@ -18,8 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 @pytest.fixture(scope="module")
 def host(tmp_path_factory):
     out = str(tmp_path_factory.mktemp("polish_host") / "libpolish_host.so")
-    subprocess.check_call(["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
-                           os.path.join(HERE, "polish_host.cpp"), "-o", out])
+    host_build.build(os.path.join(HERE, "polish_host.cpp"), out)
     lib = ctypes.CDLL(out)
     return lib
 
