@@ -4,127 +4,16 @@
 // continues from the record with GS threads standing in for the GS lanes of
 // a group (each group operation is a barrier plus a reduction in lane order,
 // the same value in every thread).
-#include <condition_variable>
 #include <cstring>
-#include <mutex>
 #include <thread>
 #include <vector>
 
 #include "../paper_2412_16490_amd/csrc/bodex_gpolish.h"
+#include "host_team.h"
 
 using namespace bodex;
 
 namespace {
-
-// GS threads of one group: shared slots, a barrier with a generation count.
-struct Shared {
-    int n;
-    std::mutex mu;
-    std::condition_variable cv;
-    int waiting = 0;
-    long gen = 0;
-    double d[8][32];
-    int i[8][4];
-    explicit Shared(int n_) : n(n_) {}
-    void barrier() {
-        std::unique_lock<std::mutex> lk(mu);
-        const long g = gen;
-        if (++waiting == n) {
-            waiting = 0;
-            ++gen;
-            cv.notify_all();
-        } else {
-            cv.wait(lk, [&] { return gen != g; });
-        }
-    }
-};
-
-template <int GS>
-struct HostTeam {
-    int sub;
-    Shared* S;
-    double sum(double v) const {
-        S->d[sub][0] = v;
-        S->barrier();
-        double r = 0.0;
-        for (int l = 0; l < GS; ++l) r += S->d[l][0];
-        S->barrier();
-        return r;
-    }
-    template <int N>
-    void sum(double (&v)[N]) const {
-        static_assert(N <= 32, "slot size");
-        for (int j = 0; j < N; ++j) S->d[sub][j] = v[j];
-        S->barrier();
-        for (int j = 0; j < N; ++j) {
-            double r = 0.0;
-            for (int l = 0; l < GS; ++l) r += S->d[l][j];
-            v[j] = r;
-        }
-        S->barrier();
-    }
-    double max(double v) const {
-        S->d[sub][0] = v;
-        S->barrier();
-        double r = S->d[0][0];
-        for (int l = 1; l < GS; ++l) r = fmax(r, S->d[l][0]);
-        S->barrier();
-        return r;
-    }
-    void argmax(double& v, int& idx) const {
-        S->d[sub][0] = v;
-        S->i[sub][0] = idx;
-        S->barrier();
-        for (int l = 0; l < GS; ++l) {
-            const double ov = S->d[l][0];
-            const int oi = S->i[l][0];
-            if (ov > v || (ov == v && unsigned(oi) < unsigned(idx))) {
-                v = ov;
-                idx = oi;
-            }
-        }
-        S->barrier();
-    }
-    void argmin_frac(double& tn, double& td, int& idx) const {
-        S->d[sub][0] = tn;
-        S->d[sub][1] = td;
-        S->i[sub][0] = idx;
-        S->barrier();
-        for (int l = 0; l < GS; ++l) {
-            const double on = S->d[l][0], od = S->d[l][1];
-            const int oi = S->i[l][0];
-            const double a = on * td, b = tn * od;
-            if (a < b || (a == b && unsigned(oi) < unsigned(idx))) {
-                tn = on;
-                td = od;
-                idx = oi;
-            }
-        }
-        S->barrier();
-    }
-    double bcast(double v, int src) const {
-        S->d[sub][0] = v;
-        S->barrier();
-        const double r = S->d[src][0];
-        S->barrier();
-        return r;
-    }
-    int bcast(int v, int src) const {
-        S->i[sub][0] = v;
-        S->barrier();
-        const int r = S->i[src][0];
-        S->barrier();
-        return r;
-    }
-    unsigned bor(unsigned v) const {
-        S->i[sub][0] = int(v);
-        S->barrier();
-        unsigned r = 0u;
-        for (int l = 0; l < GS; ++l) r |= unsigned(S->i[l][0]);
-        S->barrier();
-        return r;
-    }
-};
 
 constexpr int MM = 5, NV = 15, GS = 8;
 
