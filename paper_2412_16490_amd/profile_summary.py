@@ -3,6 +3,10 @@
   python -m paper_2412_16490_amd.profile_summary kernels DB --command CMD
       per-kernel call count, total / average / min / max duration
 
+  python -m paper_2412_16490_amd.profile_summary counters DB --kernel SUBSTR [--kernel ...] --command CMD
+      median per dispatch of every counter of a --pmc run (and the VALU busy
+      fraction when SQ_ACTIVE_INST_VALU and GRBM_GUI_ACTIVE were collected)
+
   python -m paper_2412_16490_amd.profile_summary traffic --name NAME --kernel SUBSTR \\
       --fetch DB --write DB --copy-fetch DB --copy-write DB --copy-bytes N --command CMD
       HBM bytes per launch of the kernels whose name contains SUBSTR:
@@ -111,12 +115,43 @@ def traffic(a):
     print("source_hash: %s" % kernel_source_hash(a.name))
 
 
+def counters(db, command, substrs):
+    """Median per dispatch of every counter in a --pmc run, for the kernels
+    whose names contain one of the substrings."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select dispatch_id, kernel_name, counter_name, value from counters_collection").fetchall()
+    con.close()
+    per = {}
+    for did, name, cname, val in rows:
+        if any(sub in name for sub in substrs):
+            per.setdefault(name, {}).setdefault(cname, {}).setdefault(did, 0.0)
+            per[name][cname][did] += float(val)
+    print("# rocprofv3 --pmc counters per dispatch (median over dispatches, summed over instances)")
+    print("# command: %s" % command)
+    for name in sorted(per):
+        first = next(iter(per[name].values()))
+        print("kernel: %s" % name.split("(")[0])
+        print("dispatches: %d" % len(first))
+        med = {c: statistics.median(v.values()) for c, v in per[name].items()}
+        for cname in sorted(med):
+            print("  %-24s %.4g" % (cname, med[cname]))
+        if "SQ_ACTIVE_INST_VALU" in med and med.get("GRBM_GUI_ACTIVE"):
+            # GRBM_GUI_ACTIVE sums the busy cycles of the 8 XCDs; a VALU
+            # instruction occupies its SIMD 4 cycles
+            print("  %-24s %.3f   (4 SQ_ACTIVE_INST_VALU / (1024 SIMDs x GRBM_GUI_ACTIVE / 8))" % (
+                "valu_busy", 4.0 * med["SQ_ACTIVE_INST_VALU"] / (1024.0 * med["GRBM_GUI_ACTIVE"] / 8.0)))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
     k = sub.add_parser("kernels")
     k.add_argument("db")
     k.add_argument("--command", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("db")
+    c.add_argument("--kernel", action="append", required=True)
+    c.add_argument("--command", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("--name", required=True, choices=sorted(KERNEL_FILES))
     t.add_argument("--kernel", required=True)
@@ -130,6 +165,8 @@ def main():
     a = ap.parse_args()
     if a.what == "kernels":
         kernels(a.db, a.command)
+    elif a.what == "counters":
+        counters(a.db, a.command, a.kernel)
     else:
         traffic(a)
 
