@@ -117,7 +117,7 @@ typedef struct {
                           /* parallel polish (a group of lanes, one per       */
                           /* contact); 0 = every polish ends in the one-lane  */
                           /* kernel; -1 = chosen by the number of QPs (1 up   */
-                          /* to 40,960, 12 up to 98,304, else 20).  Used with */
+                          /* to 40,960, 16 up to 98,304, else 20).  Used with */
                           /* BODEX_F_POLISH, the pyramid and gamma = 0.       */
     unsigned flags;       /* BODEX_F_*                                        */
     int admm_waves;       /* ADMM kernel register budget as resident waves   */

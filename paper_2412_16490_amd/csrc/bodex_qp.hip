@@ -318,14 +318,15 @@ int graph_entry(bodex_qp* h, uint64_t key, size_t n_ints, GraphEntry** out) {
 enum class Kind { Admm, Fin, Bwd };
 
 constexpr int kDefaultAdmmWaves = 2;
-// polish_chunk -1 (the default): the chunk by batch size.  Measured at 16
+// polish_chunk -1 (the default): the chunk by batch size.  Measured at 256
 // to 8192 grasps x 16 wrenches (5 contacts): the contact-parallel polish
-// alone (chunk 1) is ~2.8x faster than the one-lane polish up to 256 grasps
-// and 1.4x at 2048, where its latency wins; at 8192 the one-lane pass is
-// needed for throughput and a budget of 20 factorisations leaves the
-// contact-parallel kernel only the slowest QPs (0.97x the one-lane time).
+// alone (chunk 1) is 2.8x faster than the one-lane polish at 256 grasps,
+// 1.9x at 1024 and 1.4x at 2048, where its latency wins; from 4096 grasps
+// the one-lane pass is needed for throughput and a budget of 16 (4096) or 20
+// (8192) factorisations leaves the contact-parallel kernel only the slowest
+// QPs (0.89x and 0.98x the one-lane time).
 constexpr int kDefaultPolishChunk = -1;
-int auto_polish_chunk(int n_qps) { return n_qps <= 40960 ? 1 : (n_qps <= 98304 ? 12 : 20); }
+int auto_polish_chunk(int n_qps) { return n_qps <= 40960 ? 1 : (n_qps <= 98304 ? 16 : 20); }
 // ADMM stopping tolerances with the polish on, per friction model (admm_tol 0)
 constexpr float kAdmmTolPyramid = 1e-1f, kAdmmTolCone = 1e-2f;
 
