@@ -125,8 +125,9 @@ typedef struct {
     float admm_tol;       /* ADMM stops a QP at this relative KKT residual;   */
                           /* the polish then lifts it to tol_rel (0 = the     */
                           /* friction model's default: 1e-1 for PYRAMID8,     */
-                          /* 1e-2 for CIRCULAR; without BODEX_F_POLISH ADMM   */
-                          /* always runs to tol_rel)                          */
+                          /* 1e-4 for CIRCULAR, whose ADMM then also stops    */
+                          /* after min(max_iters, 200) iterations; without    */
+                          /* BODEX_F_POLISH ADMM always runs to tol_rel)      */
     int friction_cone;    /* BODEX_CONE_PYRAMID8 (default) or                 */
                           /* BODEX_CONE_CIRCULAR                              */
 } bodex_qp_params;
