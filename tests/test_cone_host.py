@@ -41,7 +41,7 @@ def test_projection_matches_closest_point_of_triangle(host):
         np.testing.assert_allclose(z, _project_contact(f, mu, fmax), atol=1e-12)
 
 
-def _polish(host, b, g, z0, gamma=0.0, beta=1.0, cap=200):
+def _polish(host, b, g, z0, gamma=0.0, beta=1.0, cap=200, growth=60.0, loose=1e-2):
     m = int(b.counts[g])
     s = int(b.woff[g + 1] - b.woff[g])
     arr = lambda a: np.ascontiguousarray(a, dtype=np.float64)
@@ -54,15 +54,16 @@ def _polish(host, b, g, z0, gamma=0.0, beta=1.0, cap=200):
     host.host_cone_polish_grasp(m, p(P), p(N), p(mu), p(T), s, ctypes.c_double(20.0), ctypes.c_double(beta),
                                 ctypes.c_double(1e-6), ctypes.c_double(1.0), ctypes.c_double(gamma),
                                 z.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.c_double(1e-3),
-                                ctypes.c_double(1e5), ctypes.c_double(1e-12), ctypes.c_double(60.0),
-                                ctypes.c_double(1e-2), cap, x.ctypes.data_as(_D),
+                                ctypes.c_double(1e5), ctypes.c_double(1e-12), ctypes.c_double(growth),
+                                ctypes.c_double(loose), cap, x.ctypes.data_as(_D),
                                 st.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                                 nw.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
     return x[:, :3 * m], st, nw
 
 
 @pytest.mark.parametrize("gamma,start", [(0.0, "cold"), (2.0, "cold"), (0.0, "perturbed"), (2.0, "perturbed")])
-def test_polish_matches_oracle(host, gamma, start):
+@pytest.mark.parametrize("growth,loose", [(60.0, 1e-2), (40.0, 0.2)], ids=["kernel_schedule", "loose_centring"])
+def test_polish_matches_oracle(host, gamma, start, growth, loose):
     b = wl.config(1, 6)
     rng = np.random.default_rng(1)
     for g in range(b.n_grasps):
@@ -78,7 +79,7 @@ def test_polish_matches_oracle(host, gamma, start):
         # a cold start (all contacts at the apex) first walks to the central
         # path; a start near the optimum (as ADMM gives) converges in far fewer
         cap = 400 if start == "cold" else 120
-        x, st, nw = _polish(host, b, g, z0, gamma=gamma, cap=cap)
+        x, st, nw = _polish(host, b, g, z0, gamma=gamma, cap=cap, growth=growth, loose=loose)
         assert np.all(st == 0)
         for j in range(s):
             f = x[j]

@@ -58,6 +58,8 @@ def _check(b, gpu, ref, qps=None, beta=1.0):
     assert qerr.max() <= 1e-5, "objective error %.3e at QP %d" % (qerr.max(), qps[np.argmax(qerr)])
     M = b.m_max
     ferr = np.abs(gpu["forces"][qps] - ref["forces"][qps][:, :3 * M]).max(axis=1)
+    print("cone check: %d QPs, objective error max %.2e, force error max %.2e" % (len(qps), qerr.max(), ferr.max()),
+          flush=True)
     assert ferr.max() <= 1e-4, "force error %.3e at QP %d" % (ferr.max(), qps[np.argmax(ferr)])
     return qerr.max(), ferr.max()
 

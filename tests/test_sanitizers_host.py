@@ -18,7 +18,7 @@ SELECTION = [
     "test_gpolish_host.py::test_chunked_polish_reaches_the_minimiser[1-1-12]",
     "test_gpolish_host.py::test_chunked_polish_reaches_the_minimiser[12-3-12]",
     "test_cone_host.py::test_projection_matches_closest_point_of_triangle",
-    "test_cone_host.py::test_polish_matches_oracle[2.0-cold]",
+    "test_cone_host.py::test_polish_matches_oracle[kernel_schedule-2.0-cold]",
     "test_hand_host.py",
     "test_oracle_kkt_and_cases.py",
     "test_oracle_bruteforce.py",
