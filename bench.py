@@ -176,7 +176,7 @@ def main():
     admm_avg = float(np.mean(admm_ms))
     fin_avg = float(np.mean(fin_ms))
     dev_ms = np.asarray(admm_ms) + np.asarray(fin_ms)  # device time of each step's launches
-    flops_a = admm_flops(5, iters, p.check_every)
+    flops_a = admm_flops(5, iters, api.admm_check_period(p))
     flops_f = float(np.sum(res["polish_flops"].double().cpu().numpy()))
     kernels = {
         "admm": {"bound": "alu", "kernel": "admm_kernel<5>", "dtype": "f32", "peak": PEAK_FP32_TFLOPS,

@@ -106,7 +106,9 @@ typedef struct {
     int max_iters;        /* ADMM iteration cap                               */
     float rho0;           /* initial ADMM step size                           */
     float alpha;          /* over-relaxation, in (0, 2)                       */
-    int check_every;      /* residual check / rho update period (iterations)  */
+    int check_every;      /* residual check / rho update period (iterations); */
+                          /* with BODEX_F_POLISH and admm_tol 0 the pyramid's */
+                          /* ADMM uses max(check_every, 20)                   */
     float rho_min;        /* clamp of the adapted rho                         */
     float rho_max;
     float rho_hysteresis; /* refactor only when rho changes by this factor    */

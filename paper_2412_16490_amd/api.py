@@ -175,6 +175,15 @@ def default_params(**overrides) -> Params:
     return p
 
 
+def admm_check_period(p: Params) -> int:
+    """The residual-check period the library's ADMM uses for these
+    parameters (include/bodex_qp.h, check_every): max(check_every, 20) for the
+    pyramid with the polish on and admm_tol 0, else check_every."""
+    if (p.flags & F_POLISH) and not (p.admm_tol > 0) and p.friction_cone == CONE_PYRAMID8:
+        return max(int(p.check_every), 20)
+    return int(p.check_every)
+
+
 def _check(rc, handle=None):
     if rc != 0:
         msg = lib().bodex_qp_last_error(handle)
