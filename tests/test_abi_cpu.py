@@ -66,3 +66,17 @@ def test_state_bytes(L):
 
 def test_destroy_null_is_noop(L):
     assert L.bodex_qp_destroy(None) == 0
+
+
+def test_admm_check_period_follows_the_header_rule(L):
+    # bodex_qp.h, check_every: with the polish on and admm_tol 0 the pyramid's
+    # warm-start ADMM checks every max(check_every, 20) iterations; otherwise
+    # check_every is used as given
+    p = api.default_params()
+    assert p.check_every == 10 and p.admm_tol == 0.0 and p.friction_cone == api.CONE_PYRAMID8
+    assert api.admm_check_period(p) == 20
+    p.check_every = 30
+    assert api.admm_check_period(p) == 30
+    for change in ({"admm_tol": 1e-3}, {"friction_cone": api.CONE_CIRCULAR}, {"flags_clear": api.F_POLISH}):
+        q = api.default_params(**change)
+        assert api.admm_check_period(q) == 10, change
