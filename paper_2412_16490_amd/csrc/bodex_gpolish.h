@@ -380,7 +380,7 @@ template <int MM, class T>
 BODEX_FI bool gpolish_accept(const T& team, GQP<MM>& Q) {
     double r6[6];
     gp_gtimes(team, Q, Q.x, true, r6);
-    double gs = 0.0, stat = 0.0, lneg = 0.0, lmax = 0.0, viol = 0.0;
+    double gs = 0.0, stat = 0.0, lneg = 0.0, lmax = 0.0, viol = 0.0, vin = 0.0;
     if (Q.live) {
         double g[3];
         gp_grad(Q, r6, Q.x, g);
@@ -404,7 +404,9 @@ BODEX_FI bool gpolish_accept(const T& team, GQP<MM>& Q) {
         for (int kk = 0; kk < 9; ++kk) {
             double c[3], b;
             row3(kk, Q.muc, Q.fmax, c, &b);
-            viol = fmax(viol, dot3(c, Q.x) - b);
+            const double v = dot3(c, Q.x) - b;
+            viol = fmax(viol, v);
+            if (!((Q.mk >> kk) & 1u)) vin = fmax(vin, v);
         }
     }
     // a NaN anywhere must reject: carry it through the maxima as +inf
@@ -414,9 +416,12 @@ BODEX_FI bool gpolish_accept(const T& team, GQP<MM>& Q) {
     lneg = team.max(nanmax(lneg));
     lmax = team.max(nanmax(lmax));
     viol = team.max(nanmax(viol));
-    const bool ok = stat <= 1e-9 * (1.0 + gs + lmax) && lneg <= 1e-9 * (1.0 + lmax) &&
-                    viol <= 1e-9 * (1.0 + Q.fmax) && isfinite(stat) && isfinite(gs);
-    Q.out.status = ok ? 0 : 1;
+    vin = team.max(nanmax(vin));
+    const bool kkt = stat <= 1e-9 * (1.0 + gs + lmax) && lneg <= 1e-9 * (1.0 + lmax) && isfinite(stat) &&
+                     isfinite(gs);
+    const double vb = 1e-9 * (1.0 + Q.fmax);
+    // violated only outside the active set: more steps (see kPolishViolated)
+    Q.out.status = kkt && viol <= vb ? 0 : (kkt && vin > vb && viol == vin ? kPolishViolated : 1);
     return true;
 }
 
@@ -618,7 +623,8 @@ BODEX_FI bool gpolish_advance(const T& team, GQP<MM>& Q, int max_steps) {
     const double t1 = tn / td;
     const double t2 = (dep || !(cz > 0.0)) ? INFINITY : sp / cz;
     const double st = t2 < t1 ? t2 : t1;
-    if (!(st < INFINITY) || !(st >= 0.0)) {
+    if (!(st < INFINITY) || !(st >= 0.0) || (Q.chg & kChgBreakAny)) {
+        Q.chg &= ~int(kChgBreakAny);
         out.status = 3;  // infeasible or broken down
         return true;
     }
@@ -652,10 +658,33 @@ template <int MM, class T>
 BODEX_FI bool gpolish_finish(const T& team, GQP<MM>& Q) {
     const bool reached = Q.mode == kAccept;
     if (reached) gpolish_accept(team, Q);
+    if (Q.out.status == kPolishViolated) {
+        Q.out.status = 0;
+        Q.phase = kSteps;
+        Q.mode = kPick;
+        return false;
+    }
     if (Q.out.status != 0 && (Q.chg & kChgUsed)) {
         Q.out.status = 0;
-        Q.chg = kNoChange;
+        Q.chg = kNoChange | (Q.chg & kChgCold);
         Q.step0 = Q.out.steps;
+        Q.refactor = true;
+        Q.phase = kWarm;
+        Q.mode = kEqp0;
+        return false;
+    }
+    // as polish_finish: once more from the empty active set
+    if (Q.out.status != 0 && !(Q.chg & kChgCold)) {
+        const PendingRow none = {-1, -1, {0.0, 0.0, 0.0}, 0.0};
+        Q.out.status = 0;
+        Q.chg = kNoChange | kChgCold;
+        Q.step0 = Q.out.steps;
+        Q.mk = 0u;
+        Q.p = none;
+        Q.mp = none;
+        Q.up = 0.0;
+        Q.mup = 0.0;
+        Q.need_mult = false;
         Q.refactor = true;
         Q.phase = kWarm;
         Q.mode = kEqp0;

@@ -1165,7 +1165,9 @@ enum PolishChange {
     kChgUsed = 1 << 10,
     kChgAllowed = 1 << 11,
     kChgRetry = 1 << 12, // take the retry below even after an accepted check (tests)
-    kChgBreak = 1 << 13  // report one breakdown of the ratio test after a one-row change (tests)
+    kChgBreak = 1 << 13, // report one breakdown of the ratio test after a one-row change (tests)
+    kChgCold = 1 << 14,  // the restart from the empty active set has been taken
+    kChgBreakAny = 1 << 15  // report one breakdown of the next ratio test (tests)
 };
 
 // The pending set change in PS.chg: row 9 i + kk, joined or left.
@@ -1193,6 +1195,12 @@ struct PolishState {
 // Status of a polish that stopped at its budget with a factorisation due:
 // its state can be saved (polish_save) and continued elsewhere.
 constexpr int kPolishSuspended = 4;
+// Acceptance-check outcome (never returned): stationary with nonnegative
+// multipliers, but a row outside the active set is violated.  The exact
+// re-solve after the last step corrects what the steps' updates accumulated
+// and can move the point across such a row (rarely, after long step
+// sequences on ill-conditioned sets); the polish then takes more steps.
+constexpr int kPolishViolated = 5;
 
 template <int MM, typename YP, typename D>
 BODEX_FI void polish_begin(const D& Dt, YP y0, PolishState<MM>& PS) {
@@ -1278,7 +1286,7 @@ BODEX_FI bool polish_accept(const D& Dt, const PolishWork<V>& W, PolishState<MM>
     const bool gam = D::kGam && S.gam;
     double r6[6];
     g_times<MM>(Dt, W.x, true, r6);
-    double gs = 0.0, stat = 0.0, lneg = 0.0, lmax = 0.0, viol = 0.0, sum1 = 0.0;
+    double gs = 0.0, stat = 0.0, lneg = 0.0, lmax = 0.0, viol = 0.0, vin = 0.0, sum1 = 0.0;
     if (gam) {
         lneg = fmax(lneg, -*lg);
         lmax = fmax(lmax, fabs(*lg));
@@ -1305,18 +1313,26 @@ BODEX_FI bool polish_accept(const D& Dt, const PolishWork<V>& W, PolishState<MM>
         }
         stat = fmax(stat, fmax(fabs(st[0]), fmax(fabs(st[1]), fabs(st[2]))));
         const double f[3] = {W.x[3 * i], W.x[3 * i + 1], W.x[3 * i + 2]};
+        const unsigned mk = contact_mask(S.mask, i);
 #pragma unroll
         for (int kk = 0; kk < 9; ++kk) {
             double c[3], b;
             row3(kk, Dt.muc[i], fm, c, &b);
-            viol = fmax(viol, dot3(c, f) - b);
+            const double v = dot3(c, f) - b;
+            viol = fmax(viol, v);
+            if (!((mk >> kk) & 1u)) vin = fmax(vin, v);
         }
         sum1 += f[0];
     }
-    if (use_gam) viol = fmax(viol, Dt.gamma - sum1);
-    const bool ok = stat <= 1e-9 * (1.0 + gs + lmax) && lneg <= 1e-9 * (1.0 + lmax) &&
-                    viol <= 1e-9 * (1.0 + fm + Dt.gamma) && isfinite(stat) && isfinite(gs);
-    out.status = ok ? 0 : 1;
+    if (use_gam) {
+        viol = fmax(viol, Dt.gamma - sum1);
+        if (!gam) vin = fmax(vin, Dt.gamma - sum1);
+    }
+    const bool kkt = stat <= 1e-9 * (1.0 + gs + lmax) && lneg <= 1e-9 * (1.0 + lmax) && isfinite(stat) &&
+                     isfinite(gs);
+    const double vb = 1e-9 * (1.0 + fm + Dt.gamma);
+    // violated only outside the active set: more steps (see kPolishViolated)
+    out.status = kkt && viol <= vb ? 0 : (kkt && vin > vb && viol == vin ? kPolishViolated : 1);
     return true;
 }
 
@@ -1589,8 +1605,9 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
     const double t1 = tn / td;
     const double t2 = (dep || !(cz > 0.0)) ? INFINITY : sp / cz;
     const double st = t2 < t1 ? t2 : t1;
-    if (!(st < INFINITY) || !(st >= 0.0) || ((PS.chg & kChgBreak) && (PS.chg & kChgUsed))) {
-        PS.chg &= ~int(kChgBreak);
+    if (!(st < INFINITY) || !(st >= 0.0) || ((PS.chg & kChgBreak) && (PS.chg & kChgUsed)) ||
+        (PS.chg & kChgBreakAny)) {
+        PS.chg &= ~int(kChgBreak | kChgBreakAny);
         out.status = 3;  // infeasible or broken down
         return true;
     }
@@ -1635,17 +1652,47 @@ BODEX_FI bool polish_advance(const D& Dt, int max_steps, const PolishWork<V>& W,
 // the QP is to be taken once more: failed after one-row changes of the
 // factor (rejected by the check, out of steps, or broken down in the ratio
 // test), it restarts from its last set with fresh factorisations only
-// (equality solve, multiplier drops, steps) and a step cap of its own.
+// (equality solve, multiplier drops, steps) and a step cap of its own.  If
+// it fails without such changes, or again after that restart, it is taken
+// once from the empty active set: the unconstrained minimiser, from which
+// the dual active-set steps are the textbook method (its infeasibility test
+// is then sound), again with fresh factorisations and a cap of its own.
+// This happens for about one QP in 1e9 (a warm set whose first step finds
+// the violated row dependent on the active rows with no multiplier to drop).
 template <int MM, typename D, class V>
 BODEX_FI bool polish_finish(const D& Dt, const PolishWork<V>& W, PolishState<MM>& PS) {
     if (PS.out.status == kPolishSuspended) return true;
     const bool reached = PS.mode == kAccept;
     if (reached) polish_accept<MM>(Dt, W, PS);
+    if (PS.out.status == kPolishViolated) {
+        PS.out.status = 0;
+        PS.phase = kSteps;
+        PS.mode = kPick;
+        return false;
+    }
     const bool forced = reached && (PS.chg & kChgRetry);
     if ((PS.out.status != 0 || forced) && (PS.chg & kChgUsed)) {
         PS.out.status = 0;
-        PS.chg = kNoChange;
+        PS.chg = kNoChange | (PS.chg & kChgCold);
         PS.step0 = PS.out.steps;
+        PS.refactor = true;
+        PS.phase = kWarm;
+        PS.mode = kEqp0;
+        return false;
+    }
+    if (PS.out.status != 0 && !(PS.chg & kChgCold)) {
+        const PendingRow none = {-1, -1, {0.0, 0.0, 0.0}, 0.0};
+        PS.out.status = 0;
+        PS.chg = kNoChange | kChgCold;
+        PS.step0 = PS.out.steps;
+        PS.S.mask = 0;
+        PS.S.gam = false;
+        PS.p = none;
+        PS.mp = none;
+        PS.up = 0.0;
+        PS.mup = 0.0;
+        PS.lg = 0.0;
+        PS.need_mult = false;
         PS.refactor = true;
         PS.phase = kWarm;
         PS.mode = kEqp0;

@@ -27,10 +27,12 @@ extern "C" {
 // then is saved to a record and finished by the contact-parallel polish.
 // Outputs x [s][15], status [s], handed [s] (1 if the group finished it),
 // counts [s][4] (factorisations, of which one-row changes, equality solves,
-// one-row steps).  Returns the number of QPs whose polish was not accepted.
+// one-row steps).  force_break: the first ratio test (in whichever kernel
+// runs it) reports a breakdown.  Returns the number of QPs whose polish was
+// not accepted.
 int host_chunked_polish(int m, const double* p, const double* n, const double* mu, const double* t, int s,
                         double kappa, double eps, const float* y0, int budget, double* x, int* status,
-                        int* handed, int* counts) {
+                        int* handed, int* counts, int force_break) {
     double G[6 * NV] = {};
     double muc[MM] = {};
     for (int i = 0; i < m; ++i) {
@@ -56,6 +58,7 @@ int host_chunked_polish(int m, const double* p, const double* n, const double* m
         PS.S.pc = LaneVec{nullptr, 1};
         polish_begin<MM>(D, y0 + 46 * j, PS);
         PS.budget = budget;
+        if (force_break) PS.chg |= kChgBreakAny;
         do {
             while (!polish_advance<MM, decltype(D), LaneVec, true>(D, 200, W, PS)) {
             }

@@ -110,7 +110,9 @@ int host_matrix_change(int m, const double* p, const double* n, const double* mu
 // force_retry = 1 every QP that used one-row changes is taken once more from
 // its final set on fresh factorisations, as after a failed acceptance check;
 // 2: the first ratio test after a one-row change reports a breakdown; 3: the
-// first attempt gets a cap of first_cap factorisations (the retry 200).
+// first attempt gets a cap of first_cap factorisations (the retry 200); 4: the
+// first ratio test reports a breakdown (before any one-row change: the
+// restart from the empty active set follows).
 int host_polish_counts(int m, const double* p, const double* n, const double* mu, const double* t, int s,
                        double kappa, double eps, const float* y0, int force_retry, int* counts, double* x,
                        int first_cap) {
@@ -138,6 +140,7 @@ int host_polish_counts(int m, const double* p, const double* n, const double* mu
         polish_begin<MM>(D, y0 + 46 * j, PS);
         if (force_retry == 1) PS.chg |= kChgRetry;
         if (force_retry == 2) PS.chg |= kChgBreak;
+        if (force_retry == 4) PS.chg |= kChgBreakAny;
         int cap = force_retry == 3 ? first_cap : 200;
         do {
             while (!polish_advance<MM>(D, cap, W, PS)) {

@@ -30,7 +30,7 @@ def _d(a):
     return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _run(host, b, g, y0, budget):
+def _run(host, b, g, y0, budget, force_break=0):
     m = int(b.counts[g])
     s = min(int(b.woff[g + 1] - b.woff[g]), 6)
     p, pp = _d(b.points[g, :m])
@@ -46,7 +46,7 @@ def _run(host, b, g, y0, budget):
     bad = host.host_chunked_polish(m, pp, pn, pm, pt, s, ctypes.c_double(20.0), ctypes.c_double(1e-6),
                                    y.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), int(budget),
                                    x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), st.ctypes.data_as(I),
-                                   hd.ctypes.data_as(I), cnt.ctypes.data_as(I))
+                                   hd.ctypes.data_as(I), cnt.ctypes.data_as(I), int(force_break))
     return bad, x[:, :3 * m], st, hd, cnt
 
 
@@ -72,3 +72,25 @@ def test_chunked_polish_reaches_the_minimiser(host, cfg, ng, budget):
         assert np.all(cnt[hd == 0, 0] <= budget)
         handed += int(hd.sum())
     assert handed > 0
+
+
+@pytest.mark.parametrize("budget", [0, 2])
+def test_group_restart_from_the_empty_set_after_a_breakdown(host, budget):
+    # the first ratio test breaks down (forced once): with budget 0 in the
+    # contact-parallel polish, which restarts from the empty active set;
+    # with budget 2 wherever the QP reaches its first step
+    b = wl.config(1, 8)
+    ref = oracle.solve_batch(b.counts, b.woff, b.points, b.normals, b.mu, b.wrench, oracle.params())
+    rng = np.random.default_rng(29)
+    hit = 0
+    for g in range(b.n_grasps):
+        s = int(b.woff[g + 1] - b.woff[g])
+        m = int(b.counts[g])
+        y0 = np.where(rng.random((s, 46)) < 0.3, rng.random((s, 46)), 0.0)
+        bad0, x0, st0, hd0, c0 = _run(host, b, g, y0, budget)
+        bad, x, st, hd, cnt = _run(host, b, g, y0, budget, force_break=1)
+        assert bad0 == 0 and bad == 0, st
+        fr = ref["forces"][b.woff[g]:b.woff[g] + len(st), :3 * m]
+        assert np.abs(x - fr).max() <= 1e-8, (g, np.abs(x - fr).max())
+        hit += int(np.sum(c0[:, 3] > 0))
+    assert hit > 0

@@ -241,3 +241,29 @@ def test_retry_after_a_failed_attempt_reaches_the_minimiser(host, mode):
         assert np.all(c1[~hit] == c0[~hit])
         retried += int(hit.sum())
     assert retried > 0
+
+
+def test_restart_from_the_empty_set_after_a_breakdown(host):
+    # a QP whose first ratio test breaks down (forced once) before any
+    # one-row change has no last set to retry from: it restarts from the
+    # empty active set (the unconstrained minimiser, from which the dual
+    # active-set steps are the textbook method) with fresh factorisations,
+    # and ends at the oracle's minimiser
+    b = wl.config(1, 16)
+    ref = oracle.solve_batch(b.counts, b.woff, b.points, b.normals, b.mu, b.wrench, oracle.params())
+    rng = np.random.default_rng(23)
+    hit_total = 0
+    for g in range(b.n_grasps):
+        s = int(b.woff[g + 1] - b.woff[g])
+        m = int(b.counts[g])
+        y0 = np.where(rng.random((s, 46)) < 0.3, rng.random((s, 46)), 0.0)
+        bad0, c0, x0 = _counts(host, b, g, y0, 0)
+        bad1, c1, x1 = _counts(host, b, g, y0, 4)
+        assert bad0 == 0 and bad1 == 0
+        fr = ref["forces"][b.woff[g]:b.woff[g + 1], :3 * m]
+        assert np.abs(x1 - fr).max() <= 1e-8, (g, np.abs(x1 - fr).max())
+        hit = c0[:, 3] > 0  # QPs that reach a ratio test: the forced breakdown hits them
+        assert np.all(c1[~hit] == c0[~hit])
+        assert np.all(c1[hit, 0] > 1)
+        hit_total += int(hit.sum())
+    assert hit_total > 0
