@@ -192,9 +192,11 @@ class Request:
 
 def request_stream(seed=CONFIG_SEEDS[4], rate=200.0, duration=60.0,
                    size_range=(16, 4096), steps=50, sigma=1e-3,
-                   max_requests=None):
+                   max_requests=None, start=0):
     """Poisson arrivals; each request is a mixed batch of log-uniform size,
-    with a random walk on its contact points (normals fixed) per step."""
+    with a random walk on its contact points (normals fixed) per step.
+    start: yield from request `start` on (the earlier ones are drawn but not
+    built, so the stream is the same)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     t = 0.0
     rid = 0
@@ -204,6 +206,9 @@ def request_stream(seed=CONFIG_SEEDS[4], rate=200.0, duration=60.0,
             return
         size = int(np.exp(rng.uniform(np.log(size_range[0]), np.log(size_range[1]))))
         sub_seed = int(rng.integers(0, 2 ** 62))
+        if rid < start:
+            rid += 1
+            continue
         b = mixed_batch(sub_seed, size, name="req%d" % rid)
         walk_rng = np.random.Generator(np.random.PCG64(sub_seed ^ 0x5DEECE66D))
         walk = (sigma * walk_rng.standard_normal((steps,) + b.points.shape)).astype(np.float32)
