@@ -349,6 +349,51 @@ hipError_t launch(Kind k, int mm, const KArgs& a, int grid, size_t lds, hipStrea
     return a.cone ? bodex::launch_backward_cone(mm, a, grid, lds, st) : bodex::launch_backward(mm, a, grid, lds, st);
 }
 
+// Chunked polish (the factorisation budget polish_chunk, -1: by batch
+// size): the one-lane pass hands QPs that need more factorisations to the
+// contact-parallel polish.  Sets up the record workspace (records for every
+// QP of the batch, so none is ever finished in the first pass for want of
+// room) in a; chunked is false where the chunked polish does not apply (no
+// polish, the circular cone, gamma > 0, chunk 0).
+int chunk_setup(bodex_qp* h, KArgs& a, int W, int mm, bool cone, bool& chunked, int& grid_g) {
+    const int chunk = h->prm.polish_chunk < 0 ? auto_polish_chunk(W) : h->prm.polish_chunk;
+    chunked = (h->prm.flags & BODEX_F_POLISH) && !cone && h->prm.gamma == 0.f && chunk > 0;
+    grid_g = 0;
+    if (!chunked) return 0;
+    const size_t K = size_t(W);
+    const size_t nd = size_t(3 * mm + 3) * K, ni = size_t(bodex::kSpInts) * K + size_t(W);
+    const int rc = ensure_device(h, &h->d_spill, &h->d_spill_cap, nd * sizeof(double) + ni * sizeof(int));
+    if (rc) return rc;
+    a.spill.d = static_cast<double*>(h->d_spill);
+    a.spill.i = reinterpret_cast<int*>(a.spill.d + nd);
+    a.spill.K = int(K);
+    a.spill_idx = a.spill.i + size_t(bodex::kSpInts) * K;
+    a.polish_budget = chunk;
+    const int gpw = bodex::kWave / bodex::gpolish_group(mm);
+    grid_g = int((K + gpw - 1) / gpw);
+    return 0;
+}
+
+// The finalize launches: one, or for the chunked polish the budgeted first
+// pass, the contact-parallel polish of what it handed on and the outputs of
+// those QPs (the record counter is the second word of the queue counters,
+// which the step's reset clears).
+int enqueue_finalize(bodex_qp* h, KArgs f, int mm, bool chunked, int* d_queue, int grid_f, int grid_g,
+                     size_t lds_f) {
+    f.queue = nullptr;
+    if (chunked) {
+        f.spill_count = d_queue + 1;
+        f.fin_mode = 1;
+        HIP_TRY(h, launch(Kind::Fin, mm, f, grid_f, lds_f, h->stream));
+        HIP_TRY(h, bodex::launch_gpolish(mm, f, grid_g, h->stream));
+        f.fin_mode = 2;
+        HIP_TRY(h, launch(Kind::Fin, mm, f, grid_f, lds_f, h->stream));
+    } else {
+        HIP_TRY(h, launch(Kind::Fin, mm, f, grid_f, lds_f, h->stream));
+    }
+    return 0;
+}
+
 int validate_params(const bodex_qp_params* p, bodex_qp* h) {
     if (!p) return fail(h, BODEX_EINVAL, "params is NULL");
     if (p->m_max < 1 || p->m_max > BODEX_MAX_CONTACTS)
@@ -694,26 +739,10 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
     a.status = out->status;
     a.pflops = out->polish_flops;
 
-    // chunked polish: the one-lane pass hands QPs that need more than
-    // polish_chunk factorisations to the contact-parallel polish (records
-    // for every QP of the batch, so none is ever finished in the first pass
-    // for want of room)
-    const int chunk = h->prm.polish_chunk < 0 ? auto_polish_chunk(W) : h->prm.polish_chunk;
-    const bool chunked = (h->prm.flags & BODEX_F_POLISH) && !cone && h->prm.gamma == 0.f && chunk > 0;
+    bool chunked = false;
     int grid_g = 0;
-    if (chunked) {
-        const size_t K = size_t(W);
-        const size_t nd = size_t(3 * mm + 3) * K, ni = size_t(bodex::kSpInts) * K + size_t(W);
-        rc = ensure_device(h, &h->d_spill, &h->d_spill_cap, nd * sizeof(double) + ni * sizeof(int));
-        if (rc) return rc;
-        a.spill.d = static_cast<double*>(h->d_spill);
-        a.spill.i = reinterpret_cast<int*>(a.spill.d + nd);
-        a.spill.K = int(K);
-        a.spill_idx = a.spill.i + size_t(bodex::kSpInts) * K;
-        a.polish_budget = chunk;
-        const int gpw = bodex::kWave / bodex::gpolish_group(mm);
-        grid_g = int((K + gpw - 1) / gpw);
-    }
+    rc = chunk_setup(h, a, W, mm, cone, chunked, grid_g);
+    if (rc) return rc;
 
     const size_t n_ints = desc_ints(G, S, lay);
     const bool timing = (h->prm.flags & BODEX_F_TIMING) != 0;
@@ -739,19 +768,8 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
         KArgs f = a;
         f.queue = nullptr;
         if (with_events) HIP_TRY(h, hipEventRecord(h->tev[2], h->stream));
-        if (chunked) {
-            // first pass (budgeted), contact-parallel polish of what it
-            // handed on, outputs of those QPs; the record counter is the
-            // second queue word, cleared with the others above
-            f.spill_count = d_queue + 1;
-            f.fin_mode = 1;
-            HIP_TRY(h, launch(Kind::Fin, mm, f, grid_f, lds_f, h->stream));
-            HIP_TRY(h, bodex::launch_gpolish(mm, f, grid_g, h->stream));
-            f.fin_mode = 2;
-            HIP_TRY(h, launch(Kind::Fin, mm, f, grid_f, lds_f, h->stream));
-        } else {
-            HIP_TRY(h, launch(Kind::Fin, mm, f, grid_f, lds_f, h->stream));
-        }
+        rc = enqueue_finalize(h, f, mm, chunked, d_queue, grid_f, grid_g, lds_f);
+        if (rc) return rc;
         if (with_events) HIP_TRY(h, hipEventRecord(h->tev[3], h->stream));
         return 0;
     };
@@ -1150,6 +1168,10 @@ int bodex_qp_descend(bodex_qp_t* h, const bodex_hand* hand, const bodex_batch* q
     const size_t lds_b = fin_lds(mm, S.slots, true);
     const int per_cu = std::max(1, std::min(16, int((160 * 1024) / std::max<size_t>(lds_a, 1))));
     const int grid_a = batched ? occupancy_grid(h, per_cu, S.n_tiles) : S.n_tiles;
+    bool chunked = false;
+    int grid_g = 0;
+    rc = chunk_setup(h, a, W, mm, cone, chunked, grid_g);
+    if (rc) return rc;
 
     // The whole descent for the descriptors at `desc`: loss weights, the
     // first contacts, then per step reset, ADMM, finalize, backward and the
@@ -1171,8 +1193,8 @@ int bodex_qp_descend(bodex_qp_t* h, const bodex_hand* hand, const bodex_batch* q
             HIP_TRY(h, bodex::launch_reset(d_queue, 4, h->stream));
             ak.queue = batched ? d_queue : nullptr;
             HIP_TRY(h, launch(Kind::Admm, mm, ak, grid_a, lds_a, h->stream, h->prm.admm_waves));
-            ak.queue = nullptr;
-            HIP_TRY(h, launch(Kind::Fin, mm, ak, S.n_tiles, lds_f, h->stream));
+            const int rf = enqueue_finalize(h, ak, mm, chunked, d_queue, S.n_tiles, grid_g, lds_f);
+            if (rf) return rf;
             KArgs ab = ad;
             ab.queue = nullptr;
             ab.dLdE = wq;
@@ -1209,7 +1231,7 @@ int bodex_qp_descend(bodex_qp_t* h, const bodex_hand* hand, const bodex_batch* q
         if (rc) return rc;
         rc = enqueue(h->d_desc);
         if (rc) return rc;
-        h->last_launches = 2 + 5 * d->iters;
+        h->last_launches = 2 + (chunked ? 7 : 5) * d->iters;
         return 0;
     }
     // Graph path: the descent's launches captured once per shape, pointers
