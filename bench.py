@@ -216,8 +216,8 @@ def main():
                    "kkt_rel_max": float(np.max(kkt)),
                    "iters_mean": float(np.mean(iters)), "iters_p99": float(np.percentile(iters, 99)),
                    "finalize_ms": round(float(np.mean(fin_ms)), 4),
-                   "polish_chunk": "auto (%d for %d QPs)" % (20 if db.n_qps > 98304 else (16 if db.n_qps > 40960 else 1),
-                                                             db.n_qps),
+                   "polish_chunk": "auto (%d for %d QPs)" % (
+                       api.bodex_qp_effective_params(p, db.n_qps)["polish_chunk"], db.n_qps),
                    "step_device_ms_median": round(float(np.median(dev_ms)), 4),
                    "step_device_ms_p99": round(float(np.percentile(dev_ms, 99)), 4)},
         "roofline": roofline,

@@ -269,6 +269,17 @@ const char *bodex_qp_last_error(const bodex_qp_t *h);
  * residual r); the pyramid layout, an upper bound for the circular cone's. */
 size_t bodex_qp_state_bytes(int n_grasps, int n_qps, int m_max);
 
+/* The values the library takes for parameters whose rule it owns (see
+ * admm_tol, check_every, max_iters and polish_chunk above), for a solve of
+ * n_qps QPs with *p: ADMM's stopping tolerance, iteration cap and residual
+ * check period, and the one-lane polish's factorisation budget (0: the
+ * polish runs one lane per QP to the end, as for the circular cone, gamma > 0
+ * or without BODEX_F_POLISH).  Needs no device.  Any output pointer may be
+ * NULL; BODEX_EINVAL (message in bodex_qp_last_error(NULL)) for invalid
+ * parameters. */
+int bodex_qp_effective_params(const bodex_qp_params *p, int n_qps, float *admm_tol, int *max_iters,
+                              int *check_every, int *polish_chunk);
+
 /* Statistics of the last solve (host copies, filled after the stream is
  * synchronised by this call): number of graph replays, refactorisations,
  * launches.  Any pointer may be NULL.  Synchronises the handle's stream. */

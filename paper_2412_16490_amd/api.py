@@ -137,6 +137,10 @@ def lib():
         L.bodex_qp_last_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
                                           ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         L.bodex_qp_last_stats.restype = ctypes.c_int
+        L.bodex_qp_effective_params.argtypes = [ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(ctypes.c_float),
+                                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                                ctypes.POINTER(ctypes.c_int)]
+        L.bodex_qp_effective_params.restype = ctypes.c_int
         L.bodex_qp_kernel_times.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
                                             ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
         L.bodex_qp_kernel_times.restype = ctypes.c_int
@@ -159,7 +163,7 @@ EXPORTED = ("bodex_qp_default_params", "bodex_qp_create", "bodex_qp_set_stream",
             "bodex_qp_solve", "bodex_qp_solve_static", "bodex_qp_backward", "bodex_qp_destroy",
             "bodex_qp_last_error", "bodex_qp_state_bytes", "bodex_qp_last_stats",
             "bodex_qp_kernel_times", "bodex_qp_detach_energy", "bodex_qp_contact_query",
-            "bodex_qp_pose_gradient", "bodex_qp_descend")
+            "bodex_qp_pose_gradient", "bodex_qp_descend", "bodex_qp_effective_params")
 
 
 def default_params(**overrides) -> Params:
@@ -175,13 +179,19 @@ def default_params(**overrides) -> Params:
     return p
 
 
+def bodex_qp_effective_params(p: Params, n_qps: int) -> dict:
+    """The values the library takes for the parameters whose rule it owns:
+    ADMM's tolerance, iteration cap and check period, and the polish's
+    factorisation budget, for a solve of n_qps QPs (no device needed)."""
+    tol, mi, ce, pc = ctypes.c_float(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().bodex_qp_effective_params(ctypes.byref(p), int(n_qps), ctypes.byref(tol), ctypes.byref(mi),
+                                           ctypes.byref(ce), ctypes.byref(pc)))
+    return {"admm_tol": tol.value, "max_iters": mi.value, "check_every": ce.value, "polish_chunk": pc.value}
+
+
 def admm_check_period(p: Params) -> int:
-    """The residual-check period the library's ADMM uses for these
-    parameters (include/bodex_qp.h, check_every): max(check_every, 20) for the
-    pyramid with the polish on and admm_tol 0, else check_every."""
-    if (p.flags & F_POLISH) and not (p.admm_tol > 0) and p.friction_cone == CONE_PYRAMID8:
-        return max(int(p.check_every), 20)
-    return int(p.check_every)
+    """The residual-check period the library's ADMM uses for these parameters."""
+    return bodex_qp_effective_params(p, 0)["check_every"]
 
 
 def _check(rc, handle=None):

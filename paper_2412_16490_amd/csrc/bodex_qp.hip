@@ -342,6 +342,28 @@ constexpr int kAdmmItersCone = 200;
 // polish: 1.87-1.90 ms against 1.95-1.99 ms).
 constexpr int kAdmmCheckPyramid = 20;
 
+// The rules the parameters leave to the library: ADMM's stopping
+// tolerance, iteration cap and check period (with the polish on and
+// admm_tol 0, the friction model's rule), and the polish's factorisation
+// budget for a batch of n_qps QPs.
+struct Effective {
+    float admm_tol;
+    int max_iters, check_every, polish_chunk;
+};
+Effective effective(const bodex_qp_params& p, int n_qps) {
+    const bool cone_model = p.friction_cone == BODEX_CONE_CIRCULAR;
+    const bool polish = (p.flags & BODEX_F_POLISH) != 0;
+    const bool model_rule = polish && !(p.admm_tol > 0.f);
+    Effective e;
+    // without the polish nothing lifts a QP past the ADMM tolerance
+    e.admm_tol = !polish ? p.tol_rel : (p.admm_tol > 0.f ? p.admm_tol : (cone_model ? kAdmmTolCone : kAdmmTolPyramid));
+    e.max_iters = (model_rule && cone_model) ? std::min(p.max_iters, kAdmmItersCone) : p.max_iters;
+    e.check_every = (model_rule && !cone_model) ? std::max(p.check_every, kAdmmCheckPyramid) : p.check_every;
+    const bool chunkable = polish && !cone_model && p.gamma == 0.f;
+    e.polish_chunk = !chunkable ? 0 : (p.polish_chunk < 0 ? auto_polish_chunk(n_qps) : p.polish_chunk);
+    return e;
+}
+
 hipError_t launch(Kind k, int mm, const KArgs& a, int grid, size_t lds, hipStream_t st, int occ = 0) {
     if (k == Kind::Admm) return bodex::launch_admm(mm, occ > 0 ? occ : kDefaultAdmmWaves, a, grid, lds, st);
     if (k == Kind::Fin)
@@ -356,8 +378,9 @@ hipError_t launch(Kind k, int mm, const KArgs& a, int grid, size_t lds, hipStrea
 // room) in a; chunked is false where the chunked polish does not apply (no
 // polish, the circular cone, gamma > 0, chunk 0).
 int chunk_setup(bodex_qp* h, KArgs& a, int W, int mm, bool cone, bool& chunked, int& grid_g) {
-    const int chunk = h->prm.polish_chunk < 0 ? auto_polish_chunk(W) : h->prm.polish_chunk;
-    chunked = (h->prm.flags & BODEX_F_POLISH) && !cone && h->prm.gamma == 0.f && chunk > 0;
+    (void)cone;  // part of the rule in effective()
+    const int chunk = effective(h->prm, W).polish_chunk;
+    chunked = chunk > 0;
     grid_g = 0;
     if (!chunked) return 0;
     const size_t K = size_t(W);
@@ -426,6 +449,7 @@ int validate_params(const bodex_qp_params* p, bodex_qp* h) {
 
 KArgs make_args(const bodex_qp* h, const bodex_batch* in) {
     const bodex_qp_params& p = h->prm;
+    const Effective e = effective(p, in->n_qps);
     KArgs a;
     std::memset(&a, 0, sizeof(a));
     a.points = in->points;
@@ -441,20 +465,15 @@ KArgs make_args(const bodex_qp* h, const bodex_batch* in) {
     a.fmax = p.force_max;
     a.gamma = p.gamma;
     a.tol = p.tol_rel;
-    // without the polish nothing lifts a QP past the ADMM tolerance; 0 picks
-    // the friction model's default stopping rule
-    const bool cone_model = p.friction_cone == BODEX_CONE_CIRCULAR;
-    const bool model_rule = (p.flags & BODEX_F_POLISH) && !(p.admm_tol > 0.f);
-    const float model_tol = cone_model ? kAdmmTolCone : kAdmmTolPyramid;
-    a.admm_tol = !(p.flags & BODEX_F_POLISH) ? p.tol_rel : (p.admm_tol > 0.f ? p.admm_tol : model_tol);
+    a.admm_tol = e.admm_tol;
     a.rho0 = p.rho0;
     a.alpha = p.alpha;
     a.rho_min = p.rho_min;
     a.rho_max = p.rho_max;
     a.hyst = p.rho_hysteresis;
     a.fp64_cond = p.fp64_cond;
-    a.max_iters = (model_rule && cone_model) ? std::min(p.max_iters, kAdmmItersCone) : p.max_iters;
-    a.check_every = (model_rule && !cone_model) ? std::max(p.check_every, kAdmmCheckPyramid) : p.check_every;
+    a.max_iters = e.max_iters;
+    a.check_every = e.check_every;
     a.warm = (p.flags & BODEX_F_WARM_START) ? 1 : 0;
     a.adaptive = (p.flags & BODEX_F_ADAPTIVE_RHO) ? 1 : 0;
     a.polish = (p.flags & BODEX_F_POLISH) ? 1 : 0;
@@ -1027,6 +1046,19 @@ int bodex_qp_kernel_times(bodex_qp_t* h, float* admm_ms, float* finalize_ms, flo
     if (!rc) rc = span(h->t_fin, 2, finalize_ms);
     if (!rc) rc = span(h->t_bwd, 4, backward_ms);
     return rc;
+}
+
+int bodex_qp_effective_params(const bodex_qp_params* p, int n_qps, float* admm_tol, int* max_iters,
+                               int* check_every, int* polish_chunk) {
+    if (!p || n_qps < 0) return fail(nullptr, BODEX_EINVAL, "params is NULL or n_qps < 0");
+    const int rc = validate_params(p, nullptr);
+    if (rc) return rc;
+    const Effective e = effective(*p, n_qps);
+    if (admm_tol) *admm_tol = e.admm_tol;
+    if (max_iters) *max_iters = e.max_iters;
+    if (check_every) *check_every = e.check_every;
+    if (polish_chunk) *polish_chunk = e.polish_chunk;
+    return 0;
 }
 
 int bodex_qp_last_stats(bodex_qp_t* h, int* launches, int* graph_replays, int* tiles) {

@@ -68,15 +68,33 @@ def test_destroy_null_is_noop(L):
     assert L.bodex_qp_destroy(None) == 0
 
 
-def test_admm_check_period_follows_the_header_rule(L):
-    # bodex_qp.h, check_every: with the polish on and admm_tol 0 the pyramid's
-    # warm-start ADMM checks every max(check_every, 20) iterations; otherwise
-    # check_every is used as given
+def test_effective_params_follow_the_header_rules(L):
+    # bodex_qp.h: with the polish on and admm_tol 0 the pyramid's warm-start
+    # ADMM stops at 1e-1 and checks every max(check_every, 20) iterations;
+    # the cone's stops at 1e-4 or min(max_iters, 200) iterations; without the
+    # polish ADMM runs to tol_rel; the polish budget follows polish_chunk
+    # (-1: 1 up to 40,960 QPs, 16 up to 98,304, else 20) for the pyramid with
+    # gamma = 0, and is 0 otherwise
     p = api.default_params()
     assert p.check_every == 10 and p.admm_tol == 0.0 and p.friction_cone == api.CONE_PYRAMID8
-    assert api.admm_check_period(p) == 20
+    e = api.bodex_qp_effective_params(p, 131072)
+    assert e["check_every"] == 20 and e["max_iters"] == 500 and abs(e["admm_tol"] - 0.1) < 1e-7
+    assert e["polish_chunk"] == 20
+    assert [api.bodex_qp_effective_params(p, n)["polish_chunk"] for n in (1, 40960, 40961, 98304, 98305)] == \
+        [1, 1, 16, 16, 20]
     p.check_every = 30
     assert api.admm_check_period(p) == 30
-    for change in ({"admm_tol": 1e-3}, {"friction_cone": api.CONE_CIRCULAR}, {"flags_clear": api.F_POLISH}):
-        q = api.default_params(**change)
-        assert api.admm_check_period(q) == 10, change
+    q = api.default_params(admm_tol=1e-3, polish_chunk=7)
+    e = api.bodex_qp_effective_params(q, 1000)
+    assert e["check_every"] == 10 and abs(e["admm_tol"] - 1e-3) < 1e-9 and e["polish_chunk"] == 7
+    c = api.default_params(friction_cone=api.CONE_CIRCULAR)
+    e = api.bodex_qp_effective_params(c, 1000)
+    assert e["check_every"] == 10 and e["max_iters"] == 200 and abs(e["admm_tol"] - 1e-4) < 1e-9
+    assert e["polish_chunk"] == 0
+    n = api.default_params(flags_clear=api.F_POLISH)
+    e = api.bodex_qp_effective_params(n, 1000)
+    assert abs(e["admm_tol"] - n.tol_rel) < 1e-12 and e["check_every"] == 10 and e["polish_chunk"] == 0
+    assert api.bodex_qp_effective_params(api.default_params(gamma=0.5), 1000)["polish_chunk"] == 0
+    bad = api.default_params(m_max=0)
+    with pytest.raises(api.BodexError):
+        api.bodex_qp_effective_params(bad, 10)
