@@ -376,9 +376,8 @@ hipError_t launch(Kind k, int mm, const KArgs& a, int grid, size_t lds, hipStrea
 // contact-parallel polish.  Sets up the record workspace (records for every
 // QP of the batch, so none is ever finished in the first pass for want of
 // room) in a; chunked is false where the chunked polish does not apply (no
-// polish, the circular cone, gamma > 0, chunk 0).
-int chunk_setup(bodex_qp* h, KArgs& a, int W, int mm, bool cone, bool& chunked, int& grid_g) {
-    (void)cone;  // part of the rule in effective()
+// polish, the circular cone, gamma > 0, chunk 0: effective()).
+int chunk_setup(bodex_qp* h, KArgs& a, int W, int mm, bool& chunked, int& grid_g) {
     const int chunk = effective(h->prm, W).polish_chunk;
     chunked = chunk > 0;
     grid_g = 0;
@@ -760,7 +759,7 @@ int bodex_qp_solve(bodex_qp_t* h, const bodex_batch* in, bodex_result* out) {
 
     bool chunked = false;
     int grid_g = 0;
-    rc = chunk_setup(h, a, W, mm, cone, chunked, grid_g);
+    rc = chunk_setup(h, a, W, mm, chunked, grid_g);
     if (rc) return rc;
 
     const size_t n_ints = desc_ints(G, S, lay);
@@ -1202,7 +1201,7 @@ int bodex_qp_descend(bodex_qp_t* h, const bodex_hand* hand, const bodex_batch* q
     const int grid_a = batched ? occupancy_grid(h, per_cu, S.n_tiles) : S.n_tiles;
     bool chunked = false;
     int grid_g = 0;
-    rc = chunk_setup(h, a, W, mm, cone, chunked, grid_g);
+    rc = chunk_setup(h, a, W, mm, chunked, grid_g);
     if (rc) return rc;
 
     // The whole descent for the descriptors at `desc`: loss weights, the
