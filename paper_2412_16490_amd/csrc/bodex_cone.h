@@ -523,11 +523,15 @@ BODEX_FI ConePolishOut cone_polish(const D& Dt, double t0, double gap, double gr
     double t = 1.0;
     {
         // -grad at weights 0 and 1 give -grad phi and -(grad Q + grad phi)
-        if (!isfinite(cone_merit<MM>(Dt, W.f, 0.0, &W.d, &qv))) {
-            out.status = 3;
-            return out;
+        // (one call site for both)
+#pragma unroll 1
+        for (int k = 0; k < 2; ++k) {
+            const double mv = cone_merit<MM>(Dt, W.f, double(k), k ? &W.r : &W.d, &qv);
+            if (k == 0 && !isfinite(mv)) {
+                out.status = 3;
+                return out;
+            }
         }
-        cone_merit<MM>(Dt, W.f, 1.0, &W.r, &qv);
         double gh = 0.0, gg = 0.0;
 #pragma unroll 1
         for (int c = 0; c < 3 * Dt.m; ++c) {
@@ -537,9 +541,13 @@ BODEX_FI ConePolishOut cone_polish(const D& Dt, double t0, double gap, double gr
         }
         if (gg > 0.0 && -gh > gg) t = fmin(-gh / gg, t0);
     }
-    double val = cone_merit<MM>(Dt, W.f, t, &W.d, &qv);
+    double val = 0.0;
+    // every pass starts from the merit and -grad at (f, t) (one call site):
+    // at the start, after an accepted line search and after raising t
 #pragma unroll 1
-    while (out.newton < max_newton) {
+    for (;;) {
+        val = cone_merit<MM>(Dt, W.f, t, &W.d, &qv);
+        if (!(out.newton < max_newton)) break;
         ++out.newton;
         // d = A^{-1} (-grad) (the normal-sum row's barrier term iu^2 s s^T is
         // part of A)
@@ -595,7 +603,6 @@ BODEX_FI ConePolishOut cone_polish(const D& Dt, double t0, double gap, double gr
             } else {
 #pragma unroll 1
                 for (int c = 0; c < 3 * Dt.m; ++c) W.f[c] = W.r[c];
-                val = cone_merit<MM>(Dt, W.f, t, &W.d, &qv);
                 ++out.grads;
                 continue;
             }
@@ -606,7 +613,6 @@ BODEX_FI ConePolishOut cone_polish(const D& Dt, double t0, double gap, double gr
             break;
         }
         t *= growth;
-        val = cone_merit<MM>(Dt, W.f, t, &W.d, &qv);
         ++out.grads;
     }
     out.t = t;

@@ -1082,18 +1082,23 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) co
             const bool finite_in = good && !(st & kStNonfinite);
             if (finite_in && a.polish) {
                 const float* zs = a.z + sw;
-                cone_start<MM>(D, [&](int r) { return double(zs[size_t(r) * W_]); }, kConePull, W);
-                ConePolishOut po = cone_polish<MM>(D, kConeT0, kConeGap, kConeGrowth, kConeLoose, a.polish_steps, W);
-                if (po.status != 0) {
-                    // once more from a point well inside (half way to the cone
-                    // axis), whose central path the barrier follows from a
-                    // small weight
-                    const int n1 = po.newton, e1 = po.evals, g1 = po.grads;
-                    cone_start<MM>(D, [&](int r) { return double(zs[size_t(r) * W_]); }, kConeRetryPull, W);
+                // a failed polish is taken once more from a point well inside
+                // (half way to the cone axis), whose central path the barrier
+                // follows from a small weight
+                ConePolishOut po;
+                int n1 = 0, e1 = 0, g1 = 0;
+#pragma unroll 1
+                for (int attempt = 0; attempt < 2; ++attempt) {
+                    cone_start<MM>(D, [&](int r) { return double(zs[size_t(r) * W_]); },
+                                   attempt ? kConeRetryPull : kConePull, W);
                     po = cone_polish<MM>(D, kConeT0, kConeGap, kConeGrowth, kConeLoose, a.polish_steps, W);
                     po.newton += n1;
                     po.evals += e1;
                     po.grads += g1;
+                    if (po.status == 0) break;
+                    n1 = po.newton;
+                    e1 = po.evals;
+                    g1 = po.grads;
                 }
                 if (a.pflops) a.pflops[w] = float(cone_polish_flops(si.m, po));
                 if (po.status == 0) {
