@@ -356,10 +356,12 @@ BODEX_FI double cone_merit(const D& Dt, const V& f, double t, const V* rhs, doub
 // A = 2 t (G^T G + eps I) + blockdiag(barrier Hessians) (+ iu^2 s s^T with
 // the normal-sum row, s the normal-component pattern, iu = 1 / (sum f_1 -
 // gamma)).  Dense: formed in registers with compile-time indices, scaled to
-// unit diagonal, Cholesky-factored; padded contacts get identity rows.
+// unit diagonal, Cholesky-factored; padded contacts get identity rows.  The
+// scale factors go to the lane's vector sc (free during the solve) and the
+// substitutions run in v, so that only the matrix occupies registers.
 // Returns false on a non-positive pivot.
 template <int MM, typename D, class V>
-BODEX_FI bool cone_newton_solve(const D& Dt, const V& f, double t, double iu, const V& v) {
+BODEX_FI bool cone_newton_solve(const D& Dt, const V& f, double t, double iu, const V& v, const V& sc) {
     constexpr int NV = 3 * MM, NK = NV * (NV + 1) / 2;
     const int m = Dt.m;
     // 2 t G^T G, one row of G at a time (few values live besides the matrix)
@@ -404,16 +406,19 @@ BODEX_FI bool cone_newton_solve(const D& Dt, const V& f, double t, double iu, co
 #pragma unroll
         for (int c = 0; c <= r; ++c)
             if (r / 3 >= m || c / 3 >= m) a[lo_idx(r, c)] = (r == c) ? 1.0 : 0.0;
-    double sc[NV], x[NV];
+    // the scale factors and the solution in the lane's vectors sc and v
 #pragma unroll
     for (int r = 0; r < NV; ++r) {
-        sc[r] = 1.0 / sqrt(a[lo_idx(r, r)]);
-        x[r] = (r < 3 * m) ? double(v[r]) * sc[r] : 0.0;
+        const double sr = 1.0 / sqrt(a[lo_idx(r, r)]);
+        sc[r] = sr;
+        v[r] = (r < 3 * m) ? double(v[r]) * sr : 0.0;
     }
 #pragma unroll
-    for (int r = 0; r < NV; ++r)
+    for (int r = 0; r < NV; ++r) {
+        const double sr = sc[r];
 #pragma unroll
-        for (int c = 0; c <= r; ++c) a[lo_idx(r, c)] *= sc[r] * sc[c];
+        for (int c = 0; c <= r; ++c) a[lo_idx(r, c)] *= sr * sc[c];
+    }
     // Cholesky (reciprocal pivots on the diagonal)
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
@@ -433,21 +438,21 @@ BODEX_FI bool cone_newton_solve(const D& Dt, const V& f, double t, double iu, co
     }
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-        double sv = x[i];
+        double sv = v[i];
 #pragma unroll
-        for (int l = 0; l < i; ++l) sv -= a[lo_idx(i, l)] * x[l];
-        x[i] = sv * a[lo_idx(i, i)];
+        for (int l = 0; l < i; ++l) sv -= a[lo_idx(i, l)] * v[l];
+        v[i] = sv * a[lo_idx(i, i)];
     }
 #pragma unroll
     for (int i = NV - 1; i >= 0; --i) {
-        double sv = x[i];
+        double sv = v[i];
 #pragma unroll
-        for (int l = i + 1; l < NV; ++l) sv -= a[lo_idx(l, i)] * x[l];
-        x[i] = sv * a[lo_idx(i, i)];
+        for (int l = i + 1; l < NV; ++l) sv -= a[lo_idx(l, i)] * v[l];
+        v[i] = sv * a[lo_idx(i, i)];
     }
 #pragma unroll
     for (int r = 0; r < NV; ++r)
-        if (r < 3 * m) v[r] = x[r] * sc[r];
+        if (r < 3 * m) v[r] = v[r] * sc[r];
     return true;
 }
 
@@ -560,7 +565,7 @@ BODEX_FI ConePolishOut cone_polish(const D& Dt, double t0, double gap, double gr
         }
 #pragma unroll 1
         for (int c = 0; c < 3 * Dt.m; ++c) W.ft[c] = W.d[c];  // keep -grad
-        if (!cone_newton_solve<MM>(Dt, W.f, t, iu, W.d)) {
+        if (!cone_newton_solve<MM>(Dt, W.f, t, iu, W.d, W.r)) {
             out.status = (nu / t <= 1e3 * gap) ? 0 : 3;
             break;
         }
