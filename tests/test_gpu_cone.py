@@ -191,6 +191,26 @@ def test_cone_backward_matches_oracle_gradient():
     assert ep2 <= 1e-3 and en2 <= 1e-3
 
 
+def test_cone_retry_after_a_failed_polish():
+    """polish_steps = 0: the barrier polish reaches its Newton-step cap before
+    the first step, so the retry from the point half way to the cone axis
+    runs as well and fails the same way.  Each QP keeps the ADMM point (forces
+    and objective equal to those of the same solve without the polish), is
+    marked rejected, and its polish work counts the start of both attempts:
+    two merit gradients each, 140 m + 20 FP64 flops apiece."""
+    b = wl.config(1, 16)
+    print("cone retry: ellipsoid m5 s16, 16 grasps, polish_steps 0", flush=True)
+    same = dict(tol_rel=1e-4, admm_tol=1e-4, max_iters=200)
+    gpu = _solve(b, polish_steps=0, **same)
+    off = _solve(b, flags=api.default_params().flags & ~api.F_POLISH, **same)
+    st = gpu["status"]
+    assert np.all(st & api.ST_POLISH_REJ) and not np.any(st & api.ST_POLISHED)
+    assert np.array_equal(gpu["forces"], off["forces"])
+    assert np.array_equal(gpu["qp_obj"], off["qp_obj"])
+    m = np.repeat(b.counts, np.diff(b.woff)).astype(np.float64)
+    assert np.allclose(gpu["polish_flops"], 4.0 * (140.0 * m + 20.0), rtol=1e-6, atol=0.0)
+
+
 def test_cone_rejects_bad_model_value():
     import ctypes
     p = api.default_params()
