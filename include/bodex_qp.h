@@ -119,7 +119,7 @@ typedef struct {
                           /* parallel polish (a group of lanes, one per       */
                           /* contact); 0 = every polish ends in the one-lane  */
                           /* kernel; -1 = chosen by the number of QPs (1 up   */
-                          /* to 40,960, 16 up to 98,304, else 20).  A QP is   */
+                          /* to 40,960, else 16).  A QP is                    */
                           /* also handed on at its next factorisation once at */
                           /* most 8 lanes of its wavefront still polish.      */
                           /* Used with BODEX_F_POLISH, the pyramid and        */

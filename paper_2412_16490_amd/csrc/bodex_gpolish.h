@@ -212,7 +212,7 @@ struct ShflTeam {
 // ---------------------------------------------------------------------------
 // One QP as one lane of its group sees it.
 // ---------------------------------------------------------------------------
-template <int MM>
+template <int MM, class LS = Sym6>
 struct GQP {
     // the lane's contact (zeros when sub >= m)
     double G[6][3];
@@ -225,7 +225,7 @@ struct GQP {
     double bt[6];
     int m, sub;
     double fmax, eps;
-    Sym6 L;
+    LS L;  // the factor (Sym6, or Sym6Shared: one copy per group)
     PendingRow p, mp;
     double up, mup;
     int phase, mode, chg, step0;
@@ -233,14 +233,14 @@ struct GQP {
     PolishOut out;
 };
 
-template <int MM>
-BODEX_FI bool gp_on(const GQP<MM>& Q, const PendingRow& p) {
+template <int MM, class LS>
+BODEX_FI bool gp_on(const GQP<MM, LS>& Q, const PendingRow& p) {
     return p.pk >= 0 && p.pk < 9 && p.pi == Q.sub;
 }
 
 // r6 = G v (minus beta t when with_t), v the lanes' 3-vectors.
-template <int MM, class T>
-BODEX_FI void gp_gtimes(const T& team, const GQP<MM>& Q, const double* v, bool with_t, double (&r6)[6]) {
+template <int MM, class T, class LS>
+BODEX_FI void gp_gtimes(const T& team, const GQP<MM, LS>& Q, const double* v, bool with_t, double (&r6)[6]) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) r6[k] = Q.G[k][0] * v[0] + Q.G[k][1] * v[1] + Q.G[k][2] * v[2];
     team.sum(r6);
@@ -251,8 +251,8 @@ BODEX_FI void gp_gtimes(const T& team, const GQP<MM>& Q, const double* v, bool w
 }
 
 // The lane's part of 2 (G^T r6 + eps v).
-template <int MM>
-BODEX_FI void gp_grad(const GQP<MM>& Q, const double (&r6)[6], const double* v, double* g) {
+template <int MM, class LS>
+BODEX_FI void gp_grad(const GQP<MM, LS>& Q, const double (&r6)[6], const double* v, double* g) {
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
         double s = Q.eps * v[t];
@@ -262,21 +262,21 @@ BODEX_FI void gp_grad(const GQP<MM>& Q, const double (&r6)[6], const double* v, 
     }
 }
 
-template <int MM>
-BODEX_FI void gp_rows(const GQP<MM>& Q, unsigned mk, ContactRows& R) {
+template <int MM, class LS>
+BODEX_FI void gp_rows(const GQP<MM, LS>& Q, unsigned mk, ContactRows& R) {
     contact_rows(mk, Q.muc, Q.fmax, R);
 }
 
-template <int MM>
-BODEX_FI void gp_refresh_proj(GQP<MM>& Q) {
+template <int MM, class LS>
+BODEX_FI void gp_refresh_proj(GQP<MM, LS>& Q) {
     ContactRows R;
     gp_rows(Q, Q.mk, R);
     contact_proj(R, Q.P);
 }
 
 // v <- H v (v: the lane's 3-vector).
-template <int MM, class T>
-BODEX_FI void gp_apply_h(const T& team, const GQP<MM>& Q, double* v) {
+template <int MM, class T, class LS>
+BODEX_FI void gp_apply_h(const T& team, const GQP<MM, LS>& Q, double* v) {
     double f[3] = {v[0], v[1], v[2]};
     proj_apply(Q.P, f);
     double gv[6];
@@ -299,8 +299,8 @@ BODEX_FI void gp_apply_h(const T& team, const GQP<MM>& Q, double* v) {
 }
 
 // eps I6 + G Pi G^T from every contact (into Q.L, to be factored).
-template <int MM, class T>
-BODEX_FI void gp_set_matrix(const T& team, GQP<MM>& Q) {
+template <int MM, class T, class LS>
+BODEX_FI void gp_set_matrix(const T& team, GQP<MM, LS>& Q) {
     double b[6][3];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -335,8 +335,8 @@ BODEX_FI void gp_set_matrix(const T& team, GQP<MM>& Q) {
 // the old factor and the rank-one term of the changed contact (see
 // matrix_row_change).  Returns false if the row has no component outside the
 // contact's other rows.
-template <int MM, class T>
-BODEX_FI bool gp_row_change(const T& team, GQP<MM>& Q, int ci, int kk, double sgn) {
+template <int MM, class T, class LS>
+BODEX_FI bool gp_row_change(const T& team, GQP<MM, LS>& Q, int ci, int kk, double sgn) {
     double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, s = 0.0;
     if (Q.sub == ci) {
         ContactRows R;
@@ -365,8 +365,8 @@ BODEX_FI bool gp_row_change(const T& team, GQP<MM>& Q, int ci, int kk, double sg
 
 // Multipliers of the lane's active rows at x with the partial multiplier up
 // on the pending row (stationarity, closed form per contact).
-template <int MM>
-BODEX_FI void gp_multipliers(const GQP<MM>& Q, const ContactRows& R, const double (&r6)[6], const PendingRow& p,
+template <int MM, class LS>
+BODEX_FI void gp_multipliers(const GQP<MM, LS>& Q, const ContactRows& R, const double (&r6)[6], const PendingRow& p,
                              double up, double* lam) {
     double h[3];
     gp_grad(Q, r6, Q.x, h);
@@ -376,8 +376,8 @@ BODEX_FI void gp_multipliers(const GQP<MM>& Q, const ContactRows& R, const doubl
     rows_coeffs(R, h, lam);
 }
 
-template <int MM, class T>
-BODEX_FI bool gpolish_accept(const T& team, GQP<MM>& Q) {
+template <int MM, class T, class LS>
+BODEX_FI bool gpolish_accept(const T& team, GQP<MM, LS>& Q) {
     double r6[6];
     gp_gtimes(team, Q, Q.x, true, r6);
     double gs = 0.0, stat = 0.0, lneg = 0.0, lmax = 0.0, viol = 0.0, vin = 0.0;
@@ -428,8 +428,8 @@ BODEX_FI bool gpolish_accept(const T& team, GQP<MM>& Q) {
 // One step of the polish (see polish_advance, whose order and decisions
 // this follows); returns true once the QP has reached its acceptance check
 // or failed.
-template <int MM, class T>
-BODEX_FI bool gpolish_advance(const T& team, GQP<MM>& Q, int max_steps) {
+template <int MM, class T, class LS>
+BODEX_FI bool gpolish_advance(const T& team, GQP<MM, LS>& Q, int max_steps) {
     PolishOut& out = Q.out;
     const double tol_add = 1e-12 * (1.0 + Q.fmax);
     const PendingRow none = {-1, -1, {0.0, 0.0, 0.0}, 0.0};
@@ -654,8 +654,8 @@ BODEX_FI bool gpolish_advance(const T& team, GQP<MM>& Q, int max_steps) {
 
 // See polish_finish: false when the QP is taken once more on fresh
 // factorisations.
-template <int MM, class T>
-BODEX_FI bool gpolish_finish(const T& team, GQP<MM>& Q) {
+template <int MM, class T, class LS>
+BODEX_FI bool gpolish_finish(const T& team, GQP<MM, LS>& Q) {
     const bool reached = Q.mode == kAccept;
     if (reached) gpolish_accept(team, Q);
     if (Q.out.status == kPolishViolated) {
@@ -695,8 +695,8 @@ BODEX_FI bool gpolish_finish(const T& team, GQP<MM>& Q) {
 
 // The lane's view of record k: its contact's G (FP64, from the FP32
 // inputs), mu_i cos(pi/8) of every contact, beta t, and the saved state.
-template <int MM, class T>
-BODEX_FI void gpolish_load(const T& team, GQP<MM>& Q, const SpillPtrs& sp, int k, int m, const double* p3,
+template <int MM, class T, class LS>
+BODEX_FI void gpolish_load(const T& team, GQP<MM, LS>& Q, const SpillPtrs& sp, int k, int m, const double* p3,
                            const double* n3, double mu_own, double kappa, const double* bt, double fmax, double eps) {
     Q.m = m;
     Q.live = Q.sub < m;
@@ -747,8 +747,8 @@ BODEX_FI void gpolish_load(const T& team, GQP<MM>& Q, const SpillPtrs& sp, int k
 
 // The finished polish back into record k: x, the active set and the counts
 // (the tail of the finalize kernel forms the outputs from them).
-template <int MM, class T>
-BODEX_FI void gpolish_store(const T& team, const GQP<MM>& Q, const SpillPtrs& sp, int k) {
+template <int MM, class T, class LS>
+BODEX_FI void gpolish_store(const T& team, const GQP<MM, LS>& Q, const SpillPtrs& sp, int k) {
     if (Q.live) {
 #pragma unroll
         for (int t = 0; t < 3; ++t) sp.dv(3 * Q.sub + t, k) = Q.x[t];

@@ -603,7 +603,18 @@ struct Sym6 {
     double a[21];
 };
 
-BODEX_FI bool chol6(Sym6& M) {
+// The same matrix in memory shared by the lanes that hold identical copies
+// (entry e at p[e * stride]); the chol6 routines take either form.
+struct Sym6Shared {
+    struct Entries {
+        double* p;
+        int stride;
+        BODEX_FI double& operator[](int e) const { return p[e * stride]; }
+    } a;
+};
+
+template <class S6>
+BODEX_FI bool chol6(S6& M) {
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
         double d = M.a[lo_idx(j, j)];
@@ -627,7 +638,8 @@ BODEX_FI bool chol6(Sym6& M) {
 }
 
 // Solve (L L^T) v = rhs in place; the diagonal of L holds reciprocals.
-BODEX_FI void chol6_solve(const Sym6& L, double* v) {
+template <class S6>
+BODEX_FI void chol6_solve(const S6& L, double* v) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         double s = v[i];
@@ -647,7 +659,8 @@ BODEX_FI void chol6_solve(const Sym6& L, double* v) {
 // M = L L^T in place (L packed lower with reciprocal diagonal): rows from
 // the last, each from its diagonal down, so that every entry of L is read
 // before it is overwritten.
-BODEX_FI void chol6_product(Sym6& L) {
+template <class S6>
+BODEX_FI void chol6_product(S6& L) {
     double d[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) d[k] = 1.0 / L.a[lo_idx(k, k)];

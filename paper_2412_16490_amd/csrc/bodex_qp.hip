@@ -322,11 +322,12 @@ constexpr int kDefaultAdmmWaves = 2;
 // to 8192 grasps x 16 wrenches (5 contacts): the contact-parallel polish
 // alone (chunk 1) is 2.8x faster than the one-lane polish at 256 grasps,
 // 1.9x at 1024 and 1.4x at 2048, where its latency wins; from 4096 grasps
-// the one-lane pass is needed for throughput and a budget of 16 (4096) or 20
-// (8192) factorisations leaves the contact-parallel kernel only the slowest
-// QPs (0.89x and 0.98x the one-lane time).
+// the one-lane pass is needed for throughput, and a budget of 16
+// factorisations (with the wavefront hand-off and the contact-parallel
+// kernel at two waves per SIMD) is the fastest measured at 4096, 8192 and
+// 16,384 grasps and level with 20 at 32,768.
 constexpr int kDefaultPolishChunk = -1;
-int auto_polish_chunk(int n_qps) { return n_qps <= 40960 ? 1 : (n_qps <= 98304 ? 16 : 20); }
+int auto_polish_chunk(int n_qps) { return n_qps <= 40960 ? 1 : 16; }
 // ADMM stopping rule with the polish on, per friction model (admm_tol 0).
 // The pyramid's active-set polish costs the same from a rough point: 1e-1.
 // The cone's barrier polish is faster from a closer one (headline batch:

@@ -73,15 +73,15 @@ def test_effective_params_follow_the_header_rules(L):
     # ADMM stops at 1e-1 and checks every max(check_every, 20) iterations;
     # the cone's stops at 1e-4 or min(max_iters, 200) iterations; without the
     # polish ADMM runs to tol_rel; the polish budget follows polish_chunk
-    # (-1: 1 up to 40,960 QPs, 16 up to 98,304, else 20) for the pyramid with
+    # (-1: 1 up to 40,960 QPs, else 16) for the pyramid with
     # gamma = 0, and is 0 otherwise
     p = api.default_params()
     assert p.check_every == 10 and p.admm_tol == 0.0 and p.friction_cone == api.CONE_PYRAMID8
     e = api.bodex_qp_effective_params(p, 131072)
     assert e["check_every"] == 20 and e["max_iters"] == 500 and abs(e["admm_tol"] - 0.1) < 1e-7
-    assert e["polish_chunk"] == 20
+    assert e["polish_chunk"] == 16
     assert [api.bodex_qp_effective_params(p, n)["polish_chunk"] for n in (1, 40960, 40961, 98304, 98305)] == \
-        [1, 1, 16, 16, 20]
+        [1, 1, 16, 16, 16]
     p.check_every = 30
     assert api.admm_check_period(p) == 30
     q = api.default_params(admm_tol=1e-3, polish_chunk=7)
