@@ -6,6 +6,7 @@
 // the same value in every thread).
 #include <cstring>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "../paper_2412_16490_amd/csrc/bodex_gpolish.h"
@@ -28,11 +29,13 @@ extern "C" {
 // Outputs x [s][15], status [s], handed [s] (1 if the group finished it),
 // counts [s][4] (factorisations, of which one-row changes, equality solves,
 // one-row steps).  force_break: the first ratio test (in whichever kernel
-// runs it) reports a breakdown.  Returns the number of QPs whose polish was
-// not accepted.
+// runs it) reports a breakdown.  shared_factor: the group keeps its 6x6
+// factor in the memory-backed form the GPU kernel uses (Sym6Shared; here
+// each thread has its own copy, since host threads do not run in lockstep).
+// Returns the number of QPs whose polish was not accepted.
 int host_chunked_polish(int m, const double* p, const double* n, const double* mu, const double* t, int s,
                         double kappa, double eps, const float* y0, int budget, double* x, int* status,
-                        int* handed, int* counts, int force_break) {
+                        int* handed, int* counts, int force_break, int shared_factor) {
     double G[6 * NV] = {};
     double muc[MM] = {};
     for (int i = 0; i < m; ++i) {
@@ -69,10 +72,15 @@ int host_chunked_polish(int m, const double* p, const double* n, const double* m
             polish_save<MM>(PS, W.x, m, sp, 0, j, 0);
             Shared sh(GS);
             std::vector<std::thread> th;
-            for (int l = 0; l < GS; ++l) {
-                th.emplace_back([&, l] {
+            auto lane = [&](int l, auto tag) {
+                using LS = decltype(tag);
                     HostTeam<GS> team{l, &sh};
-                    GQP<MM> Q;
+                    GQP<MM, LS> Q;
+                    double lbuf[21];
+                    if constexpr (std::is_same<LS, Sym6Shared>::value) {
+                        Q.L.a.p = lbuf;
+                        Q.L.a.stride = 1;
+                    }
                     Q.sub = l;
                     double p3[3] = {0.0, 0.0, 0.0}, n3[3] = {0.0, 0.0, 1.0}, mu1 = 0.5;
                     if (l < m) {
@@ -88,7 +96,12 @@ int host_chunked_polish(int m, const double* p, const double* n, const double* m
                         }
                     } while (!gpolish_finish<MM>(team, Q));
                     gpolish_store<MM>(team, Q, sp, 0);
-                });
+            };
+            for (int l = 0; l < GS; ++l) {
+                if (shared_factor)
+                    th.emplace_back([&, l] { lane(l, Sym6Shared{}); });
+                else
+                    th.emplace_back([&, l] { lane(l, Sym6{}); });
             }
             for (auto& h : th) h.join();
             for (int c = 0; c < NV; ++c) xb[c] = c < 3 * m ? sp.dv(c, 0) : 0.0;

@@ -30,7 +30,7 @@ def _d(a):
     return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _run(host, b, g, y0, budget, force_break=0):
+def _run(host, b, g, y0, budget, force_break=0, shared_factor=0):
     m = int(b.counts[g])
     s = min(int(b.woff[g + 1] - b.woff[g]), 6)
     p, pp = _d(b.points[g, :m])
@@ -46,7 +46,8 @@ def _run(host, b, g, y0, budget, force_break=0):
     bad = host.host_chunked_polish(m, pp, pn, pm, pt, s, ctypes.c_double(20.0), ctypes.c_double(1e-6),
                                    y.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), int(budget),
                                    x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), st.ctypes.data_as(I),
-                                   hd.ctypes.data_as(I), cnt.ctypes.data_as(I), int(force_break))
+                                   hd.ctypes.data_as(I), cnt.ctypes.data_as(I), int(force_break),
+                                   int(shared_factor))
     return bad, x[:, :3 * m], st, hd, cnt
 
 
@@ -94,3 +95,23 @@ def test_group_restart_from_the_empty_set_after_a_breakdown(host, budget):
         assert np.abs(x - fr).max() <= 1e-8, (g, np.abs(x - fr).max())
         hit += int(np.sum(c0[:, 3] > 0))
     assert hit > 0
+
+
+@pytest.mark.parametrize("budget", [0, 3])
+def test_group_factor_in_memory_matches_the_register_form(host, budget):
+    # the GPU kernel keeps each group's 6x6 factor once in LDS (Sym6Shared)
+    # instead of in every lane's registers: the chol6 routines through that
+    # accessor do the same arithmetic, so the results are bit-identical
+    b = wl.config(1, 10)
+    rng = np.random.default_rng(31)
+    handed = 0
+    for g in range(b.n_grasps):
+        s = int(b.woff[g + 1] - b.woff[g])
+        y0 = np.where(rng.random((s, 46)) < 0.3, rng.random((s, 46)), 0.0)
+        r0 = _run(host, b, g, y0, budget)
+        r1 = _run(host, b, g, y0, budget, shared_factor=1)
+        assert r0[0] == 0 and r1[0] == 0
+        for a0, a1 in zip(r0[1:], r1[1:]):
+            assert np.array_equal(a0, a1)
+        handed += int(r0[3].sum())
+    assert handed > 0

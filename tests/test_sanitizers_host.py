@@ -17,6 +17,7 @@ SELECTION = [
     "test_polish_host.py",
     "test_gpolish_host.py::test_chunked_polish_reaches_the_minimiser[1-1-12]",
     "test_gpolish_host.py::test_chunked_polish_reaches_the_minimiser[12-3-12]",
+    "test_gpolish_host.py::test_group_factor_in_memory_matches_the_register_form[3]",
     "test_cone_host.py::test_projection_matches_closest_point_of_triangle",
     "test_cone_host.py::test_polish_matches_oracle[kernel_schedule-2.0-cold]",
     "test_hand_host.py",
