@@ -210,12 +210,36 @@ struct ShflTeam {
 #endif
 
 // ---------------------------------------------------------------------------
-// One QP as one lane of its group sees it.
+// One QP as one lane of its group sees it.  The storage policy SP names
+// where the lane's block of G and the group's 6x6 factor live: RegStore
+// keeps both in the lane (registers); LdsStore keeps the block in memory
+// shared by the lanes (lane-interleaved) and the factor once per group
+// (every lane of the group computes it to the same bits in lockstep).
 // ---------------------------------------------------------------------------
-template <int MM, class LS = Sym6>
+// A lane's 6x3 block of G in memory: entry (k, t) at p[(3 k + t) * stride].
+struct GBlockShared {
+    double* p;
+    int stride;
+    struct Row {
+        double* p;
+        int stride;
+        BODEX_FI double& operator[](int t) const { return p[t * stride]; }
+    };
+    BODEX_FI Row operator[](int k) const { return Row{p + 3 * k * stride, stride}; }
+};
+struct RegStore {
+    using Block = double[6][3];
+    using Factor = Sym6;
+};
+struct LdsStore {
+    using Block = GBlockShared;
+    using Factor = Sym6Shared;
+};
+
+template <int MM, class LS = RegStore>
 struct GQP {
     // the lane's contact (zeros when sub >= m)
-    double G[6][3];
+    typename LS::Block G;
     double muc;
     bool live;
     unsigned mk;  // its active rows (9 bits)
@@ -225,7 +249,7 @@ struct GQP {
     double bt[6];
     int m, sub;
     double fmax, eps;
-    LS L;  // the factor (Sym6, or Sym6Shared: one copy per group)
+    typename LS::Factor L;  // the factor (one copy per lane or per group)
     PendingRow p, mp;
     double up, mup;
     int phase, mode, chg, step0;

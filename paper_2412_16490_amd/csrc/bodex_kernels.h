@@ -960,11 +960,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BODEX_F
 // Contact-parallel polish of the handed-on QPs (see bodex_gpolish.h): a
 // group of GS lanes per record, one lane per contact; all groups of the
 // grid stride over the records taken by the first pass.
-// Two resident waves per SIMD: with each group's factor kept once in LDS the
-// kernel spills 136 B per lane at that budget (one wave per SIMD: no spill,
-// 290 registers), and the handed-on QPs of the headline batch (about 1100
-// waves) then fit in one round; measured 3-4 % faster per solve at 8192 to
-// 32,768 grasps than one wave per SIMD.
+// Two resident waves per SIMD: with each group's factor and each lane's
+// block of G kept in LDS the kernel spills 16 B per lane at that budget, and
+// the handed-on QPs of the headline batch (about 1100 waves) then fit in one
+// round; measured 3-4 % faster per solve at 8192 to 32,768 grasps than one
+// wave per SIMD with both in registers.
 #ifndef BODEX_GPOLISH_WAVES
 #define BODEX_GPOLISH_WAVES 2
 #endif
@@ -975,8 +975,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BODEX_G
     const int count = min(*a.spill_count, a.spill.K);
     const ShflTeam<GS> team{sub};
     // one copy of each group's 6x6 factor: the group's lanes compute the same
-    // bits in lockstep, so they share it ([21][GPW], group-interleaved)
+    // bits in lockstep, so they share it ([21][GPW], group-interleaved); each
+    // lane's block of G ([18][64], lane-interleaved)
     __shared__ double sL[21 * GPW];
+    __shared__ double sGb[18 * kWave];
     for (int base = int(blockIdx.x) * GPW; base < count; base += int(gridDim.x) * GPW) {
         const int k = base + grp;
         if (k < count) {
@@ -995,9 +997,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BODEX_G
             double bt[6];
 #pragma unroll
             for (int r = 0; r < 6; ++r) bt[r] = double(a.beta) * double(a.wrench[size_t(w) * 6 + r]);
-            GQP<MM, Sym6Shared> Q;
+            GQP<MM, LdsStore> Q;
             Q.L.a.p = sL + grp;
             Q.L.a.stride = GPW;
+            Q.G.p = sGb + lane;
+            Q.G.stride = kWave;
             Q.sub = sub;
             gpolish_load<MM>(team, Q, a.spill, k, m, p3, n3, mu, double(a.kappa), bt, double(a.fmax),
                              double(a.eps));

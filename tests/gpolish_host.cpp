@@ -30,8 +30,9 @@ extern "C" {
 // counts [s][4] (factorisations, of which one-row changes, equality solves,
 // one-row steps).  force_break: the first ratio test (in whichever kernel
 // runs it) reports a breakdown.  shared_factor: the group keeps its 6x6
-// factor in the memory-backed form the GPU kernel uses (Sym6Shared; here
-// each thread has its own copy, since host threads do not run in lockstep).
+// factor and each lane its block of G in the memory-backed forms the GPU
+// kernel uses (LdsStore; here each thread has its own copy of the factor,
+// since host threads do not run in lockstep).
 // Returns the number of QPs whose polish was not accepted.
 int host_chunked_polish(int m, const double* p, const double* n, const double* mu, const double* t, int s,
                         double kappa, double eps, const float* y0, int budget, double* x, int* status,
@@ -76,10 +77,12 @@ int host_chunked_polish(int m, const double* p, const double* n, const double* m
                 using LS = decltype(tag);
                     HostTeam<GS> team{l, &sh};
                     GQP<MM, LS> Q;
-                    double lbuf[21];
-                    if constexpr (std::is_same<LS, Sym6Shared>::value) {
+                    double lbuf[21], gbuf[18];
+                    if constexpr (std::is_same<LS, LdsStore>::value) {
                         Q.L.a.p = lbuf;
                         Q.L.a.stride = 1;
+                        Q.G.p = gbuf;
+                        Q.G.stride = 1;
                     }
                     Q.sub = l;
                     double p3[3] = {0.0, 0.0, 0.0}, n3[3] = {0.0, 0.0, 1.0}, mu1 = 0.5;
@@ -99,9 +102,9 @@ int host_chunked_polish(int m, const double* p, const double* n, const double* m
             };
             for (int l = 0; l < GS; ++l) {
                 if (shared_factor)
-                    th.emplace_back([&, l] { lane(l, Sym6Shared{}); });
+                    th.emplace_back([&, l] { lane(l, LdsStore{}); });
                 else
-                    th.emplace_back([&, l] { lane(l, Sym6{}); });
+                    th.emplace_back([&, l] { lane(l, RegStore{}); });
             }
             for (auto& h : th) h.join();
             for (int c = 0; c < NV; ++c) xb[c] = c < 3 * m ? sp.dv(c, 0) : 0.0;
